@@ -1,0 +1,197 @@
+"""TEST INFRASTRUCTURE ONLY: the double-precision CPU oracle.
+
+A plain, slow reference of one time step of the hybrid lattice-Boltzmann /
+finite-difference scheme of Coelho, Araujo and Telo da Gama (arXiv:1907.13415),
+written in C (``lc_oracle.c``) and loaded here through ctypes.  Only the test
+suite, the smoke check and the CPU-baseline leg of the benchmark may import
+this package; the GPU library never does, and the two share no code.
+
+Array conventions (numpy, float64, C order):
+  f  : (q, nz, ny, nx)  populations in the oracle's velocity order;
+  q5 : (5, nz, ny, nx)  order tensor (xx, xy, xz, yy, yz), Qzz = -Qxx - Qyy;
+  params: (A0, gamma, K, Gamma, xi, tau).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lc_oracle.c")
+_LIB = os.path.join(_HERE, "liblc_oracle.so")
+
+D2Q9 = 0
+D3Q19 = 1
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no floating-point contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        lib.lco_lattice.argtypes = [ctypes.c_int, _ip, _dp]
+        lib.lco_lattice.restype = ctypes.c_int
+        lib.lco_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_long]
+        lib.lco_run.restype = ctypes.c_int
+        lib.lco_fields.argtypes = [ctypes.c_int] * 4 + [_dp] * 12
+        lib.lco_fields.restype = ctypes.c_int
+        lib.lco_rate.argtypes = [ctypes.c_int] * 3 + [_dp] * 6
+        lib.lco_rate.restype = ctypes.c_int
+        lib.lco_stress.argtypes = [ctypes.c_int] * 3 + [_dp] * 5
+        lib.lco_stress.restype = ctypes.c_int
+        lib.lco_feq.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
+        lib.lco_feq.restype = None
+        lib.lco_source.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        lib.lco_source.restype = None
+        lib.lco_observe.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_int, _dp]
+        lib.lco_observe.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _params(p):
+    a = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+    assert a.shape == (6,), "params = (A0, gamma, K, Gamma, xi, tau)"
+    return a
+
+
+def lattice(lat: int):
+    """Velocity table c (q, 3) and weights w (q,) of the oracle."""
+    c = np.zeros(19 * 3, dtype=np.int32)
+    w = np.zeros(19, dtype=np.float64)
+    q = _load().lco_lattice(lat, c.ctypes.data_as(_ip), w.ctypes.data_as(_dp))
+    if q < 0:
+        raise ValueError("unknown lattice")
+    return c[: 3 * q].reshape(q, 3).astype(np.int64), w[:q].copy()
+
+
+def _dims(q5):
+    assert q5.ndim == 4 and q5.shape[0] == 5
+    nz, ny, nx = q5.shape[1:]
+    return nx, ny, nz
+
+
+def run(lat, f, q5, params, nsteps):
+    """Advance (f, q5) by nsteps; returns new arrays."""
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    q5 = np.array(q5, dtype=np.float64, order="C", copy=True)
+    nx, ny, nz = _dims(q5)
+    p = _params(params)
+    rc = _load().lco_run(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(nsteps))
+    if rc != 0:
+        raise ValueError("lco_run failed: %d" % rc)
+    return f, q5
+
+
+def fields(lat, f, q5, params):
+    """Intermediates of one step at state (f, q5)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    q5 = np.ascontiguousarray(q5, dtype=np.float64)
+    nx, ny, nz = _dims(q5)
+    sh = (nz, ny, nx)
+    out = dict(rho=np.zeros(sh), u=np.zeros((3,) + sh), F=np.zeros((3,) + sh),
+               H=np.zeros((3, 3) + sh), tau=np.zeros((3, 3) + sh), G=np.zeros((3, 3) + sh),
+               R=np.zeros((5,) + sh), Rp=np.zeros((5,) + sh), S=np.zeros((3, 3) + sh))
+    p = _params(params)
+    rc = _load().lco_fields(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5),
+                            *[_ptr(out[k]) for k in ("rho", "u", "F", "H", "tau", "G", "R", "Rp", "S")])
+    if rc != 0:
+        raise ValueError("lco_fields failed: %d" % rc)
+    return out
+
+
+def rate(q5, u, params):
+    """Beris-Edwards rate R (5 comps), co-rotational S and H (3x3) for given u."""
+    q5 = np.ascontiguousarray(q5, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    nx, ny, nz = _dims(q5)
+    sh = (nz, ny, nx)
+    R = np.zeros((5,) + sh)
+    S = np.zeros((3, 3) + sh)
+    H = np.zeros((3, 3) + sh)
+    p = _params(params)
+    rc = _load().lco_rate(nx, ny, nz, _ptr(p), _ptr(q5), _ptr(u), _ptr(R), _ptr(S), _ptr(H))
+    if rc != 0:
+        raise ValueError("lco_rate failed")
+    return R, S, H
+
+
+def stress(q5, params):
+    """Stress tau (3x3), body force F (3) and molecular field H (3x3)."""
+    q5 = np.ascontiguousarray(q5, dtype=np.float64)
+    nx, ny, nz = _dims(q5)
+    sh = (nz, ny, nx)
+    tau = np.zeros((3, 3) + sh)
+    F = np.zeros((3,) + sh)
+    H = np.zeros((3, 3) + sh)
+    p = _params(params)
+    rc = _load().lco_stress(nx, ny, nz, _ptr(p), _ptr(q5), _ptr(tau), _ptr(F), _ptr(H))
+    if rc != 0:
+        raise ValueError("lco_stress failed")
+    return tau, F, H
+
+
+def feq(lat, rho, u):
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(3))
+    q = 9 if lat == D2Q9 else 19
+    out = np.zeros(q)
+    _load().lco_feq(lat, float(rho), _ptr(u), _ptr(out))
+    return out
+
+
+def source(lat, tau, u, F):
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(3))
+    F = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(3))
+    q = 9 if lat == D2Q9 else 19
+    out = np.zeros(q)
+    _load().lco_source(lat, float(tau), _ptr(u), _ptr(F), _ptr(out))
+    return out
+
+
+def observe(lat, f, q5, params, half_axis=0):
+    """mass, lattice momentum (3), max |u|, sum S, half-domain sum S."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    q5 = np.ascontiguousarray(q5, dtype=np.float64)
+    nx, ny, nz = _dims(q5)
+    out = np.zeros(7)
+    p = _params(params)
+    rc = _load().lco_observe(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(half_axis), _ptr(out))
+    if rc != 0:
+        raise ValueError("lco_observe failed")
+    return dict(mass=out[0], mom=out[1:4].copy(), umax=out[4], ssum=out[5], ssum_half=out[6])
+
+
+def rest_populations(lat, shape, rho=1.0, rel=None):
+    """f_i = w_i rho (1 + rel_i) with the oracle's own weights."""
+    _, w = lattice(lat)
+    f = np.empty((len(w),) + tuple(shape))
+    for i, wi in enumerate(w):
+        f[i] = wi * rho
+    if rel is not None:
+        f *= 1.0 + rel
+    return f

@@ -1,0 +1,572 @@
+/*
+ * lc_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, double-precision CPU reference for one time step of the
+ * hybrid lattice-Boltzmann / finite-difference scheme for nematic liquid
+ * crystals of Coelho, Araujo and Telo da Gama, "Lattice-Boltzmann simulation
+ * of free nematic-isotropic interfaces" (arXiv:1907.13415).  It exists so that
+ * the GPU library can be checked against something obviously correct.  Only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * load it; the GPU library never links, calls or includes it, and the two
+ * share no code, headers or tables.
+ *
+ * Every tensor is handled as a full 3x3 matrix with literal index loops, in
+ * the order the paper writes the equations.  No fusion, no blocking.
+ *
+ * Storage (shared only as an interface convention with the tests):
+ *   site index  s = x + nx*(y + ny*z),  periodic in every direction;
+ *   populations f[i*N + s], i over the lattice velocities (table below);
+ *   order tensor q5[c*N + s], c = (xx, xy, xz, yy, yz); Qzz = -Qxx - Qyy.
+ *   parameters p[6] = (A0, gamma, K, Gamma, xi, tau).
+ *
+ * Readings of the paper used here (where it is silent):
+ *   - The collision is BGK with the BGK forcing term printed in Sec. 1.2.1.
+ *   - The Laplacian is the compact (2d+1)-point second difference summed over
+ *     the axes; first derivatives are the central differences of Sec. 1.2.2.
+ *   - One step is Jacobi in time: F, rho and u come from the state at step n;
+ *     both Heun stages and the collision use that u and F.
+ *   - The predictor Q^P is carried as five components with Qzz = -Qxx-Qyy;
+ *     the velocity gradient is not recomputed for the corrector.
+ *   - F_alpha = d_beta Pi_{alpha beta} (second index), without the
+ *     hydrostatic P0 (Sec. 1.2.1).  On the two-dimensional D2Q9 lattice the
+ *     z component of F and u is dropped (it has no z velocities).
+ *   - A periodic axis of length one has zero central and second differences,
+ *     which is how a two-dimensional grid is handled.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define LCO_D2Q9 0
+#define LCO_D3Q19 1
+
+/* ---- velocity sets ------------------------------------------------------
+ * D2Q9: rest, four axis links, four diagonals.  D3Q19: rest, six axis links,
+ * twelve face diagonals.  Weights follow from the Gauss-Hermite quadrature
+ * with c_s^2 = 1/3 (Sec. 1.2.1 quotes c_s = 1/sqrt(3)). */
+static const int C2[9][3] = {
+    {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+static const double W2[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                             1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int C3[19][3] = {
+    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+    {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+    {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+static const double W3[19] = {
+    1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+static const double CS2 = 1.0 / 3.0; /* c_s^2, Sec. 1.2.1 */
+
+typedef struct {
+  int q;
+  const int (*c)[3];
+  const double *w;
+  int ndim_u; /* velocity components carried by the lattice (2 or 3) */
+} lattice_t;
+
+static int get_lattice(int lattice, lattice_t *L) {
+  if (lattice == LCO_D2Q9) {
+    L->q = 9; L->c = C2; L->w = W2; L->ndim_u = 2;
+    return 0;
+  }
+  if (lattice == LCO_D3Q19) {
+    L->q = 19; L->c = C3; L->w = W3; L->ndim_u = 3;
+    return 0;
+  }
+  return -1;
+}
+
+/* Velocity table export: c[i*3 + a], w[i].  Returns q, or -1. */
+int lco_lattice(int lattice, int *c, double *w) {
+  lattice_t L;
+  if (get_lattice(lattice, &L)) return -1;
+  for (int i = 0; i < L.q; i++) {
+    for (int a = 0; a < 3; a++) c[i * 3 + a] = L.c[i][a];
+    w[i] = L.w[i];
+  }
+  return L.q;
+}
+
+/* ---- grid helpers ------------------------------------------------------- */
+typedef struct {
+  int nx, ny, nz;
+  size_t N;
+} grid_t;
+
+static size_t wrap(long v, int n) {
+  long r = v % n;
+  if (r < 0) r += n;
+  return (size_t)r;
+}
+
+static size_t site(const grid_t *g, long x, long y, long z) {
+  return wrap(x, g->nx) + (size_t)g->nx * (wrap(y, g->ny) + (size_t)g->ny * wrap(z, g->nz));
+}
+
+static void coords(const grid_t *g, size_t s, long *x, long *y, long *z) {
+  *x = (long)(s % (size_t)g->nx);
+  *y = (long)((s / (size_t)g->nx) % (size_t)g->ny);
+  *z = (long)(s / ((size_t)g->nx * (size_t)g->ny));
+}
+
+/* Neighbour of site s shifted by +/-1 along axis a. */
+static size_t shift(const grid_t *g, size_t s, int a, int d) {
+  long x, y, z;
+  coords(g, s, &x, &y, &z);
+  if (a == 0) x += d;
+  if (a == 1) y += d;
+  if (a == 2) z += d;
+  return site(g, x, y, z);
+}
+
+/* Full symmetric traceless tensor from the five stored components
+ * (uniaxial definition and symmetry of Q, Sec. 1.1). */
+static void full_Q(const double *q5, size_t N, size_t s, double Q[3][3]) {
+  double xx = q5[0 * N + s], xy = q5[1 * N + s], xz = q5[2 * N + s];
+  double yy = q5[3 * N + s], yz = q5[4 * N + s];
+  Q[0][0] = xx; Q[0][1] = xy; Q[0][2] = xz;
+  Q[1][0] = xy; Q[1][1] = yy; Q[1][2] = yz;
+  Q[2][0] = xz; Q[2][1] = yz; Q[2][2] = -xx - yy;
+}
+
+/* Central first differences, Sec. 1.2.2:  dQ[g][a][b] = d_g Q_ab. */
+static void grad_Q(const grid_t *g, const double *q5, size_t s, double dQ[3][3][3]) {
+  for (int gg = 0; gg < 3; gg++) {
+    double Qp[3][3], Qm[3][3];
+    full_Q(q5, g->N, shift(g, s, gg, +1), Qp);
+    full_Q(q5, g->N, shift(g, s, gg, -1), Qm);
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) dQ[gg][a][b] = (Qp[a][b] - Qm[a][b]) / 2.0;
+  }
+}
+
+/* Compact second-order Laplacian: sum over axes of V(x+e) - 2V(x) + V(x-e). */
+static void lap_Q(const grid_t *g, const double *q5, size_t s, double L[3][3]) {
+  double Q0[3][3];
+  full_Q(q5, g->N, s, Q0);
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) L[a][b] = 0.0;
+  for (int gg = 0; gg < 3; gg++) {
+    double Qp[3][3], Qm[3][3];
+    full_Q(q5, g->N, shift(g, s, gg, +1), Qp);
+    full_Q(q5, g->N, shift(g, s, gg, -1), Qm);
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) L[a][b] += Qp[a][b] - 2.0 * Q0[a][b] + Qm[a][b];
+  }
+}
+
+/* Molecular field, Eq. (4):
+ * H = -A0(1-g/3) Q - A0 g (Tr(Q^2) I/3 - Q Q^T) - A0 g Q Tr(Q^2) + K lap Q. */
+static void molecular_field(const double Q[3][3], const double L[3][3],
+                            const double *p, double H[3][3]) {
+  const double A0 = p[0], gam = p[1], K = p[2];
+  double trQ2 = 0.0;
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) trQ2 += Q[a][b] * Q[a][b];
+  for (int a = 0; a < 3; a++) {
+    for (int b = 0; b < 3; b++) {
+      double QQ = 0.0; /* Q_{a g} Q_{b g} */
+      for (int gg = 0; gg < 3; gg++) QQ += Q[a][gg] * Q[b][gg];
+      double delta = (a == b) ? 1.0 : 0.0;
+      H[a][b] = -A0 * (1.0 - gam / 3.0) * Q[a][b]
+                - A0 * gam * (trQ2 * delta / 3.0 - QQ)
+                - A0 * gam * Q[a][b] * trQ2
+                + K * L[a][b];
+    }
+  }
+}
+
+/* Liquid-crystal stress, Eq. (6), without the hydrostatic -P0 (the body
+ * force of Sec. 1.2.1 removes it), with dF/d(d_b Q_gn) = K d_b Q_gn. */
+static void stress(const double Q[3][3], const double H[3][3], const double dQ[3][3][3],
+                   const double *p, double tau[3][3]) {
+  const double K = p[2], xi = p[4];
+  double Qp[3][3];
+  double QH = 0.0;
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      Qp[a][b] = Q[a][b] + ((a == b) ? 1.0 / 3.0 : 0.0);
+      QH += Q[a][b] * H[a][b];
+    }
+  for (int a = 0; a < 3; a++) {
+    for (int b = 0; b < 3; b++) {
+      double t = 2.0 * xi * Qp[a][b] * QH;
+      for (int gg = 0; gg < 3; gg++) t -= xi * H[a][gg] * Qp[gg][b];
+      for (int gg = 0; gg < 3; gg++) t -= xi * Qp[a][gg] * H[gg][b];
+      for (int gg = 0; gg < 3; gg++)
+        for (int n = 0; n < 3; n++) t -= dQ[a][gg][n] * K * dQ[b][gg][n];
+      for (int gg = 0; gg < 3; gg++) t += Q[a][gg] * H[gg][b] - H[a][gg] * Q[gg][b];
+      tau[a][b] = t;
+    }
+  }
+}
+
+/* Beris-Edwards rate, Eq. (1)-(2): R = Gamma H + S(W, D, Q) - (u . grad) Q,
+ * with G[a][b] = d_b u_a, D = (G + G^T)/2, W = (G - G^T)/2. */
+static void be_rate(const double Q[3][3], const double H[3][3], const double dQ[3][3][3],
+                    const double u[3], const double G[3][3], const double *p,
+                    double R[3][3], double Sout[3][3]) {
+  const double Gam = p[3], xi = p[4];
+  double D[3][3], W[3][3], Qp[3][3];
+  double QdU = 0.0; /* Q_{g e} d_g u_e */
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      D[a][b] = (G[a][b] + G[b][a]) / 2.0;
+      W[a][b] = (G[a][b] - G[b][a]) / 2.0;
+      Qp[a][b] = Q[a][b] + ((a == b) ? 1.0 / 3.0 : 0.0);
+    }
+  for (int gg = 0; gg < 3; gg++)
+    for (int e = 0; e < 3; e++) QdU += Q[gg][e] * G[e][gg];
+  for (int a = 0; a < 3; a++) {
+    for (int b = 0; b < 3; b++) {
+      double S = 0.0;
+      for (int gg = 0; gg < 3; gg++) S += (xi * D[a][gg] + W[a][gg]) * Qp[b][gg];
+      for (int gg = 0; gg < 3; gg++) S += Qp[a][gg] * (xi * D[gg][b] - W[gg][b]);
+      S -= 2.0 * xi * Qp[a][b] * QdU;
+      double adv = 0.0;
+      for (int gg = 0; gg < 3; gg++) adv += u[gg] * dQ[gg][a][b];
+      R[a][b] = Gam * H[a][b] + S - adv;
+      if (Sout) Sout[a][b] = S;
+    }
+  }
+}
+
+static void store5(const double T[3][3], double *out5, size_t N, size_t s) {
+  out5[0 * N + s] = T[0][0];
+  out5[1 * N + s] = T[0][1];
+  out5[2 * N + s] = T[0][2];
+  out5[3 * N + s] = T[1][1];
+  out5[4 * N + s] = T[1][2];
+}
+
+/* ---- equilibrium and forcing (Sec. 1.2.1) -------------------------------- */
+
+/* Second-order Hermite equilibrium, Eq. (8). */
+static double feq_i(const lattice_t *L, int i, double rho, const double u[3]) {
+  double cu = 0.0, uu = 0.0;
+  for (int a = 0; a < 3; a++) {
+    cu += L->c[i][a] * u[a];
+    uu += u[a] * u[a];
+  }
+  return rho * L->w[i] * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+}
+
+/* BGK forcing term S_i printed after Eq. (9). */
+static double source_i(const lattice_t *L, int i, double tau, const double u[3], const double F[3]) {
+  double cu = 0.0;
+  for (int a = 0; a < 3; a++) cu += L->c[i][a] * u[a];
+  double s = 0.0;
+  for (int a = 0; a < 3; a++) {
+    double v = L->c[i][a] / CS2 * (1.0 + cu / CS2) - u[a] / CS2;
+    s += v * F[a];
+  }
+  return L->w[i] * (1.0 - 1.0 / (2.0 * tau)) * s;
+}
+
+void lco_feq(int lattice, double rho, const double *u, double *out) {
+  lattice_t L;
+  if (get_lattice(lattice, &L)) return;
+  for (int i = 0; i < L.q; i++) out[i] = feq_i(&L, i, rho, u);
+}
+
+void lco_source(int lattice, double tau, const double *u, const double *F, double *out) {
+  lattice_t L;
+  if (get_lattice(lattice, &L)) return;
+  for (int i = 0; i < L.q; i++) out[i] = source_i(&L, i, tau, u, F);
+}
+
+/* ---- whole-grid stages --------------------------------------------------- */
+
+/* H (9 per site) and tau (9 per site) from Q. */
+static void stage_H_tau(const grid_t *g, const double *p, const double *q5,
+                        double *H9, double *tau9) {
+  const size_t N = g->N;
+#pragma omp parallel for schedule(static)
+  for (size_t s = 0; s < N; s++) {
+    double Q[3][3], L[3][3], H[3][3], dQ[3][3][3], tau[3][3];
+    full_Q(q5, N, s, Q);
+    lap_Q(g, q5, s, L);
+    molecular_field(Q, L, p, H);
+    grad_Q(g, q5, s, dQ);
+    stress(Q, H, dQ, p, tau);
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        if (H9) H9[(a * 3 + b) * N + s] = H[a][b];
+        tau9[(a * 3 + b) * N + s] = tau[a][b];
+      }
+  }
+}
+
+/* Body force F_a = d_b tau_ab (central differences), then rho and the
+ * force-corrected velocity of Eq. (9). */
+static void stage_force_moments(const grid_t *g, const lattice_t *L, const double *tau9,
+                                const double *f, double *F3, double *rho1, double *u3) {
+  const size_t N = g->N;
+#pragma omp parallel for schedule(static)
+  for (size_t s = 0; s < N; s++) {
+    double F[3];
+    for (int a = 0; a < 3; a++) {
+      F[a] = 0.0;
+      for (int b = 0; b < 3; b++) {
+        size_t sp = shift(g, s, b, +1), sm = shift(g, s, b, -1);
+        F[a] += (tau9[(a * 3 + b) * N + sp] - tau9[(a * 3 + b) * N + sm]) / 2.0;
+      }
+    }
+    if (L->ndim_u == 2) F[2] = 0.0; /* D2Q9 carries no z momentum */
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < L->q; i++) {
+      double fi = f[(size_t)i * N + s];
+      rho += fi;
+      for (int a = 0; a < 3; a++) j[a] += L->c[i][a] * fi;
+    }
+    rho1[s] = rho;
+    for (int a = 0; a < 3; a++) {
+      F3[a * N + s] = F[a];
+      u3[a * N + s] = (j[a] + F[a] / 2.0) / rho;
+    }
+  }
+}
+
+/* Velocity gradient G[a][b] = d_b u_a at site s. */
+static void velocity_gradient(const grid_t *g, const double *u3, size_t s, double G[3][3]) {
+  const size_t N = g->N;
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++) {
+      size_t sp = shift(g, s, b, +1), sm = shift(g, s, b, -1);
+      G[a][b] = (u3[a * N + sp] - u3[a * N + sm]) / 2.0;
+    }
+}
+
+/* Rate of the five stored components for the tensor field q5, with a given
+ * velocity field u3 (3 per site).  Optional full outputs S9, H9. */
+static void stage_rate(const grid_t *g, const double *p, const double *q5, const double *u3,
+                       double *R5, double *S9, double *H9) {
+  const size_t N = g->N;
+#pragma omp parallel for schedule(static)
+  for (size_t s = 0; s < N; s++) {
+    double Q[3][3], L[3][3], H[3][3], dQ[3][3][3], G[3][3], R[3][3], S[3][3], u[3];
+    full_Q(q5, N, s, Q);
+    lap_Q(g, q5, s, L);
+    molecular_field(Q, L, p, H);
+    grad_Q(g, q5, s, dQ);
+    velocity_gradient(g, u3, s, G);
+    for (int a = 0; a < 3; a++) u[a] = u3[a * N + s];
+    be_rate(Q, H, dQ, u, G, p, R, S);
+    store5(R, R5, N, s);
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) {
+        if (S9) S9[(a * 3 + b) * N + s] = S[a][b];
+        if (H9) H9[(a * 3 + b) * N + s] = H[a][b];
+      }
+  }
+}
+
+static int check_args(int lattice, int nx, int ny, int nz, const double *p, lattice_t *L, grid_t *g) {
+  if (get_lattice(lattice, L)) return -1;
+  if (nx < 1 || ny < 1 || nz < 1) return -1;
+  if (lattice == LCO_D2Q9 && nz != 1) return -1;
+  if (!(p[5] > 0.5)) return -1;
+  g->nx = nx; g->ny = ny; g->nz = nz;
+  g->N = (size_t)nx * (size_t)ny * (size_t)nz;
+  return 0;
+}
+
+/* Intermediate fields of one step at state (f, q5).  Any output may be NULL.
+ *   rho[N], u[3N] (force-corrected), F[3N], H[9N], tau[9N], G[9N] (d_b u_a),
+ *   R[5N] (rate at Q), Rp[5N] (rate at the predictor), S9[9N] (co-rotational
+ *   term at Q). */
+int lco_fields(int lattice, int nx, int ny, int nz, const double *p,
+               const double *f, const double *q5,
+               double *rho_o, double *u_o, double *F_o, double *H_o, double *tau_o,
+               double *G_o, double *R_o, double *Rp_o, double *S_o) {
+  lattice_t L;
+  grid_t g;
+  if (check_args(lattice, nx, ny, nz, p, &L, &g)) return -1;
+  const size_t N = g.N;
+  double *tau9 = malloc(9 * N * sizeof(double));
+  double *H9 = malloc(9 * N * sizeof(double));
+  double *F3 = malloc(3 * N * sizeof(double));
+  double *u3 = malloc(3 * N * sizeof(double));
+  double *rho = malloc(N * sizeof(double));
+  double *R5 = malloc(5 * N * sizeof(double));
+  double *qp = malloc(5 * N * sizeof(double));
+  double *Rp5 = malloc(5 * N * sizeof(double));
+  if (!tau9 || !H9 || !F3 || !u3 || !rho || !R5 || !qp || !Rp5) return -2;
+  stage_H_tau(&g, p, q5, H9, tau9);
+  stage_force_moments(&g, &L, tau9, f, F3, rho, u3);
+  stage_rate(&g, p, q5, u3, R5, S_o, NULL);
+  for (size_t k = 0; k < 5 * N; k++) qp[k] = q5[k] + R5[k];
+  stage_rate(&g, p, qp, u3, Rp5, NULL, NULL);
+  if (rho_o) memcpy(rho_o, rho, N * sizeof(double));
+  if (u_o) memcpy(u_o, u3, 3 * N * sizeof(double));
+  if (F_o) memcpy(F_o, F3, 3 * N * sizeof(double));
+  if (H_o) memcpy(H_o, H9, 9 * N * sizeof(double));
+  if (tau_o) memcpy(tau_o, tau9, 9 * N * sizeof(double));
+  if (R_o) memcpy(R_o, R5, 5 * N * sizeof(double));
+  if (Rp_o) memcpy(Rp_o, Rp5, 5 * N * sizeof(double));
+  if (G_o) {
+    for (size_t s = 0; s < N; s++) {
+      double G[3][3];
+      velocity_gradient(&g, u3, s, G);
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) G_o[(a * 3 + b) * N + s] = G[a][b];
+    }
+  }
+  free(tau9); free(H9); free(F3); free(u3); free(rho); free(R5); free(qp); free(Rp5);
+  return 0;
+}
+
+/* Rate R(Q) for a prescribed velocity field u3[3N] (used by consistency
+ * checks of the stress against the co-rotational term).  Outputs R5[5N],
+ * optional S9[9N] and H9[9N]. */
+int lco_rate(int nx, int ny, int nz, const double *p, const double *q5, const double *u3,
+             double *R5, double *S9, double *H9) {
+  grid_t g;
+  if (nx < 1 || ny < 1 || nz < 1) return -1;
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.N = (size_t)nx * (size_t)ny * (size_t)nz;
+  stage_rate(&g, p, q5, u3, R5, S9, H9);
+  return 0;
+}
+
+/* Stress tau[9N] and body force F[3N] of a tensor field (no lattice). */
+int lco_stress(int nx, int ny, int nz, const double *p, const double *q5,
+               double *tau_o, double *F_o, double *H_o) {
+  grid_t g;
+  if (nx < 1 || ny < 1 || nz < 1) return -1;
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.N = (size_t)nx * (size_t)ny * (size_t)nz;
+  const size_t N = g.N;
+  double *tau9 = tau_o ? tau_o : malloc(9 * N * sizeof(double));
+  stage_H_tau(&g, p, q5, H_o, tau9);
+  if (F_o) {
+    for (size_t s = 0; s < N; s++)
+      for (int a = 0; a < 3; a++) {
+        double F = 0.0;
+        for (int b = 0; b < 3; b++) {
+          size_t sp = shift(&g, s, b, +1), sm = shift(&g, s, b, -1);
+          F += (tau9[(a * 3 + b) * N + sp] - tau9[(a * 3 + b) * N + sm]) / 2.0;
+        }
+        F_o[a * N + s] = F;
+      }
+  }
+  if (!tau_o) free(tau9);
+  return 0;
+}
+
+/* ---- one full time step ---------------------------------------------------
+ * Molecular field and stress from Q(n); body force; rho and force-corrected
+ * u; Heun predictor-corrector for Q (Sec. 1.2.2 steps 1-5) with u, grad u
+ * frozen; BGK collision with forcing; periodic streaming. */
+static void one_step(const grid_t *g, const lattice_t *L, const double *p,
+                     const double *f, const double *q5, double *f_out, double *q5_out,
+                     double *tau9, double *F3, double *rho, double *u3,
+                     double *R5, double *qp, double *Rp5) {
+  const size_t N = g->N;
+  const double tau = p[5];
+  stage_H_tau(g, p, q5, NULL, tau9);
+  stage_force_moments(g, L, tau9, f, F3, rho, u3);
+  stage_rate(g, p, q5, u3, R5, NULL, NULL);          /* step 1 */
+  for (size_t k = 0; k < 5 * N; k++) qp[k] = q5[k] + R5[k]; /* step 2 */
+  stage_rate(g, p, qp, u3, Rp5, NULL, NULL);         /* step 3 */
+  for (size_t k = 0; k < 5 * N; k++)                 /* steps 4-5 */
+    q5_out[k] = q5[k] + (R5[k] + Rp5[k]) / 2.0;
+#pragma omp parallel for schedule(static)
+  for (size_t s = 0; s < N; s++) {
+    double u[3], F[3];
+    for (int a = 0; a < 3; a++) {
+      u[a] = u3[a * N + s];
+      F[a] = F3[a * N + s];
+    }
+    long x, y, z;
+    coords(g, s, &x, &y, &z);
+    for (int i = 0; i < L->q; i++) {
+      double fi = f[(size_t)i * N + s];
+      double post = fi - (fi - feq_i(L, i, rho[s], u)) / tau + source_i(L, i, tau, u, F);
+      size_t d = site(g, x + L->c[i][0], y + L->c[i][1], z + L->c[i][2]);
+      f_out[(size_t)i * N + d] = post;
+    }
+  }
+}
+
+/* Advance (f, q5) by nsteps in place.  Returns 0, -1 bad args, -2 no memory. */
+int lco_run(int lattice, int nx, int ny, int nz, const double *p, double *f, double *q5,
+            long nsteps) {
+  lattice_t L;
+  grid_t g;
+  if (check_args(lattice, nx, ny, nz, p, &L, &g) || nsteps < 0) return -1;
+  const size_t N = g.N;
+  double *f2 = malloc((size_t)L.q * N * sizeof(double));
+  double *q2 = malloc(5 * N * sizeof(double));
+  double *tau9 = malloc(9 * N * sizeof(double));
+  double *F3 = malloc(3 * N * sizeof(double));
+  double *rho = malloc(N * sizeof(double));
+  double *u3 = malloc(3 * N * sizeof(double));
+  double *R5 = malloc(5 * N * sizeof(double));
+  double *qp = malloc(5 * N * sizeof(double));
+  double *Rp5 = malloc(5 * N * sizeof(double));
+  if (!f2 || !q2 || !tau9 || !F3 || !rho || !u3 || !R5 || !qp || !Rp5) return -2;
+  for (long n = 0; n < nsteps; n++) {
+    one_step(&g, &L, p, f, q5, f2, q2, tau9, F3, rho, u3, R5, qp, Rp5);
+    memcpy(f, f2, (size_t)L.q * N * sizeof(double));
+    memcpy(q5, q2, 5 * N * sizeof(double));
+  }
+  free(f2); free(q2); free(tau9); free(F3); free(rho); free(u3); free(R5); free(qp); free(Rp5);
+  return 0;
+}
+
+/* ---- observables ----------------------------------------------------------
+ * out[0] mass = sum f; out[1..3] lattice momentum sum c f; out[4] max |u|
+ * (force-corrected); out[5] sum of S = sqrt(1.5 Q:Q) over the grid;
+ * out[6] sum of S over the half domain c <= coordinate <= c + n/2 along
+ * half_axis (end planes weighted 1/2, c = n/2), the trapezoid integral that
+ * locates the right-hand interface of a centred slab. */
+int lco_observe(int lattice, int nx, int ny, int nz, const double *p,
+                const double *f, const double *q5, int half_axis, double *out) {
+  lattice_t L;
+  grid_t g;
+  if (check_args(lattice, nx, ny, nz, p, &L, &g) || half_axis < 0 || half_axis > 2) return -1;
+  const size_t N = g.N;
+  double *u3 = malloc(3 * N * sizeof(double));
+  if (!u3) return -2;
+  if (lco_fields(lattice, nx, ny, nz, p, f, q5, NULL, u3, NULL, NULL, NULL, NULL, NULL, NULL, NULL))
+    return -1;
+  double mass = 0.0, mom[3] = {0, 0, 0}, umax = 0.0, ssum = 0.0, shalf = 0.0;
+  int n_ax = half_axis == 0 ? nx : (half_axis == 1 ? ny : nz);
+  long c0 = n_ax / 2, c1 = n_ax / 2 + n_ax / 2;
+  for (size_t s = 0; s < N; s++) {
+    for (int i = 0; i < L.q; i++) {
+      double fi = f[(size_t)i * N + s];
+      mass += fi;
+      for (int a = 0; a < 3; a++) mom[a] += L.c[i][a] * fi;
+    }
+    double uu = 0.0;
+    for (int a = 0; a < 3; a++) uu += u3[a * N + s] * u3[a * N + s];
+    if (sqrt(uu) > umax) umax = sqrt(uu);
+    double Q[3][3], qq = 0.0;
+    full_Q(q5, N, s, Q);
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) qq += Q[a][b] * Q[a][b];
+    double S = sqrt(1.5 * qq);
+    ssum += S;
+    long x, y, z;
+    coords(&g, s, &x, &y, &z);
+    long k = half_axis == 0 ? x : (half_axis == 1 ? y : z);
+    if (k == c0 || k == (c1 % n_ax)) shalf += 0.5 * S;
+    else if (k > c0 && k < c1) shalf += S;
+  }
+  out[0] = mass;
+  out[1] = mom[0]; out[2] = mom[1]; out[3] = mom[2];
+  out[4] = umax;
+  out[5] = ssum;
+  out[6] = shalf;
+  free(u3);
+  return 0;
+}
