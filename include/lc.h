@@ -1,0 +1,195 @@
+/*
+ * lc.h -- C ABI of the MI355X hybrid lattice-Boltzmann / finite-difference
+ * library for nematic liquid crystals.
+ *
+ * The method is that of Coelho, Araujo and Telo da Gama, "Lattice-Boltzmann
+ * simulation of free nematic-isotropic interfaces" (arXiv:1907.13415):
+ * the Beris-Edwards equation for the Landau-de Gennes order tensor Q
+ * (Sec. 1.1, Eqs. 1-4) integrated by a predictor-corrector finite-difference
+ * scheme (Sec. 1.2.2), coupled through the stress of Eq. (6) and its
+ * divergence to a forced lattice-Boltzmann Navier-Stokes solver (Sec. 1.2.1,
+ * Eqs. 7-9), on one grid with one time step (dx = dt = 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grids are periodic in every direction.  The site index is
+ *    s = x + nx*(y + ny*z), x fastest.  Two-dimensional grids use D2Q9 and
+ *    nz = 1; D3Q19 accepts any nz >= 1.
+ *  - Fields are structure-of-arrays, component-major: populations
+ *    f[i*N + s] (i over the lattice velocities, see lc_lattice_info), order
+ *    tensor Q[c*N + s] with c = (xx, xy, xz, yy, yz) and Qzz = -Qxx - Qyy.
+ *  - Velocity order.  D2Q9: 0 (0,0); 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1);
+ *    5 (1,1); 6 (-1,1); 7 (-1,-1); 8 (1,-1).  D3Q19: 0 rest; 1..6 = +x, -x,
+ *    +y, -y, +z, -z; 7..18 = (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1)
+ *    (-1,0,-1) (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1).
+ *  - Storage precision.  LC_FP64 stores f and Q as double.  LC_FP32_DEV
+ *    stores the deviation f_i - w_i*rho0 (rho0 = 1) and Q as float and does
+ *    all per-site arithmetic in float; reductions accumulate in double.
+ *    Every load/export entry point speaks double "logical" values (full f)
+ *    whatever the storage precision.
+ *  - Memory ownership.  The caller allocates and owns every device buffer
+ *    (for example as torch tensors); the library never allocates device
+ *    memory.  It keeps only a small host-side context and, for the batched
+ *    form, a captured HIP graph.  All work is enqueued on the HIP stream
+ *    given at init; only calls documented as synchronising wait for it.
+ *  - Errors.  Every call returns an lc_status; on failure lc_last_error()
+ *    gives a message (thread-local).  Asynchronous device errors surface at
+ *    the next synchronising call.  No C++ exception crosses this ABI.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lc_status;
+#define LC_OK 0
+#define LC_EINVAL (-1)       /* bad argument: sizes, parameters, pointers */
+#define LC_ENOMEM (-2)       /* buffer too small / host allocation failed */
+#define LC_EDEVICE (-3)      /* HIP runtime error (message has the details) */
+#define LC_ENONFINITE (-4)   /* NaN or Inf found in the state by lc_observe */
+#define LC_ESTATE (-5)       /* call out of order (e.g. step before load) */
+#define LC_EUNSUPPORTED (-6) /* valid request this build does not provide */
+
+#define LC_D2Q9 0
+#define LC_D3Q19 1
+
+#define LC_FP64 0
+#define LC_FP32_DEV 1
+
+/* Kernel variants for lc_set_variant. */
+#define LC_VARIANT_AUTO 0
+#define LC_VARIANT_STAGED 1 /* one kernel per stage, intermediates in scratch */
+#define LC_VARIANT_SPLIT 2  /* two sweeps: LB update + velocity, then Q update */
+#define LC_VARIANT_FUSED 3  /* single sweep with LDS halo tiles */
+
+typedef struct {
+  int32_t lattice;   /* LC_D2Q9 or LC_D3Q19 */
+  int32_t precision; /* LC_FP64 or LC_FP32_DEV */
+  int32_t nx, ny, nz;
+} lc_grid;
+
+/* Model parameters in lattice units (Sec. 2 lists the paper's set).
+ *   A0, gamma : bulk Landau-de Gennes coefficients of Eq. (3);
+ *   K         : one-constant elasticity of Eq. (3);
+ *   Gamma     : rotational diffusion constant of Eq. (1);
+ *   xi        : flow-alignment parameter of Eq. (2);
+ *   eta, tau  : viscosity of Eq. (5) and the BGK relaxation time; the
+ *               lattice-Boltzmann viscosity is eta = rho0 (tau - 1/2)/3 with
+ *               rho0 = 1, so eta must match tau to 1e-12 (relative).
+ * Requirements: all finite, tau > 1/2, K >= 0, Gamma > 0, A0 > 0. */
+typedef struct {
+  double A0, gamma, K, Gamma, xi, eta, tau;
+} lc_params;
+
+/* Caller-owned device buffers.  f[0], f[1]: q*N values each; Q[0], Q[1]:
+ * 5*N values each (element size 8 for LC_FP64, 4 for LC_FP32_DEV);
+ * scratch: lc_scratch_bytes() bytes.  All 256-byte aligned, disjoint, and
+ * valid for the lifetime of the context. */
+typedef struct {
+  void *f[2];
+  void *Q[2];
+  void *scratch;
+} lc_buffers;
+
+/* Observables (all accumulated in double).
+ *   mass      : sum of f over sites and velocities;
+ *   mom[3]    : lattice momentum sum c_i f_i (conserved by the scheme);
+ *   umax      : max over sites of |u|, u the force-corrected velocity of
+ *               Eq. (9), which is the one Sec. 1.2.2 feeds to Eq. (1);
+ *   ssum      : sum over sites of S = sqrt(1.5 Q:Q) (exact for uniaxial Q);
+ *   ssum_half : sum of S over c <= k <= c + n/2 along half_axis (end planes
+ *               weighted 1/2; c = n/2), which locates the right-hand
+ *               interface of a slab centred at n/2 (Sec. 2.1);
+ *   step      : steps taken since the last load;
+ *   nonfinite : 1 if any NaN or Inf was found in f or Q. */
+typedef struct {
+  double mass;
+  double mom[3];
+  double umax;
+  double ssum;
+  double ssum_half;
+  int64_t step;
+  int32_t nonfinite;
+  int32_t half_axis;
+} lc_observables;
+
+#define LC_OBS_MASS 1u
+#define LC_OBS_MOM 2u
+#define LC_OBS_UMAX 4u
+#define LC_OBS_S 8u
+#define LC_OBS_ALL 15u
+
+/* Fields for lc_export (double, component-major, N sites each). */
+#define LC_FIELD_F 0     /* q components: populations f_i */
+#define LC_FIELD_Q 1     /* 5 components (xx, xy, xz, yy, yz) */
+#define LC_FIELD_RHO 2   /* 1 component: density sum f_i */
+#define LC_FIELD_U 3     /* 3 components: force-corrected velocity, Eq. (9) */
+#define LC_FIELD_FORCE 4 /* 3 components: F_a = d_b Pi_ab + d_a P0 (Sec. 1.2.1) */
+#define LC_FIELD_S 5     /* 1 component: sqrt(1.5 Q:Q) */
+
+typedef struct lc_ctx lc_ctx;
+typedef struct lc_batch lc_batch;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lc_last_error(void);
+
+/* Velocity set of a lattice: *q, c[i*3 + a] (q*3 ints) and w[i] (q doubles).
+ * c and w may be NULL to query q only. */
+lc_status lc_lattice_info(int32_t lattice, int32_t *q, int32_t *c, double *w);
+
+/* Bytes of one f buffer, one Q buffer and the scratch buffer for a grid
+ * (any output pointer may be NULL). */
+lc_status lc_buffer_bytes(const lc_grid *grid, size_t *f_bytes, size_t *q_bytes,
+                          size_t *scratch_bytes);
+
+/* Create a context over caller-owned buffers.  `stream` is a hipStream_t
+ * (NULL = default stream).  Validates the grid, the parameters and the
+ * buffers (LC_EINVAL).  The state is undefined until lc_load_state. */
+lc_status lc_init(const lc_grid *grid, const lc_params *params, const lc_buffers *bufs,
+                  void *stream, lc_ctx **out);
+
+/* Replace the parameters (same validation as lc_init); for sweeps. */
+lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
+
+/* Choose the kernel variant (LC_VARIANT_*); AUTO picks the fastest the
+ * build provides for this grid.  LC_EUNSUPPORTED if not available. */
+lc_status lc_set_variant(lc_ctx *ctx, int32_t variant);
+
+/* Load the state from device arrays of double logical values: f_dev (q*N)
+ * and Q_dev (5*N).  f_dev == NULL loads the fluid at rest with rho = 1,
+ * f_i = w_i (the initial condition of Sec. 2).  Resets the step counter.
+ * Asynchronous on the context stream. */
+lc_status lc_load_state(lc_ctx *ctx, const double *f_dev, const double *Q_dev);
+
+/* Enqueue n >= 0 time steps (asynchronous). */
+lc_status lc_step(lc_ctx *ctx, int64_t n);
+
+/* Reduce the current state to observables (mask of LC_OBS_*; fields not
+ * requested are 0) with half-domain axis half_axis (0, 1, 2).  Synchronises
+ * the stream.  Returns LC_ENONFINITE (with *out filled) if the state holds a
+ * NaN or Inf. */
+lc_status lc_observe(lc_ctx *ctx, uint32_t mask, int32_t half_axis, lc_observables *out);
+
+/* Write a field of the current state as double to dst_dev (device memory,
+ * size given by the field, N = nx*ny*nz).  Asynchronous. */
+lc_status lc_export(lc_ctx *ctx, int32_t field, double *dst_dev);
+
+/* Wait for the context stream and report any pending device error. */
+lc_status lc_sync(lc_ctx *ctx);
+
+/* Steps taken since the last load. */
+int64_t lc_step_count(const lc_ctx *ctx);
+
+/* Destroy the context (device buffers stay with the caller). */
+lc_status lc_free(lc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LC_H */

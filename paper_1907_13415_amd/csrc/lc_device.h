@@ -1,0 +1,254 @@
+// lc_device.h -- per-site device arithmetic of the hybrid LB / FD step.
+//
+// Everything here is inlined into the kernels.  Symmetric traceless tensors
+// are carried as five values (xx, xy, xz, yy, yz), zz = -xx - yy, and the
+// tensor algebra of Eqs. (2), (4) and (6) is written out using that symmetry
+// rather than as 3x3 loops.  T is the arithmetic type (double for LC_FP64,
+// float for LC_FP32_DEV).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lc {
+
+// ---------------------------------------------------------------------------
+// Velocity sets.  c_s^2 = 1/3 (Sec. 1.2.1).  The order is part of the ABI.
+template <int LAT>
+struct Lattice;
+
+template <>
+struct Lattice<0> {  // D2Q9
+  static constexpr int q = 9;
+  static constexpr int dim = 2;
+  __host__ __device__ static constexpr int cx(int i) {
+    return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+template <>
+struct Lattice<1> {  // D3Q19
+  static constexpr int q = 19;
+  static constexpr int dim = 3;
+  // rest; +-x, +-y, +-z; xy edges; xz edges; yz edges
+  __host__ __device__ static constexpr int cx(int i) {
+    return i == 1 || i == 7 || i == 9 || i == 11 || i == 13
+               ? 1
+               : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    return i == 3 || i == 7 || i == 10 || i == 15 || i == 17
+               ? 1
+               : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int cz(int i) {
+    return i == 5 || i == 11 || i == 14 || i == 15 || i == 18
+               ? 1
+               : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Per-launch constants derived from lc_params (in the arithmetic type).
+template <typename T>
+struct Coef {
+  T lin;     // -A0 (1 - gamma/3): coefficient of Q in H
+  T quad;    // A0 gamma: coefficient of Q.Q (and -1/3 of its trace) in H
+  T K;       // elastic constant
+  T Gam;     // rotational diffusion
+  T xi;      // flow alignment
+  T xi_p;    // (xi + 1)/2
+  T xi_m;    // (xi - 1)/2
+  T omega;   // 1/tau
+  T src;     // 1 - 1/(2 tau)
+};
+
+template <typename T>
+struct Sym {
+  T xx, xy, xz, yy, yz;
+  __device__ __forceinline__ T zz() const { return -xx - yy; }
+};
+
+template <typename T>
+__device__ __forceinline__ Sym<T> sym_zero() {
+  return Sym<T>{T(0), T(0), T(0), T(0), T(0)};
+}
+
+// Full contraction A:B of two symmetric traceless tensors.
+template <typename T>
+__device__ __forceinline__ T ddot(const Sym<T>& a, const Sym<T>& b) {
+  return a.xx * b.xx + a.yy * b.yy + (a.xx + a.yy) * (b.xx + b.yy) +
+         T(2) * (a.xy * b.xy + a.xz * b.xz + a.yz * b.yz);
+}
+
+// Molecular field, Eq. (4), from Q and its Laplacian L:
+//   H = lin Q + quad (Q.Q - Tr(Q^2) I/3) - quad Tr(Q^2) Q + K L.
+template <typename T>
+__device__ __forceinline__ Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>& L,
+                                                  const Coef<T>& c) {
+  const T zz = Q.zz();
+  const T sxx = Q.xx * Q.xx + Q.xy * Q.xy + Q.xz * Q.xz;
+  const T syy = Q.xy * Q.xy + Q.yy * Q.yy + Q.yz * Q.yz;
+  const T szz = Q.xz * Q.xz + Q.yz * Q.yz + zz * zz;
+  const T sxy = Q.xx * Q.xy + Q.xy * Q.yy + Q.xz * Q.yz;
+  const T sxz = Q.xx * Q.xz + Q.xy * Q.yz + Q.xz * zz;
+  const T syz = Q.xy * Q.xz + Q.yy * Q.yz + Q.yz * zz;
+  const T tr2 = sxx + syy + szz;
+  const T a = c.lin - c.quad * tr2;
+  const T third = c.quad * tr2 * T(1.0 / 3.0);
+  Sym<T> H;
+  H.xx = a * Q.xx + c.quad * sxx - third + c.K * L.xx;
+  H.yy = a * Q.yy + c.quad * syy - third + c.K * L.yy;
+  H.xy = a * Q.xy + c.quad * sxy + c.K * L.xy;
+  H.xz = a * Q.xz + c.quad * sxz + c.K * L.xz;
+  H.yz = a * Q.yz + c.quad * syz + c.K * L.yz;
+  return H;
+}
+
+// Stress of Eq. (6) without the hydrostatic part, as a general 3x3 tensor:
+//   tau = 2 xi (Q + I/3)(Q:H) - xi [H (Q+I/3) + (Q+I/3) H]
+//         - K d_a Q : d_b Q + Q H - H Q.
+// With M = H Q this is 2 xi Qp q_h - (2xi/3) H - K E - (xi+1) M - (xi-1) M^T.
+// dQ[g] = d_g Q (g = x, y, z).
+template <typename T>
+__device__ __forceinline__ void stress(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
+                                       const Coef<T>& c, T (&tau)[3][3]) {
+  const T Qm[3][3] = {{Q.xx, Q.xy, Q.xz}, {Q.xy, Q.yy, Q.yz}, {Q.xz, Q.yz, Q.zz()}};
+  const T Hm[3][3] = {{H.xx, H.xy, H.xz}, {H.xy, H.yy, H.yz}, {H.xz, H.yz, H.zz()}};
+  const T qh = ddot(Q, H);
+  T M[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+      M[a][b] = Hm[a][0] * Qm[0][b] + Hm[a][1] * Qm[1][b] + Hm[a][2] * Qm[2][b];
+  const T two_xi_qh = T(2) * c.xi * qh;
+  const T xi23 = c.xi * T(2.0 / 3.0);
+  const T ap = c.xi + T(1), am = c.xi - T(1);
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+      const T qp = Qm[a][b] + (a == b ? T(1.0 / 3.0) : T(0));
+      const T E = ddot(dQ[a], dQ[b]);
+      tau[a][b] = two_xi_qh * qp - xi23 * Hm[a][b] - c.K * E - ap * M[a][b] - am * M[b][a];
+    }
+  }
+}
+
+// Beris-Edwards rate, Eqs. (1)-(2), on the stored components:
+//   R = Gamma H + S - (u.grad) Q,
+//   S = A + A^T - 2 xi (Q + I/3)(Q:G),  A = [xi D + W](Q + I/3),
+// with G[a][b] = d_b u_a, so xi D + W = (xi+1)/2 G + (xi-1)/2 G^T.
+template <typename T>
+__device__ __forceinline__ Sym<T> be_rate(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
+                                          const T (&u)[3], const T (&G)[3][3], const Coef<T>& c) {
+  const T Qp[3][3] = {{Q.xx + T(1.0 / 3.0), Q.xy, Q.xz},
+                      {Q.xy, Q.yy + T(1.0 / 3.0), Q.yz},
+                      {Q.xz, Q.yz, Q.zz() + T(1.0 / 3.0)}};
+  T B[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = 0; b < 3; b++) B[a][b] = c.xi_p * G[a][b] + c.xi_m * G[b][a];
+  // A = B Qp; only the entries needed for the five stored components of S.
+  auto A = [&](int a, int b) { return B[a][0] * Qp[0][b] + B[a][1] * Qp[1][b] + B[a][2] * Qp[2][b]; };
+  const T qg = Q.xx * G[0][0] + Q.yy * G[1][1] + Q.zz() * G[2][2] + Q.xy * (G[0][1] + G[1][0]) +
+               Q.xz * (G[0][2] + G[2][0]) + Q.yz * (G[1][2] + G[2][1]);
+  const T k = T(2) * c.xi * qg;
+  Sym<T> R;
+  R.xx = c.Gam * H.xx + T(2) * A(0, 0) - k * Qp[0][0] -
+         (u[0] * dQ[0].xx + u[1] * dQ[1].xx + u[2] * dQ[2].xx);
+  R.yy = c.Gam * H.yy + T(2) * A(1, 1) - k * Qp[1][1] -
+         (u[0] * dQ[0].yy + u[1] * dQ[1].yy + u[2] * dQ[2].yy);
+  R.xy = c.Gam * H.xy + A(0, 1) + A(1, 0) - k * Qp[0][1] -
+         (u[0] * dQ[0].xy + u[1] * dQ[1].xy + u[2] * dQ[2].xy);
+  R.xz = c.Gam * H.xz + A(0, 2) + A(2, 0) - k * Qp[0][2] -
+         (u[0] * dQ[0].xz + u[1] * dQ[1].xz + u[2] * dQ[2].xz);
+  R.yz = c.Gam * H.yz + A(1, 2) + A(2, 1) - k * Qp[1][2] -
+         (u[0] * dQ[0].yz + u[1] * dQ[1].yz + u[2] * dQ[2].yz);
+  return R;
+}
+
+// ---------------------------------------------------------------------------
+// Periodic neighbour offsets of a site.
+struct Nbr {
+  int64_t xp, xm, yp, ym, zp, zm;  // index offsets (signed) to the +/- neighbours
+};
+
+__device__ __forceinline__ Nbr neighbours(int x, int y, int z, int nx, int ny, int nz) {
+  const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+  Nbr n;
+  n.xp = (x + 1 == nx) ? -(int64_t)(nx - 1) * sx : sx;
+  n.xm = (x == 0) ? (int64_t)(nx - 1) * sx : -sx;
+  n.yp = (y + 1 == ny) ? -(int64_t)(ny - 1) * sy : sy;
+  n.ym = (y == 0) ? (int64_t)(ny - 1) * sy : -sy;
+  n.zp = (z + 1 == nz) ? -(int64_t)(nz - 1) * sz : sz;
+  n.zm = (z == 0) ? (int64_t)(nz - 1) * sz : -sz;
+  return n;
+}
+
+template <typename S>
+__device__ __forceinline__ Sym<S> load_sym(const S* __restrict__ q, int64_t N, int64_t s) {
+  return Sym<S>{q[s], q[N + s], q[2 * N + s], q[3 * N + s], q[4 * N + s]};
+}
+
+template <typename S>
+__device__ __forceinline__ void store_sym(S* __restrict__ q, int64_t N, int64_t s, const Sym<S>& v) {
+  q[s] = v.xx;
+  q[N + s] = v.xy;
+  q[2 * N + s] = v.xz;
+  q[3 * N + s] = v.yy;
+  q[4 * N + s] = v.yz;
+}
+
+// Central differences and compact Laplacian of a symmetric tensor field at
+// site s (Sec. 1.2.2: second-order differences).
+template <typename S, int DIM>
+__device__ __forceinline__ void stencil(const S* __restrict__ q, int64_t N, int64_t s, const Nbr& nb,
+                                        Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
+  c = load_sym(q, N, s);
+  const Sym<S> xp = load_sym(q, N, s + nb.xp), xm = load_sym(q, N, s + nb.xm);
+  const Sym<S> yp = load_sym(q, N, s + nb.yp), ym = load_sym(q, N, s + nb.ym);
+  auto half_diff = [](const Sym<S>& p, const Sym<S>& m) {
+    return Sym<S>{(p.xx - m.xx) * S(0.5), (p.xy - m.xy) * S(0.5), (p.xz - m.xz) * S(0.5),
+                  (p.yy - m.yy) * S(0.5), (p.yz - m.yz) * S(0.5)};
+  };
+  d[0] = half_diff(xp, xm);
+  d[1] = half_diff(yp, ym);
+  L.xx = (xp.xx + xm.xx) + (yp.xx + ym.xx);
+  L.xy = (xp.xy + xm.xy) + (yp.xy + ym.xy);
+  L.xz = (xp.xz + xm.xz) + (yp.xz + ym.xz);
+  L.yy = (xp.yy + xm.yy) + (yp.yy + ym.yy);
+  L.yz = (xp.yz + xm.yz) + (yp.yz + ym.yz);
+  S ncen = S(-4);
+  if constexpr (DIM == 3) {
+    const Sym<S> zp = load_sym(q, N, s + nb.zp), zm = load_sym(q, N, s + nb.zm);
+    d[2] = half_diff(zp, zm);
+    L.xx += zp.xx + zm.xx;
+    L.xy += zp.xy + zm.xy;
+    L.xz += zp.xz + zm.xz;
+    L.yy += zp.yy + zm.yy;
+    L.yz += zp.yz + zm.yz;
+    ncen = S(-6);
+  } else {
+    d[2] = sym_zero<S>();
+  }
+  L.xx += ncen * c.xx;
+  L.xy += ncen * c.xy;
+  L.xz += ncen * c.xz;
+  L.yy += ncen * c.yy;
+  L.yz += ncen * c.yz;
+}
+
+}  // namespace lc

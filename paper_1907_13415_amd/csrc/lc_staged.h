@@ -1,0 +1,216 @@
+// lc_staged.h -- the step as four simple sweeps, one site per thread.
+//
+// Stage kernels keep their intermediates in the caller's scratch buffer:
+//   stage_tau  : Q -> stress tau (Eq. 6) at every site;
+//   stage_lb   : f, tau -> body force, rho, u (Eq. 9), BGK collision with
+//                forcing and push streaming -> f_next; stores u;
+//   stage_pred : Q, u -> R(Q) and the predictor Q^P = Q + R (Sec. 1.2.2);
+//   stage_corr : Q, Q^P, R, u -> Q_next = Q + (R(Q) + R(Q^P))/2.
+// This is the plainest correct mapping of the method onto the GPU; the
+// fused and split kernels compute the same per-site arithmetic with fewer
+// HBM round trips.
+#pragma once
+
+#include "lc_device.h"
+
+namespace lc {
+
+struct GridDims {
+  int nx, ny, nz;
+  int64_t N;
+};
+
+// Number of stress components kept: D2Q9 needs tau_xx, tau_xy, tau_yx,
+// tau_yy (the z row of F is not carried); D3Q19 needs all nine.
+template <int LAT>
+struct TauLayout {
+  static constexpr int n = Lattice<LAT>::dim == 2 ? 4 : 9;
+  __host__ __device__ static constexpr int idx(int a, int b) {
+    return Lattice<LAT>::dim == 2 ? a * 2 + b : a * 3 + b;
+  }
+};
+
+template <int LAT, typename S>
+__global__ void __launch_bounds__(256) stage_tau(const S* __restrict__ Q, S* __restrict__ tau,
+                                                 GridDims g, Coef<S> c) {
+  constexpr int DIM = Lattice<LAT>::dim;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+  const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+  Sym<S> q, L, d[3];
+  stencil<S, DIM>(Q, g.N, s, nb, q, d, L);
+  const Sym<S> H = molecular_field(q, L, c);
+  S t[3][3];
+  stress(q, H, d, c, t);
+  constexpr int D = DIM;
+#pragma unroll
+  for (int a = 0; a < D; a++)
+#pragma unroll
+    for (int b = 0; b < D; b++) tau[TauLayout<LAT>::idx(a, b) * g.N + s] = t[a][b];
+}
+
+// Body force F_a = sum_b [tau_ab(x+e_b) - tau_ab(x-e_b)]/2 (Sec. 1.2.1).
+template <int LAT, typename S>
+__device__ __forceinline__ void body_force(const S* __restrict__ tau, int64_t N, int64_t s, const Nbr& nb,
+                                           S (&F)[3]) {
+  constexpr int DIM = Lattice<LAT>::dim;
+  const int64_t off[3][2] = {{nb.xp, nb.xm}, {nb.yp, nb.ym}, {nb.zp, nb.zm}};
+#pragma unroll
+  for (int a = 0; a < 3; a++) F[a] = S(0);
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    S acc = S(0);
+#pragma unroll
+    for (int b = 0; b < DIM; b++) {
+      const S* t = tau + TauLayout<LAT>::idx(a, b) * N;
+      acc += (t[s + off[b][0]] - t[s + off[b][1]]) * S(0.5);
+    }
+    F[a] = acc;
+  }
+}
+
+// Density and force-corrected velocity (Eq. 9) from the populations at s.
+// With DEV the stored values are f_i - w_i (rho0 = 1); sum_i w_i c_i = 0.
+template <int LAT, typename S, bool DEV>
+__device__ __forceinline__ void moments(const S (&f)[Lattice<LAT>::q], const S (&F)[3], S& rho, S (&u)[3]) {
+  using L = Lattice<LAT>;
+  S m = S(0), jx = S(0), jy = S(0), jz = S(0);
+#pragma unroll
+  for (int i = 0; i < L::q; i++) {
+    m += f[i];
+    if (L::cx(i) == 1) jx += f[i];
+    if (L::cx(i) == -1) jx -= f[i];
+    if (L::cy(i) == 1) jy += f[i];
+    if (L::cy(i) == -1) jy -= f[i];
+    if (L::cz(i) == 1) jz += f[i];
+    if (L::cz(i) == -1) jz -= f[i];
+  }
+  rho = DEV ? S(1) + m : m;
+  const S inv = S(1) / rho;
+  u[0] = (jx + S(0.5) * F[0]) * inv;
+  u[1] = (jy + S(0.5) * F[1]) * inv;
+  u[2] = L::dim == 3 ? (jz + S(0.5) * F[2]) * inv : S(0);
+}
+
+// BGK collision with the forcing term of Sec. 1.2.1, in place on f.
+// Equilibrium Eq. (8) with c_s^2 = 1/3; in DEV form the rest weight w_i is
+// removed from both f and f_eq, so only deviations are formed.
+template <int LAT, typename S, bool DEV>
+__device__ __forceinline__ void collide(S (&f)[Lattice<LAT>::q], S rho, const S (&u)[3], const S (&F)[3],
+                                        const Coef<S>& c) {
+  using L = Lattice<LAT>;
+  const S uu15 = S(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const S uF3 = S(3) * (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]);
+  const S drho = DEV ? rho - S(1) : rho;
+#pragma unroll
+  for (int i = 0; i < L::q; i++) {
+    const S w = S(L::w(i));
+    const S cu = S(L::cx(i)) * u[0] + S(L::cy(i)) * u[1] + S(L::cz(i)) * u[2];
+    const S cF = S(L::cx(i)) * F[0] + S(L::cy(i)) * F[1] + S(L::cz(i)) * F[2];
+    // f_eq - (DEV ? w : 0)
+    const S feq = DEV ? w * (drho + rho * (S(3) * cu + S(4.5) * cu * cu - uu15))
+                      : w * rho * (S(1) + S(3) * cu + S(4.5) * cu * cu - uu15);
+    const S src = w * c.src * (S(3) * cF * (S(1) + S(3) * cu) - uF3);
+    f[i] = f[i] - c.omega * (f[i] - feq) + src;
+  }
+}
+
+template <int LAT, typename S, bool DEV>
+__global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const S* __restrict__ tau,
+                                                S* __restrict__ fout, S* __restrict__ uout,
+                                                GridDims g, Coef<S> c) {
+  using L = Lattice<LAT>;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t N = g.N;
+  const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+  const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+  S F[3];
+  body_force<LAT, S>(tau, N, s, nb, F);
+  S f[L::q];
+#pragma unroll
+  for (int i = 0; i < L::q; i++) f[i] = fin[i * N + s];
+  S rho, u[3];
+  moments<LAT, S, DEV>(f, F, rho, u);
+#pragma unroll
+  for (int a = 0; a < L::dim; a++) uout[a * N + s] = u[a];
+  collide<LAT, S, DEV>(f, rho, u, F, c);
+#pragma unroll
+  for (int i = 0; i < L::q; i++) {
+    int64_t d = s;
+    if (L::cx(i) == 1) d += nb.xp;
+    if (L::cx(i) == -1) d += nb.xm;
+    if (L::cy(i) == 1) d += nb.yp;
+    if (L::cy(i) == -1) d += nb.ym;
+    if (L::cz(i) == 1) d += nb.zp;
+    if (L::cz(i) == -1) d += nb.zm;
+    fout[i * N + d] = f[i];
+  }
+}
+
+// Velocity gradient G[a][b] = d_b u_a (central differences).
+template <int DIM, typename S>
+__device__ __forceinline__ void velocity_gradient(const S* __restrict__ u, int64_t N, int64_t s, const Nbr& nb,
+                                                  S (&G)[3][3], S (&uc)[3]) {
+  const int64_t off[3][2] = {{nb.xp, nb.xm}, {nb.yp, nb.ym}, {nb.zp, nb.zm}};
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    uc[a] = a < DIM ? u[a * N + s] : S(0);
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+      G[a][b] = (a < DIM && b < DIM) ? (u[a * N + s + off[b][0]] - u[a * N + s + off[b][1]]) * S(0.5) : S(0);
+  }
+}
+
+template <int LAT, typename S>
+__global__ void __launch_bounds__(256) stage_pred(const S* __restrict__ Q, const S* __restrict__ u,
+                                                  S* __restrict__ qp, S* __restrict__ rq, GridDims g,
+                                                  Coef<S> c) {
+  constexpr int DIM = Lattice<LAT>::dim;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+  const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+  Sym<S> q, L, d[3];
+  stencil<S, DIM>(Q, g.N, s, nb, q, d, L);
+  const Sym<S> H = molecular_field(q, L, c);
+  S G[3][3], uc[3];
+  velocity_gradient<DIM, S>(u, g.N, s, nb, G, uc);
+  const Sym<S> R = be_rate(q, H, d, uc, G, c);
+  store_sym(rq, g.N, s, R);
+  store_sym(qp, g.N, s, Sym<S>{q.xx + R.xx, q.xy + R.xy, q.xz + R.xz, q.yy + R.yy, q.yz + R.yz});
+}
+
+template <int LAT, typename S>
+__global__ void __launch_bounds__(256) stage_corr(const S* __restrict__ Q, const S* __restrict__ qp,
+                                                  const S* __restrict__ rq, const S* __restrict__ u,
+                                                  S* __restrict__ Qout, GridDims g, Coef<S> c) {
+  constexpr int DIM = Lattice<LAT>::dim;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+  const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+  Sym<S> p, L, d[3];
+  stencil<S, DIM>(qp, g.N, s, nb, p, d, L);
+  const Sym<S> H = molecular_field(p, L, c);
+  S G[3][3], uc[3];
+  velocity_gradient<DIM, S>(u, g.N, s, nb, G, uc);
+  const Sym<S> Rp = be_rate(p, H, d, uc, G, c);
+  const Sym<S> q = load_sym(Q, g.N, s);
+  const Sym<S> R = load_sym(rq, g.N, s);
+  store_sym(Qout, g.N, s,
+            Sym<S>{q.xx + S(0.5) * (R.xx + Rp.xx), q.xy + S(0.5) * (R.xy + Rp.xy),
+                   q.xz + S(0.5) * (R.xz + Rp.xz), q.yy + S(0.5) * (R.yy + Rp.yy),
+                   q.yz + S(0.5) * (R.yz + Rp.yz)});
+}
+
+}  // namespace lc

@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/lc.h declares, and validates arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(lc_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1907_13415_amd import lc
+    lib = ctypes.CDLL(lc.LIB_PATH)
+    names = _declared()
+    assert "lc_init" in names and "lc_step" in names and "lc_observe" in names
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_lattice_info_matches_quadrature():
+    import numpy as np
+    from paper_1907_13415_amd import lc
+    for lat, q in ((lc.LC_D2Q9, 9), (lc.LC_D3Q19, 19)):
+        c, w = lc.lc_lattice_info(lat)
+        assert c.shape == (q, 3)
+        assert abs(w.sum() - 1) < 1e-15
+        m2 = np.einsum("i,ia,ib->ab", w, c, c)
+        d = 2 if q == 9 else 3
+        assert np.allclose(m2[:d, :d], np.eye(d) / 3, atol=1e-15)
+
+
+def _fake_bufs(lc, align=256):
+    base = 1 << 40
+    return lc.lc_buffers((ctypes.c_void_p * 2)(base, base + 1 * (1 << 30)),
+                         (ctypes.c_void_p * 2)(base + 2 * (1 << 30), base + 3 * (1 << 30)),
+                         base + 4 * (1 << 30) + (0 if align == 256 else 8))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=0.4), dict(K=-1.0), dict(Gamma=0.0), dict(A0=0.0),
+    dict(eta=0.2), dict(gamma=float("nan")), dict(xi=float("inf")),
+])
+def test_init_rejects_bad_params(bad):
+    from paper_1907_13415_amd import lc
+    p = dict(A0=1.0, gamma=2.7, K=0.04, Gamma=0.3, xi=0.7, tau=1.0)
+    p.update({k: v for k, v in bad.items() if k != "eta"})
+    params = lc.make_params(p["A0"], p["gamma"], p["K"], p["Gamma"], p["xi"], p["tau"], eta=bad.get("eta"))
+    grid = lc.make_grid(lc.LC_D2Q9, lc.LC_FP64, 16, 16, 1)
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_init(grid, params, _fake_bufs(lc), 0)
+    assert e.value.code == lc.LC_EINVAL
+
+
+@pytest.mark.parametrize("grid", [(0, 0, 16, 16, 2), (0, 0, 0, 16, 1), (2, 0, 16, 16, 1), (0, 3, 16, 16, 1),
+                                  (1, 1, 8, -1, 8)])
+def test_init_rejects_bad_grid(grid):
+    from paper_1907_13415_amd import lc
+    params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_init(lc.make_grid(*grid), params, _fake_bufs(lc), 0)
+    assert e.value.code == lc.LC_EINVAL
+
+
+def test_init_rejects_misaligned_buffers_and_accepts_good_ones():
+    from paper_1907_13415_amd import lc
+    params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
+    grid = lc.make_grid(lc.LC_D3Q19, lc.LC_FP32_DEV, 8, 8, 8)
+    with pytest.raises(lc.LCError):
+        lc.lc_init(grid, params, _fake_bufs(lc, align=8), 0)
+    ctx = lc.lc_init(grid, params, _fake_bufs(lc), 0)
+    # stepping before loading a state is an ordering error, caught on the host
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_step(ctx, 1)
+    assert e.value.code == lc.LC_ESTATE
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_step(ctx, -1)
+    assert e.value.code == lc.LC_EINVAL
+    lc.lc_free(ctx)
+
+
+def test_buffer_bytes():
+    from paper_1907_13415_amd import lc
+    fb, qb, sb = lc.lc_buffer_bytes(lc.make_grid(lc.LC_D3Q19, lc.LC_FP32_DEV, 16, 8, 4))
+    assert fb == 19 * 512 * 4 and qb == 5 * 512 * 4 and sb > 0
+    fb, qb, sb = lc.lc_buffer_bytes(lc.make_grid(lc.LC_D2Q9, lc.LC_FP64, 16, 8, 1))
+    assert fb == 9 * 128 * 8 and qb == 5 * 128 * 8
