@@ -10,6 +10,7 @@
 
 #include "../../include/lc.h"
 #include "lc_aux.h"
+#include "lc_split.h"
 #include "lc_runtime.h"
 
 namespace lc {
@@ -158,6 +159,47 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
   return hip_check(hipGetLastError(), "step launch");
 }
 
+// Tile shapes of the two-sweep kernels (LDS per block stays below 64 KB).
+template <int LAT, typename S>
+struct SplitCfg {
+  static constexpr bool d3 = Lattice<LAT>::dim == 3;
+  static constexpr bool f64 = sizeof(S) == 8;
+  static constexpr int LB_TX = 32, LB_TY = (d3 && f64) ? 4 : 8;
+  static constexpr int Q_TX = (d3 && f64) ? 16 : 32, Q_TY = 8;
+  static constexpr int ZC = 32;
+};
+
+template <int LAT, typename S, bool DEV>
+static lc_status run_steps_split(lc_ctx* c, int64_t n) {
+  using C = SplitCfg<LAT, S>;
+  const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
+  const Coef<S> k = make_coef<S>(c->p);
+  S* u = reinterpret_cast<S*>(static_cast<char*>(c->b.scratch) + c->L.off_u);
+  const int zc = C::d3 ? C::ZC : 1;
+  const unsigned gz = unsigned((c->g.nz + zc - 1) / zc);
+  const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY, gz);
+  const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY, gz);
+  for (int64_t it = 0; it < n; it++) {
+    const S* f0 = static_cast<const S*>(c->b.f[c->parity]);
+    S* f1 = static_cast<S*>(c->b.f[c->parity ^ 1]);
+    const S* q0 = static_cast<const S*>(c->b.Q[c->parity]);
+    S* q1 = static_cast<S*>(c->b.Q[c->parity ^ 1]);
+    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY>), g1, dim3(C::LB_TX, C::LB_TY), 0, c->stream, q0,
+                       f0, f1, u, gd, k, zc);
+    hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u, q1, gd,
+                       k, zc);
+    c->parity ^= 1;
+    c->step++;
+  }
+  return hip_check(hipGetLastError(), "step launch");
+}
+
+template <int LAT, typename S, bool DEV>
+static lc_status run_steps(lc_ctx* c, int64_t n) {
+  if (c->variant == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV>(c, n);
+  return run_steps_staged<LAT, S, DEV>(c, n);
+}
+
 template <int LAT, typename S, bool DEV>
 static lc_status compute_tau(lc_ctx* c) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
@@ -302,7 +344,7 @@ lc_status lc_init(const lc_grid* grid, const lc_params* params, const lc_buffers
   c->parity = 0;
   c->step = 0;
   c->loaded = false;
-  c->variant = LC_VARIANT_STAGED;
+  c->variant = LC_VARIANT_SPLIT;
   *out = c;
   return LC_OK;
 }
@@ -319,12 +361,15 @@ lc_status lc_set_params(lc_ctx* c, const lc_params* params) {
 lc_status lc_set_variant(lc_ctx* c, int32_t variant) {
   clear_error();
   if (!c) return fail(LC_EINVAL, "ctx is NULL");
-  if (variant == LC_VARIANT_AUTO || variant == LC_VARIANT_STAGED) {
+  if (variant == LC_VARIANT_AUTO || variant == LC_VARIANT_SPLIT) {
+    c->variant = LC_VARIANT_SPLIT;
+    return LC_OK;
+  }
+  if (variant == LC_VARIANT_STAGED) {
     c->variant = LC_VARIANT_STAGED;
     return LC_OK;
   }
-  if (variant == LC_VARIANT_SPLIT || variant == LC_VARIANT_FUSED)
-    return fail(LC_EUNSUPPORTED, "variant %d not available", variant);
+  if (variant == LC_VARIANT_FUSED) return fail(LC_EUNSUPPORTED, "variant %d not available", variant);
   return fail(LC_EINVAL, "unknown variant %d", variant);
 }
 
@@ -345,7 +390,7 @@ lc_status lc_step(lc_ctx* c, int64_t n) {
   if (n < 0) return fail(LC_EINVAL, "n must be >= 0");
   if (!c->loaded) return fail(LC_ESTATE, "lc_step before lc_load_state");
   if (n == 0) return LC_OK;
-  return LC_DISPATCH(c, run_steps_staged, n);
+  return LC_DISPATCH(c, run_steps, n);
 }
 
 lc_status lc_observe(lc_ctx* c, uint32_t mask, int32_t half_axis, lc_observables* out) {

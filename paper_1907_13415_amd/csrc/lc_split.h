@@ -1,0 +1,364 @@
+// lc_split.h -- the step as two sweeps with LDS halo tiles.
+//
+//   split_lb : stress (Eq. 6) on the tile plus a one-site ring, kept in LDS;
+//              body force, moments (Eq. 9), BGK collision with forcing and
+//              push streaming for the tile; stores the force-corrected u.
+//   split_q  : rate R(Q) and predictor Q^P on the tile plus ring (LDS),
+//              then the corrector R(Q^P) and Q(n+1) for the tile
+//              (Sec. 1.2.2, steps 1-5).
+//
+// A block owns a TX x TY column of sites and marches along z through a
+// chunk of planes.  In-plane neighbours come from LDS planes staged with a
+// two-site halo; z neighbours of computed quantities stay in registers of
+// the owning thread (a three-plane window), so nothing is recomputed along
+// z.  Every index is taken modulo the grid (periodic), so any grid size,
+// including sizes smaller than the tile, is handled.  On two-dimensional
+// lattices the block treats its single plane without the z pipeline.
+#pragma once
+
+#include "lc_staged.h"
+
+namespace lc {
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+template <int TX, int TY>
+struct Tile {
+  static constexpr int NT = TX * TY;
+  static constexpr int W2 = TX + 4, H2 = TY + 4, R2 = W2 * H2;  // two-site halo
+  static constexpr int W1 = TX + 2, H1 = TY + 2, R1 = W1 * H1;  // one-site halo
+  static constexpr int RING = 2 * TX + 2 * TY;                  // one-site ring, no corners
+  static_assert(RING <= NT, "tile too thin for its ring");
+  // R1 coordinates of ring point k: top row, bottom row, left, right column.
+  __device__ static __forceinline__ void ring(int k, int& i, int& j) {
+    if (k < TX) {
+      i = k + 1;
+      j = 0;
+    } else if (k < 2 * TX) {
+      i = k - TX + 1;
+      j = TY + 1;
+    } else if (k < 2 * TX + TY) {
+      i = 0;
+      j = k - 2 * TX + 1;
+    } else {
+      i = TX + 1;
+      j = k - 2 * TX - TY + 1;
+    }
+  }
+  // R2 index of the R1 point (i, j).
+  __device__ static __forceinline__ int r2(int i, int j) { return (i + 1) + W2 * (j + 1); }
+};
+
+// Stencil of a symmetric tensor from LDS planes: centre plane `m` indexed
+// by the R2 index k, z neighbours in planes zp/zm at the same index.
+template <typename S, int DIM, int W2, int R2>
+__device__ __forceinline__ void stencil_lds(const S (*m)[R2], const S (*zp)[R2], const S (*zm)[R2], int k,
+                                            Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
+  S v[5], lap[5], dx[5], dy[5], dz[5];
+#pragma unroll
+  for (int q = 0; q < 5; q++) {
+    const S cc = m[q][k];
+    const S xp = m[q][k + 1], xm = m[q][k - 1], yp = m[q][k + W2], ym = m[q][k - W2];
+    v[q] = cc;
+    dx[q] = (xp - xm) * S(0.5);
+    dy[q] = (yp - ym) * S(0.5);
+    S l = (xp + xm) + (yp + ym);
+    if constexpr (DIM == 3) {
+      const S zpv = zp[q][k], zmv = zm[q][k];
+      dz[q] = (zpv - zmv) * S(0.5);
+      l += zpv + zmv;
+      lap[q] = l - S(6) * cc;
+    } else {
+      dz[q] = S(0);
+      lap[q] = l - S(4) * cc;
+    }
+  }
+  c = Sym<S>{v[0], v[1], v[2], v[3], v[4]};
+  d[0] = Sym<S>{dx[0], dx[1], dx[2], dx[3], dx[4]};
+  d[1] = Sym<S>{dy[0], dy[1], dy[2], dy[3], dy[4]};
+  d[2] = Sym<S>{dz[0], dz[1], dz[2], dz[3], dz[4]};
+  L = Sym<S>{lap[0], lap[1], lap[2], lap[3], lap[4]};
+}
+
+// Load plane gz of NC component arrays (component stride N) into an LDS
+// plane over the R2 region of the block, with periodic wrap.
+// dst points at an LDS plane laid out [NC][R2].
+template <typename S, int TX, int TY, int NC>
+__device__ __forceinline__ void load_region(S* dst, const S* const* src, int x0, int y0, int gz,
+                                            const GridDims& g, int tid) {
+  constexpr int W2 = TX + 4, R2 = (TX + 4) * (TY + 4), NT = TX * TY;
+  const int plane = g.nx * g.ny * gz;
+  for (int k = tid; k < R2; k += NT) {
+    const int i = k % W2, j = k / W2;
+    const int gx = wrapi(x0 - 2 + i, g.nx), gy = wrapi(y0 - 2 + j, g.ny);
+    const int s = plane + gx + g.nx * gy;
+#pragma unroll
+    for (int q = 0; q < NC; q++) dst[q * R2 + k] = src[q][s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep 1: stress in LDS, body force, moments, collision, streaming.
+template <int LAT, typename S, bool DEV, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, const S* __restrict__ fin,
+                                                   S* __restrict__ fout, S* __restrict__ uout, GridDims g,
+                                                   Coef<S> c, int zc) {
+  using L = Lattice<LAT>;
+  using T = Tile<TX, TY>;
+  constexpr int DIM = L::dim;
+  constexpr int NQP = DIM == 3 ? 3 : 1;  // Q planes held
+  constexpr int NTP = DIM == 3 ? 2 : 1;  // stress planes held
+  constexpr int NTC = 2 * DIM;           // tau_{a x} and tau_{a y}, a < DIM
+  __shared__ S sQ[NQP][5][T::R2];
+  __shared__ S sT[NTP][NTC][T::R1];
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < g.nx && y < g.ny;
+  const int64_t N = g.N;
+  const S* const qsrc[5] = {Qin, Qin + N, Qin + 2 * N, Qin + 3 * N, Qin + 4 * N};
+
+  // stress at the R1 point (i, j) of plane slot m with z neighbours zp/zm
+  auto tau_point = [&](int m, int zp, int zm, int i, int j, S (&t)[3][3]) {
+    Sym<S> q, Lq, d[3];
+    stencil_lds<S, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
+    const Sym<S> H = molecular_field(q, Lq, c);
+    stress(q, H, d, c, t);
+  };
+  // stress of the whole region of plane slot m into sT[ts]; returns the
+  // owner's tau_{a z}
+  auto tau_plane = [&](int m, int zp, int zm, int ts, S (&tz)[3]) {
+    {
+      S t[3][3];
+      const int i = tx + 1, j = ty + 1;
+      tau_point(m, zp, zm, i, j, t);
+      const int k1 = i + T::W1 * j;
+#pragma unroll
+      for (int a = 0; a < DIM; a++) {
+        sT[ts][a][k1] = t[a][0];
+        sT[ts][DIM + a][k1] = t[a][1];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; a++) tz[a] = t[a][2];
+    }
+    if (tid < T::RING) {
+      S t[3][3];
+      int i, j;
+      T::ring(tid, i, j);
+      tau_point(m, zp, zm, i, j, t);
+      const int k1 = i + T::W1 * j;
+#pragma unroll
+      for (int a = 0; a < DIM; a++) {
+        sT[ts][a][k1] = t[a][0];
+        sT[ts][DIM + a][k1] = t[a][1];
+      }
+    }
+  };
+  // lattice-Boltzmann update of the owner's site in plane z
+  auto lb_site = [&](int z, int ts, const S (&tzp)[3], const S (&tzm)[3]) {
+    if (!own) return;
+    const int k1 = (tx + 1) + T::W1 * (ty + 1);
+    S F[3] = {S(0), S(0), S(0)};
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      S acc = (sT[ts][a][k1 + 1] - sT[ts][a][k1 - 1]) + (sT[ts][DIM + a][k1 + T::W1] - sT[ts][DIM + a][k1 - T::W1]);
+      if constexpr (DIM == 3) acc += tzp[a] - tzm[a];
+      F[a] = S(0.5) * acc;
+    }
+    const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+    S f[L::q];
+#pragma unroll
+    for (int i = 0; i < L::q; i++) f[i] = fin[i * N + s];
+    S rho, u[3];
+    moments<LAT, S, DEV>(f, F, rho, u);
+#pragma unroll
+    for (int a = 0; a < DIM; a++) uout[a * N + s] = u[a];
+    collide<LAT, S, DEV>(f, rho, u, F, c);
+    const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+#pragma unroll
+    for (int i = 0; i < L::q; i++) {
+      int64_t d = s;
+      if (L::cx(i) == 1) d += nb.xp;
+      if (L::cx(i) == -1) d += nb.xm;
+      if (L::cy(i) == 1) d += nb.yp;
+      if (L::cy(i) == -1) d += nb.ym;
+      if (L::cz(i) == 1) d += nb.zp;
+      if (L::cz(i) == -1) d += nb.zm;
+      fout[i * N + d] = f[i];
+    }
+  };
+
+  if constexpr (DIM == 2) {
+    load_region<S, TX, TY, 5>(&sQ[0][0][0], qsrc, x0, y0, 0, g, tid);
+    __syncthreads();
+    S tz[3];
+    tau_plane(0, 0, 0, 0, tz);
+    __syncthreads();
+    lb_site(0, 0, tz, tz);
+  } else {
+    const int zb = blockIdx.z * zc;
+    const int ze = min(zb + zc, g.nz);
+    auto slot = [](int p) { return (p + 3) % 3; };  // p >= -3
+    load_region<S, TX, TY, 5>(&sQ[slot(zb - 2)][0][0], qsrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
+    load_region<S, TX, TY, 5>(&sQ[slot(zb - 1)][0][0], qsrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
+    S tzA[3] = {S(0), S(0), S(0)}, tzB[3] = {S(0), S(0), S(0)}, tzC[3];
+    for (int p = zb - 1; p <= ze; p++) {
+      load_region<S, TX, TY, 5>(&sQ[slot(p + 1)][0][0], qsrc, x0, y0, wrapi(p + 1, g.nz), g, tid);
+      __syncthreads();
+      tau_plane(slot(p), slot(p + 1), slot(p - 1), p & 1, tzC);
+      __syncthreads();
+      if (p - 1 >= zb) lb_site(p - 1, (p - 1) & 1, tzC, tzA);
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        tzA[a] = tzB[a];
+        tzB[a] = tzC[a];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sweep 2: predictor on tile + ring (LDS), corrector on the tile.
+template <int LAT, typename S, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) split_q(const S* __restrict__ Qin, const S* __restrict__ uin,
+                                                  S* __restrict__ Qout, GridDims g, Coef<S> c, int zc) {
+  using L = Lattice<LAT>;
+  using T = Tile<TX, TY>;
+  constexpr int DIM = L::dim;
+  constexpr int NP = DIM == 3 ? 3 : 1;
+  constexpr int NC = 5 + DIM;  // Q components then u components
+  constexpr int NPP = DIM == 3 ? 2 : 1;
+  __shared__ S sQ[NP][NC][T::R2];
+  __shared__ S sP[NPP][5][T::R1];
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool own = x < g.nx && y < g.ny;
+  const int64_t N = g.N;
+  const S* src[NC];
+#pragma unroll
+  for (int q = 0; q < 5; q++) src[q] = Qin + q * N;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) src[5 + a] = uin + a * N;
+  const S* const* csrc = src;
+
+  struct Stash {
+    Sym<S> q, r;
+    S u[3];
+    S G[3][3];
+  };
+
+  // rate and predictor at R1 point (i, j) of plane slot m
+  auto pred_point = [&](int m, int zp, int zm, int i, int j, Stash& st) {
+    const int k = T::r2(i, j);
+    Sym<S> q, Lq, d[3];
+    stencil_lds<S, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
+    const Sym<S> H = molecular_field(q, Lq, c);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      st.u[a] = a < DIM ? sQ[m][5 + a][k] : S(0);
+      st.G[a][0] = a < DIM ? (sQ[m][5 + a][k + 1] - sQ[m][5 + a][k - 1]) * S(0.5) : S(0);
+      st.G[a][1] = a < DIM ? (sQ[m][5 + a][k + T::W2] - sQ[m][5 + a][k - T::W2]) * S(0.5) : S(0);
+      if constexpr (DIM == 3)
+        st.G[a][2] = (sQ[zp][5 + a][k] - sQ[zm][5 + a][k]) * S(0.5);
+      else
+        st.G[a][2] = S(0);
+    }
+    st.q = q;
+    st.r = be_rate(q, H, d, st.u, st.G, c);
+  };
+  auto store_pred = [&](int ps, int i, int j, const Stash& st) {
+    const int k1 = i + T::W1 * j;
+    sP[ps][0][k1] = st.q.xx + st.r.xx;
+    sP[ps][1][k1] = st.q.xy + st.r.xy;
+    sP[ps][2][k1] = st.q.xz + st.r.xz;
+    sP[ps][3][k1] = st.q.yy + st.r.yy;
+    sP[ps][4][k1] = st.q.yz + st.r.yz;
+  };
+  // predictor over the region; the owner keeps its stash and its Q^P
+  auto pred_plane = [&](int m, int zp, int zm, int ps, Stash& st, Sym<S>& qp) {
+    pred_point(m, zp, zm, tx + 1, ty + 1, st);
+    store_pred(ps, tx + 1, ty + 1, st);
+    qp = Sym<S>{st.q.xx + st.r.xx, st.q.xy + st.r.xy, st.q.xz + st.r.xz, st.q.yy + st.r.yy, st.q.yz + st.r.yz};
+    if (tid < T::RING) {
+      int i, j;
+      T::ring(tid, i, j);
+      Stash tmp;
+      pred_point(m, zp, zm, i, j, tmp);
+      store_pred(ps, i, j, tmp);
+    }
+  };
+  // corrector at the owner's site of plane z
+  auto corr_site = [&](int z, int ps, const Stash& st, const Sym<S>& qpz_p, const Sym<S>& qpz_m) {
+    if (!own) return;
+    const int k1 = (tx + 1) + T::W1 * (ty + 1);
+    S v[5], lap[5], dx[5], dy[5], dz[5];
+    const S qpzp[5] = {qpz_p.xx, qpz_p.xy, qpz_p.xz, qpz_p.yy, qpz_p.yz};
+    const S qpzm[5] = {qpz_m.xx, qpz_m.xy, qpz_m.xz, qpz_m.yy, qpz_m.yz};
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+      const S cc = sP[ps][q][k1];
+      const S xp = sP[ps][q][k1 + 1], xm = sP[ps][q][k1 - 1];
+      const S yp = sP[ps][q][k1 + T::W1], ym = sP[ps][q][k1 - T::W1];
+      v[q] = cc;
+      dx[q] = (xp - xm) * S(0.5);
+      dy[q] = (yp - ym) * S(0.5);
+      S l = (xp + xm) + (yp + ym);
+      if constexpr (DIM == 3) {
+        dz[q] = (qpzp[q] - qpzm[q]) * S(0.5);
+        l += qpzp[q] + qpzm[q];
+        lap[q] = l - S(6) * cc;
+      } else {
+        dz[q] = S(0);
+        lap[q] = l - S(4) * cc;
+      }
+    }
+    const Sym<S> p{v[0], v[1], v[2], v[3], v[4]};
+    const Sym<S> d[3] = {Sym<S>{dx[0], dx[1], dx[2], dx[3], dx[4]}, Sym<S>{dy[0], dy[1], dy[2], dy[3], dy[4]},
+                         Sym<S>{dz[0], dz[1], dz[2], dz[3], dz[4]}};
+    const Sym<S> Lp{lap[0], lap[1], lap[2], lap[3], lap[4]};
+    const Sym<S> H = molecular_field(p, Lp, c);
+    const Sym<S> Rp = be_rate(p, H, d, st.u, st.G, c);
+    const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+    Qout[s] = st.q.xx + S(0.5) * (st.r.xx + Rp.xx);
+    Qout[N + s] = st.q.xy + S(0.5) * (st.r.xy + Rp.xy);
+    Qout[2 * N + s] = st.q.xz + S(0.5) * (st.r.xz + Rp.xz);
+    Qout[3 * N + s] = st.q.yy + S(0.5) * (st.r.yy + Rp.yy);
+    Qout[4 * N + s] = st.q.yz + S(0.5) * (st.r.yz + Rp.yz);
+  };
+
+  if constexpr (DIM == 2) {
+    load_region<S, TX, TY, NC>(&sQ[0][0][0], csrc, x0, y0, 0, g, tid);
+    __syncthreads();
+    Stash st;
+    Sym<S> qp;
+    pred_plane(0, 0, 0, 0, st, qp);
+    __syncthreads();
+    corr_site(0, 0, st, qp, qp);
+  } else {
+    const int zb = blockIdx.z * zc;
+    const int ze = min(zb + zc, g.nz);
+    auto slot = [](int p) { return (p + 3) % 3; };
+    load_region<S, TX, TY, NC>(&sQ[slot(zb - 2)][0][0], csrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
+    load_region<S, TX, TY, NC>(&sQ[slot(zb - 1)][0][0], csrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
+    Stash stB, stC;  // planes p-1 and p
+    Sym<S> qpA = sym_zero<S>(), qpB = sym_zero<S>(), qpC;
+    for (int p = zb - 1; p <= ze; p++) {
+      load_region<S, TX, TY, NC>(&sQ[slot(p + 1)][0][0], csrc, x0, y0, wrapi(p + 1, g.nz), g, tid);
+      __syncthreads();
+      pred_plane(slot(p), slot(p + 1), slot(p - 1), p & 1, stC, qpC);
+      __syncthreads();
+      if (p - 1 >= zb) corr_site(p - 1, (p - 1) & 1, stB, qpC, qpA);
+      qpA = qpB;
+      qpB = qpC;
+      stB = stC;
+    }
+  }
+}
+
+}  // namespace lc

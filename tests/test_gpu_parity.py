@@ -172,3 +172,71 @@ def test_fp32dev_within_tolerance_on_S(variant):
     err = np.abs(S_gpu - S_ref).max()
     _announce("fp32dev max |dS| = %.3e" % err)
     assert err < 1e-5
+
+
+def _export_dev(lc, s, field, ncomp):
+    import torch
+    out = torch.empty((ncomp,) + s.shape, dtype=torch.float64, device=s.device)
+    with torch.cuda.stream(s.stream):
+        lc.lc_export(s.ctx, field, out.data_ptr())
+    s.stream.synchronize()
+    return out
+
+
+def _patch(t, z, y, x, r):
+    """(C, 2r+1, 2r+1, 2r+1) periodic patch of a device tensor around (z, y, x)."""
+    import torch
+    nz, ny, nx = t.shape[1:]
+    iz = torch.tensor([(z + d) % nz for d in range(-r, r + 1)], device=t.device)
+    iy = torch.tensor([(y + d) % ny for d in range(-r, r + 1)], device=t.device)
+    ix = torch.tensor([(x + d) % nx for d in range(-r, r + 1)], device=t.device)
+    return t[:, iz][:, :, iy][:, :, :, ix].cpu().numpy()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32dev", 2e-6), ("fp64", 1e-12)])
+def test_full_size_slab_256cubed_sampled_sites(prec, tol):
+    """The 256^3 D3Q19 slab workload in the launch configuration the
+    benchmark times: one GPU step from a developed state is compared, at
+    sampled sites (tile corners, chunk boundaries, periodic edges and random
+    sites), with the oracle run on a periodic patch of radius 6 around each
+    site (the step depends on Q within 4 sites and f within 2)."""
+    lc = _lc()
+    _announce("full-size 256^3 %s" % prec)
+    w = inputs.config2(256)
+    s = lc.Solver("D3Q19", prec, w.shape, w.params)
+    s.load(w.q5)
+    s.step(3)
+    f0 = _export_dev(lc, s, lc.LC_FIELD_F, 19)
+    q0 = _export_dev(lc, s, lc.LC_FIELD_Q, 5)
+    s.step(1)
+    f1 = _export_dev(lc, s, lc.LC_FIELD_F, 19)
+    q1 = _export_dev(lc, s, lc.LC_FIELD_Q, 5)
+    rng = np.random.default_rng(42)
+    sites = [(0, 0, 0), (255, 255, 255), (31, 7, 31), (32, 8, 32), (127, 128, 64), (191, 3, 250), (64, 64, 0),
+             (96, 255, 33)]
+    sites += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(40)]
+    r = 6
+    worst_f = worst_q = 0.0
+    for (z, y, x) in sites:
+        fp = _patch(f0, z, y, x, r)
+        qp = _patch(q0, z, y, x, r)
+        fr, qr = oracle.run(oracle.D3Q19, fp, qp, w.params, 1)
+        got_f = f1[:, z, y, x].cpu().numpy()
+        got_q = q1[:, z, y, x].cpu().numpy()
+        worst_f = max(worst_f, np.abs(got_f - fr[:, r, r, r]).max() / (1 / 3))
+        worst_q = max(worst_q, np.abs(got_q - qr[:, r, r, r]).max() / (1 / 3))
+    _announce("256^3 %s sampled: err f %.3e Q %.3e" % (prec, worst_f, worst_q))
+    assert worst_f < tol and worst_q < tol
+
+
+@pytest.mark.parametrize("prec", ["fp64"])
+def test_full_size_droplet_256sq_fp64(prec):
+    """The 256^2 droplet workload (delta gamma = 0.005) on the full grid
+    for 200 steps, in the launch configuration of the library default."""
+    lc = _lc()
+    w = inputs.config1(0.005)
+    s = lc.Solver("D2Q9", prec, w.shape, w.params)
+    s.load(w.q5)
+    s.step(200)
+    f_ref, q_ref = oracle.run(0, oracle.rest_populations(0, w.shape), w.q5, w.params, 200)
+    _compare_state(lc, s, f_ref, q_ref, TOL64, "droplet 256^2 step 200")
