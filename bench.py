@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -82,6 +84,14 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
+    if args.calibrate:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
     w = inputs.config2(args.n)
     res = {}
     for prec in ("fp32dev",) + (() if args.no_fp64 else ("fp64",)):

@@ -6,17 +6,30 @@
 namespace lc {
 
 // Logical double state -> storage form.  f_dev == nullptr: fluid at rest.
+// The population buffer is in pull form: buf_i(y) = f_i(y + c_i).
 template <int LAT, typename S, bool DEV>
 __global__ void __launch_bounds__(256) load_state(const double* __restrict__ f_dev,
                                                   const double* __restrict__ q_dev, S* __restrict__ f,
-                                                  S* __restrict__ Q, int64_t N) {
+                                                  S* __restrict__ Q, GridDims g) {
   using L = Lattice<LAT>;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t N = g.N;
+  const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+  const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
 #pragma unroll
   for (int i = 0; i < L::q; i++) {
+    int64_t d = s;
+    if (L::cx(i) == 1) d += nb.xp;
+    if (L::cx(i) == -1) d += nb.xm;
+    if (L::cy(i) == 1) d += nb.yp;
+    if (L::cy(i) == -1) d += nb.ym;
+    if (L::cz(i) == 1) d += nb.zp;
+    if (L::cz(i) == -1) d += nb.zm;
     const double w = L::w(i);
-    const double v = f_dev ? f_dev[i * N + s] : w;
+    const double v = f_dev ? f_dev[i * N + d] : w;
     f[i * N + s] = DEV ? S(v - w) : S(v);
   }
 #pragma unroll
@@ -24,15 +37,21 @@ __global__ void __launch_bounds__(256) load_state(const double* __restrict__ f_d
 }
 
 template <int LAT, typename S, bool DEV>
-__global__ void __launch_bounds__(256) export_fq(const S* __restrict__ f, const S* __restrict__ Q,
-                                                 double* __restrict__ fo, double* __restrict__ qo,
-                                                 int64_t N) {
+__global__ void __launch_bounds__(256) export_fq(const S* __restrict__ fb, const S* __restrict__ Q,
+                                                 double* __restrict__ fo, double* __restrict__ qo, GridDims g) {
   using L = Lattice<LAT>;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= N) return;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t N = g.N;
+  const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
   if (fo) {
+    const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+    S f[L::q];
+    gather_f<LAT, S>(fb, N, s, nb, f);
 #pragma unroll
-    for (int i = 0; i < L::q; i++) fo[i * N + s] = DEV ? L::w(i) + double(f[i * N + s]) : double(f[i * N + s]);
+    for (int i = 0; i < L::q; i++) fo[i * N + s] = DEV ? L::w(i) + double(f[i]) : double(f[i]);
   }
   if (qo) {
 #pragma unroll
@@ -61,8 +80,7 @@ __global__ void __launch_bounds__(256) export_derived(const S* __restrict__ fin,
   S F[3];
   body_force<LAT, S>(tau, N, s, nb, F);
   S f[L::q];
-#pragma unroll
-  for (int i = 0; i < L::q; i++) f[i] = fin[i * N + s];
+  gather_f<LAT, S>(fin, N, s, nb, f);
   S rho, u[3];
   moments<LAT, S, DEV>(f, F, rho, u);
   if (which == 0) {
@@ -128,9 +146,10 @@ __global__ void __launch_bounds__(256) observe_partial(const S* __restrict__ fin
     S f[L::q];
     bool bad = false;
     double m = 0, jx = 0, jy = 0, jz = 0;
+    const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+    gather_f<LAT, S>(fin, N, s, nb, f);
 #pragma unroll
     for (int i = 0; i < L::q; i++) {
-      f[i] = fin[i * N + s];
       const double fi = double(f[i]);
       bad |= !isfinite(fi);
       m += fi;
@@ -143,7 +162,6 @@ __global__ void __launch_bounds__(256) observe_partial(const S* __restrict__ fin
     v[2] = jy;
     v[3] = jz;
     if (want_u) {
-      const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
       S F[3], rho, u[3];
       body_force<LAT, S>(tau, N, s, nb, F);
       moments<LAT, S, DEV>(f, F, rho, u);

@@ -31,6 +31,10 @@ struct Lattice<0> {  // D2Q9
   __host__ __device__ static constexpr double w(int i) {
     return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
   }
+  // index of the velocity -c_i
+  __host__ __device__ static constexpr int opp(int i) {
+    return i == 0 ? 0 : (i < 5 ? (i <= 2 ? i + 2 : i - 2) : (i <= 6 ? i + 2 : i - 2));
+  }
 };
 
 template <>
@@ -56,6 +60,8 @@ struct Lattice<1> {  // D3Q19
   __host__ __device__ static constexpr double w(int i) {
     return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
   }
+  // index of the velocity -c_i (pairs are adjacent: odd i pairs with i + 1)
+  __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 };
 
 // ---------------------------------------------------------------------------

@@ -212,10 +212,9 @@ static lc_status compute_tau(lc_ctx* c) {
 
 template <int LAT, typename S, bool DEV>
 static lc_status do_load(lc_ctx* c, const double* f, const double* q) {
-  const int64_t N = c->L.N;
-  const unsigned nb = unsigned((N + 255) / 256);
-  hipLaunchKernelGGL((load_state<LAT, S, DEV>), dim3(nb), dim3(256), 0, c->stream, f, q,
-                     static_cast<S*>(c->b.f[0]), static_cast<S*>(c->b.Q[0]), N);
+  const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
+  hipLaunchKernelGGL((load_state<LAT, S, DEV>), site_grid(c->g), site_block(), 0, c->stream, f, q,
+                     static_cast<S*>(c->b.f[0]), static_cast<S*>(c->b.Q[0]), gd);
   return hip_check(hipGetLastError(), "load launch");
 }
 
@@ -225,9 +224,9 @@ static lc_status do_export(lc_ctx* c, int field, double* dst) {
   const S* f = static_cast<const S*>(c->b.f[c->parity]);
   const S* q = static_cast<const S*>(c->b.Q[c->parity]);
   if (field == LC_FIELD_F || field == LC_FIELD_Q) {
-    const unsigned nb = unsigned((N + 255) / 256);
-    hipLaunchKernelGGL((export_fq<LAT, S, DEV>), dim3(nb), dim3(256), 0, c->stream, f, q,
-                       field == LC_FIELD_F ? dst : nullptr, field == LC_FIELD_Q ? dst : nullptr, N);
+    const GridDims gd{c->g.nx, c->g.ny, c->g.nz, N};
+    hipLaunchKernelGGL((export_fq<LAT, S, DEV>), site_grid(c->g), site_block(), 0, c->stream, f, q,
+                       field == LC_FIELD_F ? dst : nullptr, field == LC_FIELD_Q ? dst : nullptr, gd);
     return hip_check(hipGetLastError(), "export launch");
   }
   int which = field == LC_FIELD_RHO ? 0 : field == LC_FIELD_U ? 1 : field == LC_FIELD_FORCE ? 2 : 3;

@@ -100,6 +100,48 @@ __device__ __forceinline__ void load_region(S* dst, const S* const* src, int x0,
   }
 }
 
+// Register-staged form of load_region for software pipelining: fetch_region
+// issues the global loads of a plane into registers (one iteration ahead),
+// store_region later writes them to an LDS plane.
+template <typename S, int TX, int TY, int NC>
+struct RegionRegs {
+  static constexpr int R2 = (TX + 4) * (TY + 4), NT = TX * TY;
+  static constexpr int P = (R2 + NT - 1) / NT;  // points per thread
+  S v[P][NC];
+};
+
+template <typename S, int TX, int TY, int NC>
+__device__ __forceinline__ void fetch_region(RegionRegs<S, TX, TY, NC>& r, const S* const* src, int x0, int y0,
+                                             int gz, const GridDims& g, int tid) {
+  using RR = RegionRegs<S, TX, TY, NC>;
+  constexpr int W2 = TX + 4;
+  const uint32_t plane = uint32_t(g.nx) * uint32_t(g.ny) * uint32_t(gz);
+#pragma unroll
+  for (int p = 0; p < RR::P; p++) {
+    const int k = tid + p * RR::NT;
+    if (p < RR::P - 1 || k < RR::R2) {
+      const int i = k % W2, j = k / W2;
+      const int gx = wrapi(x0 - 2 + i, g.nx), gy = wrapi(y0 - 2 + j, g.ny);
+      const uint32_t s = plane + uint32_t(gx) + uint32_t(g.nx) * uint32_t(gy);
+#pragma unroll
+      for (int q = 0; q < NC; q++) r.v[p][q] = src[q][s];
+    }
+  }
+}
+
+template <typename S, int TX, int TY, int NC>
+__device__ __forceinline__ void store_region(const RegionRegs<S, TX, TY, NC>& r, S* dst, int tid) {
+  using RR = RegionRegs<S, TX, TY, NC>;
+#pragma unroll
+  for (int p = 0; p < RR::P; p++) {
+    const int k = tid + p * RR::NT;
+    if (p < RR::P - 1 || k < RR::R2) {
+#pragma unroll
+      for (int q = 0; q < NC; q++) dst[q * RR::R2 + k] = r.v[p][q];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sweep 1: stress in LDS, body force, moments, collision, streaming.
 template <int LAT, typename S, bool DEV, int TX, int TY>
@@ -158,8 +200,43 @@ __global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, co
       }
     }
   };
-  // lattice-Boltzmann update of the owner's site in plane z
-  auto lb_site = [&](int z, int ts, const S (&tzp)[3], const S (&tzm)[3]) {
+  // periodic neighbour offsets of the owner's site in plane z (unsigned
+  // arithmetic modulo 2^32 on in-range indices)
+  struct Off {
+    uint32_t s, xp, xm, yp, ym, zp, zm;
+  };
+  auto offsets = [&](int z) {
+    Off o;
+    const uint32_t sy = uint32_t(g.nx), sz = uint32_t(g.nx) * uint32_t(g.ny);
+    o.s = uint32_t(x) + sy * uint32_t(y) + sz * uint32_t(z);
+    o.xp = (x + 1 == g.nx) ? 0u - uint32_t(g.nx - 1) : 1u;
+    o.xm = (x == 0) ? uint32_t(g.nx - 1) : 0u - 1u;
+    o.yp = (y + 1 == g.ny) ? 0u - uint32_t(g.ny - 1) * sy : sy;
+    o.ym = (y == 0) ? uint32_t(g.ny - 1) * sy : 0u - sy;
+    o.zp = (z + 1 == g.nz) ? 0u - uint32_t(g.nz - 1) * sz : sz;
+    o.zm = (z == 0) ? uint32_t(g.nz - 1) * sz : 0u - sz;
+    return o;
+  };
+  // gather the owner's populations of plane z: f_i(x) = buf_i(x - c_i)
+  // (issued one plane ahead and consumed by lb_site)
+  auto fetch_f = [&](int z, S (&f)[L::q]) {
+    if (!own) return;
+    const Off o = offsets(z);
+#pragma unroll
+    for (int i = 0; i < L::q; i++) {
+      uint32_t d = o.s;
+      if (L::cx(i) == 1) d += o.xm;
+      if (L::cx(i) == -1) d += o.xp;
+      if (L::cy(i) == 1) d += o.ym;
+      if (L::cy(i) == -1) d += o.yp;
+      if (L::cz(i) == 1) d += o.zm;
+      if (L::cz(i) == -1) d += o.zp;
+      f[i] = (fin + size_t(i) * size_t(N))[d];
+    }
+  };
+  // lattice-Boltzmann update of the owner's site in plane z; writes the
+  // post-collision populations at the site (pull form)
+  auto lb_site = [&](int z, int ts, const S (&tzp)[3], const S (&tzm)[3], S (&f)[L::q]) {
     if (!own) return;
     const int k1 = (tx + 1) + T::W1 * (ty + 1);
     S F[3] = {S(0), S(0), S(0)};
@@ -169,49 +246,44 @@ __global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, co
       if constexpr (DIM == 3) acc += tzp[a] - tzm[a];
       F[a] = S(0.5) * acc;
     }
-    const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-    S f[L::q];
-#pragma unroll
-    for (int i = 0; i < L::q; i++) f[i] = fin[i * N + s];
+    const uint32_t s = uint32_t(x) + uint32_t(g.nx) * (uint32_t(y) + uint32_t(g.ny) * uint32_t(z));
     S rho, u[3];
     moments<LAT, S, DEV>(f, F, rho, u);
 #pragma unroll
-    for (int a = 0; a < DIM; a++) uout[a * N + s] = u[a];
-    collide<LAT, S, DEV>(f, rho, u, F, c);
-    const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
+    for (int a = 0; a < DIM; a++) (uout + size_t(a) * size_t(N))[s] = u[a];
+    collide_pairs<LAT, S, DEV>(f, rho, u, F, c);
 #pragma unroll
-    for (int i = 0; i < L::q; i++) {
-      int64_t d = s;
-      if (L::cx(i) == 1) d += nb.xp;
-      if (L::cx(i) == -1) d += nb.xm;
-      if (L::cy(i) == 1) d += nb.yp;
-      if (L::cy(i) == -1) d += nb.ym;
-      if (L::cz(i) == 1) d += nb.zp;
-      if (L::cz(i) == -1) d += nb.zm;
-      fout[i * N + d] = f[i];
-    }
+    for (int i = 0; i < L::q; i++) (fout + size_t(i) * size_t(N))[s] = f[i];
   };
 
   if constexpr (DIM == 2) {
     load_region<S, TX, TY, 5>(&sQ[0][0][0], qsrc, x0, y0, 0, g, tid);
     __syncthreads();
-    S tz[3];
+    S tz[3], f[L::q];
+    fetch_f(0, f);
     tau_plane(0, 0, 0, 0, tz);
     __syncthreads();
-    lb_site(0, 0, tz, tz);
+    lb_site(0, 0, tz, tz, f);
   } else {
     const int zb = blockIdx.z * zc;
     const int ze = min(zb + zc, g.nz);
     auto slot = [](int p) { return (p + 3) % 3; };  // p >= -3
+    // software pipeline: the halo region of plane p+2 and the populations of
+    // plane p are in flight while plane p's stress and plane p-1's update run
+    RegionRegs<S, TX, TY, 5> rq;
     load_region<S, TX, TY, 5>(&sQ[slot(zb - 2)][0][0], qsrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
     load_region<S, TX, TY, 5>(&sQ[slot(zb - 1)][0][0], qsrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
+    fetch_region<S, TX, TY, 5>(rq, qsrc, x0, y0, wrapi(zb, g.nz), g, tid);
     S tzA[3] = {S(0), S(0), S(0)}, tzB[3] = {S(0), S(0), S(0)}, tzC[3];
+    S f[L::q];
     for (int p = zb - 1; p <= ze; p++) {
-      load_region<S, TX, TY, 5>(&sQ[slot(p + 1)][0][0], qsrc, x0, y0, wrapi(p + 1, g.nz), g, tid);
+      store_region<S, TX, TY, 5>(rq, &sQ[slot(p + 1)][0][0], tid);
+      if (p + 2 <= ze + 1) fetch_region<S, TX, TY, 5>(rq, qsrc, x0, y0, wrapi(p + 2, g.nz), g, tid);
       __syncthreads();
       tau_plane(slot(p), slot(p + 1), slot(p - 1), p & 1, tzC);
       __syncthreads();
-      if (p - 1 >= zb) lb_site(p - 1, (p - 1) & 1, tzC, tzA);
+      if (p - 1 >= zb) lb_site(p - 1, (p - 1) & 1, tzC, tzA, f);
+      if (p >= zb && p < ze) fetch_f(p, f);
 #pragma unroll
       for (int a = 0; a < 3; a++) {
         tzA[a] = tzB[a];
@@ -344,12 +416,15 @@ __global__ void __launch_bounds__(TX* TY) split_q(const S* __restrict__ Qin, con
     const int zb = blockIdx.z * zc;
     const int ze = min(zb + zc, g.nz);
     auto slot = [](int p) { return (p + 3) % 3; };
+    RegionRegs<S, TX, TY, NC> rq;
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 2)][0][0], csrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 1)][0][0], csrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
+    fetch_region<S, TX, TY, NC>(rq, csrc, x0, y0, wrapi(zb, g.nz), g, tid);
     Stash stB, stC;  // planes p-1 and p
     Sym<S> qpA = sym_zero<S>(), qpB = sym_zero<S>(), qpC;
     for (int p = zb - 1; p <= ze; p++) {
-      load_region<S, TX, TY, NC>(&sQ[slot(p + 1)][0][0], csrc, x0, y0, wrapi(p + 1, g.nz), g, tid);
+      store_region<S, TX, TY, NC>(rq, &sQ[slot(p + 1)][0][0], tid);
+      if (p + 2 <= ze + 1) fetch_region<S, TX, TY, NC>(rq, csrc, x0, y0, wrapi(p + 2, g.nz), g, tid);
       __syncthreads();
       pred_plane(slot(p), slot(p + 1), slot(p - 1), p & 1, stC, qpC);
       __syncthreads();

@@ -118,6 +118,61 @@ __device__ __forceinline__ void collide(S (&f)[Lattice<LAT>::q], S rho, const S 
   }
 }
 
+// The same collision evaluated on pairs of opposite velocities: for c and
+// -c the even parts (in c) of f_eq and of the forcing term are shared and
+// the odd parts change sign.
+template <int LAT, typename S, bool DEV>
+__device__ __forceinline__ void collide_pairs(S (&f)[Lattice<LAT>::q], S rho, const S (&u)[3], const S (&F)[3],
+                                              const Coef<S>& c) {
+  using L = Lattice<LAT>;
+  const S uu15 = S(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const S uF3 = S(3) * (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]);
+  const S base = DEV ? rho - S(1) : rho;
+  const S keep = S(1) - c.omega;
+  const S om_rho = c.omega * rho;
+  // rest population: c = 0
+  {
+    const S w = S(L::w(0));
+    const S feq = w * (base - rho * uu15);
+    f[0] = keep * f[0] + c.omega * feq - w * c.src * uF3;
+  }
+#pragma unroll
+  for (int i = 1; i < L::q; i++) {
+    if (L::opp(i) < i) continue;
+    const int j = L::opp(i);
+    const S w = S(L::w(i));
+    const S cu = S(L::cx(i)) * u[0] + S(L::cy(i)) * u[1] + S(L::cz(i)) * u[2];
+    const S cF = S(L::cx(i)) * F[0] + S(L::cy(i)) * F[1] + S(L::cz(i)) * F[2];
+    const S even = w * (c.omega * base + om_rho * (S(4.5) * cu * cu - uu15) + c.src * (S(9) * cF * cu - uF3));
+    const S odd = w * S(3) * (om_rho * cu + c.src * cF);
+    const S fi = f[i], fj = f[j];
+    f[i] = keep * fi + even + odd;
+    f[j] = keep * fj + even - odd;
+  }
+}
+
+// Storage convention of the population buffers ("pull" form): the buffer
+// of step n holds at site y the post-collision values of step n-1 before
+// streaming, so the populations at x are f_i(x) = buf_i(x - c_i).  Kernels
+// gather on read and write their post-collision values at their own site,
+// which keeps every store aligned and whole.
+template <int LAT, typename S>
+__device__ __forceinline__ void gather_f(const S* __restrict__ buf, int64_t N, int64_t s, const Nbr& nb,
+                                         S (&f)[Lattice<LAT>::q]) {
+  using L = Lattice<LAT>;
+#pragma unroll
+  for (int i = 0; i < L::q; i++) {
+    int64_t d = s;
+    if (L::cx(i) == 1) d += nb.xm;
+    if (L::cx(i) == -1) d += nb.xp;
+    if (L::cy(i) == 1) d += nb.ym;
+    if (L::cy(i) == -1) d += nb.yp;
+    if (L::cz(i) == 1) d += nb.zm;
+    if (L::cz(i) == -1) d += nb.zp;
+    f[i] = buf[i * N + d];
+  }
+}
+
 template <int LAT, typename S, bool DEV>
 __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const S* __restrict__ tau,
                                                 S* __restrict__ fout, S* __restrict__ uout,
@@ -133,24 +188,14 @@ __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const
   S F[3];
   body_force<LAT, S>(tau, N, s, nb, F);
   S f[L::q];
-#pragma unroll
-  for (int i = 0; i < L::q; i++) f[i] = fin[i * N + s];
+  gather_f<LAT, S>(fin, N, s, nb, f);
   S rho, u[3];
   moments<LAT, S, DEV>(f, F, rho, u);
 #pragma unroll
   for (int a = 0; a < L::dim; a++) uout[a * N + s] = u[a];
   collide<LAT, S, DEV>(f, rho, u, F, c);
 #pragma unroll
-  for (int i = 0; i < L::q; i++) {
-    int64_t d = s;
-    if (L::cx(i) == 1) d += nb.xp;
-    if (L::cx(i) == -1) d += nb.xm;
-    if (L::cy(i) == 1) d += nb.yp;
-    if (L::cy(i) == -1) d += nb.ym;
-    if (L::cz(i) == 1) d += nb.zp;
-    if (L::cz(i) == -1) d += nb.zm;
-    fout[i * N + d] = f[i];
-  }
+  for (int i = 0; i < L::q; i++) fout[i * N + s] = f[i];
 }
 
 // Velocity gradient G[a][b] = d_b u_a (central differences).
