@@ -160,6 +160,11 @@ lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
  * build provides for this grid.  LC_EUNSUPPORTED if not available. */
 lc_status lc_set_variant(lc_ctx *ctx, int32_t variant);
 
+/* Planes each block marches through along z in the two-sweep kernels
+ * (>= 1; larger chunks recompute fewer boundary planes, smaller chunks give
+ * more blocks).  0 restores the built-in default.  Ignored by 2D grids. */
+lc_status lc_set_chunk(lc_ctx *ctx, int32_t planes);
+
 /* Load the state from device arrays of double logical values: f_dev (q*N)
  * and Q_dev (5*N).  f_dev == NULL loads the fluid at rest with rho = 1,
  * f_i = w_i (the initial condition of Sec. 2).  Resets the step counter.

@@ -130,6 +130,7 @@ struct lc_ctx {
   int64_t step;
   bool loaded;
   int variant;
+  int zchunk;  // 0: default
 };
 
 // ---------------------------------------------------------------------------
@@ -166,7 +167,11 @@ struct SplitCfg {
   static constexpr bool f64 = sizeof(S) == 8;
   static constexpr int LB_TX = 32, LB_TY = (d3 && f64) ? 4 : 8;
   static constexpr int Q_TX = (d3 && f64) ? 16 : 32, Q_TY = 8;
-  static constexpr int ZC = 32;
+  static constexpr int ZC = f64 ? 32 : 128;  // measured best on 256^3
+  // waves per SIMD the register allocation is held to (LDS allows 4 blocks
+  // of the single-precision 3D stress sweep per CU)
+  static constexpr int LB_WPE = (d3 && !f64) ? 4 : 1;
+  static constexpr int Q_WPE = 1;
 };
 
 template <int LAT, typename S, bool DEV>
@@ -175,7 +180,7 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = make_coef<S>(c->p);
   S* u = reinterpret_cast<S*>(static_cast<char*>(c->b.scratch) + c->L.off_u);
-  const int zc = C::d3 ? C::ZC : 1;
+  const int zc = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC) : 1;
   const unsigned gz = unsigned((c->g.nz + zc - 1) / zc);
   const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY, gz);
   const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY, gz);
@@ -184,9 +189,9 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
     S* f1 = static_cast<S*>(c->b.f[c->parity ^ 1]);
     const S* q0 = static_cast<const S*>(c->b.Q[c->parity]);
     S* q1 = static_cast<S*>(c->b.Q[c->parity ^ 1]);
-    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY>), g1, dim3(C::LB_TX, C::LB_TY), 0, c->stream, q0,
+    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, c->stream, q0,
                        f0, f1, u, gd, k, zc);
-    hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u, q1, gd,
+    hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u, q1, gd,
                        k, zc);
     c->parity ^= 1;
     c->step++;
@@ -344,6 +349,7 @@ lc_status lc_init(const lc_grid* grid, const lc_params* params, const lc_buffers
   c->step = 0;
   c->loaded = false;
   c->variant = LC_VARIANT_SPLIT;
+  c->zchunk = 0;
   *out = c;
   return LC_OK;
 }
@@ -370,6 +376,14 @@ lc_status lc_set_variant(lc_ctx* c, int32_t variant) {
   }
   if (variant == LC_VARIANT_FUSED) return fail(LC_EUNSUPPORTED, "variant %d not available", variant);
   return fail(LC_EINVAL, "unknown variant %d", variant);
+}
+
+lc_status lc_set_chunk(lc_ctx* c, int32_t planes) {
+  clear_error();
+  if (!c) return fail(LC_EINVAL, "ctx is NULL");
+  if (planes < 0) return fail(LC_EINVAL, "planes must be >= 0");
+  c->zchunk = planes;
+  return LC_OK;
 }
 
 lc_status lc_load_state(lc_ctx* c, const double* f_dev, const double* q_dev) {

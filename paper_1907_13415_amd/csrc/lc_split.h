@@ -144,8 +144,8 @@ __device__ __forceinline__ void store_region(const RegionRegs<S, TX, TY, NC>& r,
 
 // ---------------------------------------------------------------------------
 // Sweep 1: stress in LDS, body force, moments, collision, streaming.
-template <int LAT, typename S, bool DEV, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, const S* __restrict__ fin,
+template <int LAT, typename S, bool DEV, int TX, int TY, int WPE>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) split_lb(const S* __restrict__ Qin, const S* __restrict__ fin,
                                                    S* __restrict__ fout, S* __restrict__ uout, GridDims g,
                                                    Coef<S> c, int zc) {
   using L = Lattice<LAT>;
@@ -153,9 +153,12 @@ __global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, co
   constexpr int DIM = L::dim;
   constexpr int NQP = DIM == 3 ? 3 : 1;  // Q planes held
   constexpr int NTP = DIM == 3 ? 2 : 1;  // stress planes held
-  constexpr int NTC = 2 * DIM;           // tau_{a x} and tau_{a y}, a < DIM
+  // tau_{a x} is needed at x +- 1 (rows 1..TY of the R1 region, all
+  // columns) and tau_{a y} at y +- 1 (columns 1..TX, all rows)
+  constexpr int NXA = T::W1 * TY, NYA = TX * T::H1;
   __shared__ S sQ[NQP][5][T::R2];
-  __shared__ S sT[NTP][NTC][T::R1];
+  __shared__ S sTx[NTP][DIM][NXA];
+  __shared__ S sTy[NTP][DIM][NYA];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
@@ -178,11 +181,11 @@ __global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, co
       S t[3][3];
       const int i = tx + 1, j = ty + 1;
       tau_point(m, zp, zm, i, j, t);
-      const int k1 = i + T::W1 * j;
+      const int kx = i + T::W1 * (j - 1), ky = (i - 1) + TX * j;
 #pragma unroll
       for (int a = 0; a < DIM; a++) {
-        sT[ts][a][k1] = t[a][0];
-        sT[ts][DIM + a][k1] = t[a][1];
+        sTx[ts][a][kx] = t[a][0];
+        sTy[ts][a][ky] = t[a][1];
       }
 #pragma unroll
       for (int a = 0; a < 3; a++) tz[a] = t[a][2];
@@ -192,11 +195,14 @@ __global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, co
       int i, j;
       T::ring(tid, i, j);
       tau_point(m, zp, zm, i, j, t);
-      const int k1 = i + T::W1 * j;
+      if (j == 0 || j == TY + 1) {  // top and bottom rows feed d/dy
+        const int ky = (i - 1) + TX * j;
 #pragma unroll
-      for (int a = 0; a < DIM; a++) {
-        sT[ts][a][k1] = t[a][0];
-        sT[ts][DIM + a][k1] = t[a][1];
+        for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
+      } else {  // left and right columns feed d/dx
+        const int kx = i + T::W1 * (j - 1);
+#pragma unroll
+        for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = t[a][0];
       }
     }
   };
@@ -238,11 +244,11 @@ __global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, co
   // post-collision populations at the site (pull form)
   auto lb_site = [&](int z, int ts, const S (&tzp)[3], const S (&tzm)[3], S (&f)[L::q]) {
     if (!own) return;
-    const int k1 = (tx + 1) + T::W1 * (ty + 1);
+    const int kx = (tx + 1) + T::W1 * ty, ky = tx + TX * (ty + 1);
     S F[3] = {S(0), S(0), S(0)};
 #pragma unroll
     for (int a = 0; a < DIM; a++) {
-      S acc = (sT[ts][a][k1 + 1] - sT[ts][a][k1 - 1]) + (sT[ts][DIM + a][k1 + T::W1] - sT[ts][DIM + a][k1 - T::W1]);
+      S acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + TX] - sTy[ts][a][ky - TX]);
       if constexpr (DIM == 3) acc += tzp[a] - tzm[a];
       F[a] = S(0.5) * acc;
     }
@@ -295,8 +301,8 @@ __global__ void __launch_bounds__(TX* TY) split_lb(const S* __restrict__ Qin, co
 
 // ---------------------------------------------------------------------------
 // Sweep 2: predictor on tile + ring (LDS), corrector on the tile.
-template <int LAT, typename S, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) split_q(const S* __restrict__ Qin, const S* __restrict__ uin,
+template <int LAT, typename S, int TX, int TY, int WPE>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) split_q(const S* __restrict__ Qin, const S* __restrict__ uin,
                                                   S* __restrict__ Qout, GridDims g, Coef<S> c, int zc) {
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;

@@ -66,6 +66,7 @@ def _load():
         "lc_init": ([P(lc_grid), P(lc_params), P(lc_buffers), ctypes.c_void_p, P(ctypes.c_void_p)], ctypes.c_int32),
         "lc_set_params": ([ctypes.c_void_p, P(lc_params)], ctypes.c_int32),
         "lc_set_variant": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+        "lc_set_chunk": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
         "lc_load_state": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
         "lc_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
         "lc_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
@@ -133,6 +134,10 @@ def lc_set_params(ctx, params):
 
 def lc_set_variant(ctx, variant):
     _check(_lib.lc_set_variant(ctx, variant))
+
+
+def lc_set_chunk(ctx, planes):
+    _check(_lib.lc_set_chunk(ctx, int(planes)))
 
 
 def lc_load_state(ctx, f_ptr, q_ptr):
@@ -215,6 +220,9 @@ class Solver:
 
     def set_variant(self, v):
         lc_set_variant(self.ctx, v)
+
+    def set_chunk(self, planes):
+        lc_set_chunk(self.ctx, planes)
 
     def set_params(self, params):
         self.params = make_params(*params)
