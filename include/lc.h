@@ -193,6 +193,59 @@ int64_t lc_step_count(const lc_ctx *ctx);
 /* Destroy the context (device buffers stay with the caller). */
 lc_status lc_free(lc_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent two-dimensional D2Q9 grids of their own
+ * sizes and parameters (for example a temperature sweep in gamma around the
+ * coexistence value of Sec. 2.1) advanced together.  All grids share one
+ * storage precision.  The grids' fields live in caller-owned arenas: grid k
+ * occupies f_offsets[k] bytes into each f arena (9*N_k values) and
+ * q_offsets[k] bytes into each Q arena (5*N_k values), in the single-grid
+ * layout.  A step of the batch is two kernel launches covering the tiles of
+ * every grid; runs of steps are captured once in a HIP graph (64 steps per
+ * graph) and replayed on the batch stream.
+ * ------------------------------------------------------------------------- */
+
+/* Arena sizes and per-grid byte offsets (f_offsets, q_offsets: ngrids
+ * entries each, may be NULL). */
+lc_status lc_batch_layout(int32_t ngrids, const lc_grid *grids, size_t *f_bytes, size_t *q_bytes,
+                          size_t *scratch_bytes, size_t *f_offsets, size_t *q_offsets);
+
+/* Create a batch over caller-owned arenas (arena->f[0..1], arena->Q[0..1],
+ * arena->scratch sized by lc_batch_layout, 256-byte aligned).  params has
+ * ngrids entries, each validated as in lc_init.  Synchronises the stream
+ * once (descriptor upload). */
+lc_status lc_batch_init(int32_t ngrids, const lc_grid *grids, const lc_params *params,
+                        const lc_buffers *arena, void *stream, lc_batch **out);
+
+/* Load grid k (same conventions as lc_load_state).  Every grid must be
+ * loaded before the batch steps; loading after steps were taken resets the
+ * batch, and every grid must then be loaded again. */
+lc_status lc_batch_load_state(lc_batch *b, int32_t k, const double *f_dev, const double *Q_dev);
+
+/* Enqueue n >= 0 steps of every grid (asynchronous; graph replays for
+ * whole runs of 64 steps, direct launches for the rest). */
+lc_status lc_batch_step(lc_batch *b, int64_t n);
+
+/* Select the tile shape (0: 32x8, 1: 64x4, 2: 16x16 sites per block).
+ * Results do not depend on the tile shape. */
+lc_status lc_batch_set_tile(lc_batch *b, int32_t variant);
+
+/* Time every tile shape for trial_steps steps (after one untimed step) with
+ * HIP events and keep the fastest.  The state advances by
+ * 3 * (trial_steps + 1) steps: tune before loading the real state, or load
+ * it again afterwards.  Synchronises the stream. */
+lc_status lc_batch_autotune(lc_batch *b, int32_t trial_steps, int32_t *chosen, double *ms_per_step);
+
+/* Observables of every grid: out has ngrids entries.  Synchronises. */
+lc_status lc_batch_observe(lc_batch *b, uint32_t mask, int32_t half_axis, lc_observables *out);
+
+/* Export a field of grid k (as lc_export). */
+lc_status lc_batch_export(lc_batch *b, int32_t k, int32_t field, double *dst_dev);
+
+/* Destroy the batch (graphs and its capture stream; arenas stay with the
+ * caller). */
+lc_status lc_batch_free(lc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,56 @@
+// lc_batch.h -- many independent two-dimensional grids in one launch.
+//
+// Each grid has its own size and parameters (for a temperature sweep each
+// grid carries its own gamma).  The grids' fields are packed into shared
+// arenas; a descriptor table gives every grid's size, arena offsets and
+// coefficients, and a tile table maps each block of a launch to its grid.
+// One launch of each sweep covers the tiles of all grids, so a time step of
+// the whole batch is two launches, and a run of steps is captured once in a
+// HIP graph and replayed.
+#pragma once
+
+#include "lc_split.h"
+
+namespace lc {
+
+template <typename S>
+struct BatchDesc {
+  int nx, ny;
+  int64_t N;
+  int64_t f_off, q_off, u_off;  // element offsets into the arenas
+  int tile0, tiles_x;           // first block of this grid, tiles along x
+  Coef<S> c;
+};
+
+template <int LAT, typename S, bool DEV, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    batch_lb(const BatchDesc<S>* __restrict__ desc, const int* __restrict__ tile_grid, const S* __restrict__ Qa,
+             const S* __restrict__ fa, S* __restrict__ fb, S* __restrict__ ua) {
+  const int b = blockIdx.x;
+  const int k = tile_grid[b];
+  const BatchDesc<S> d = desc[k];
+  const int t = b - d.tile0;
+  const GridDims g{d.nx, d.ny, 1, d.N};
+  split_lb_body<LAT, S, DEV, TX, TY>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g, d.c, 1,
+                                     t % d.tiles_x, t / d.tiles_x, 0);
+}
+
+template <int LAT, typename S, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    batch_q(const BatchDesc<S>* __restrict__ desc, const int* __restrict__ tile_grid, const S* __restrict__ Qa,
+            const S* __restrict__ ua, S* __restrict__ Qb) {
+  const int b = blockIdx.x;
+  const int k = tile_grid[b];
+  const BatchDesc<S> d = desc[k];
+  const int t = b - d.tile0;
+  const GridDims g{d.nx, d.ny, 1, d.N};
+  split_q_body<LAT, S, TX, TY>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.c, 1, t % d.tiles_x,
+                               t / d.tiles_x, 0);
+}
+
+// Tile shapes the batch can run with (chosen by lc_batch_autotune).
+constexpr int BATCH_NV = 3;
+__host__ __device__ constexpr int batch_tx(int v) { return v == 0 ? 32 : (v == 1 ? 64 : 16); }
+__host__ __device__ constexpr int batch_ty(int v) { return v == 0 ? 8 : (v == 1 ? 4 : 16); }
+
+}  // namespace lc

@@ -11,6 +11,9 @@
 #include "../../include/lc.h"
 #include "lc_aux.h"
 #include "lc_split.h"
+#include "lc_batch.h"
+
+#include <vector>
 #include "lc_runtime.h"
 
 namespace lc {
@@ -246,8 +249,10 @@ static lc_status do_export(lc_ctx* c, int field, double* dst) {
   return hip_check(hipGetLastError(), "export launch");
 }
 
+// Reductions of the current state into OBS_W doubles at res (device),
+// enqueued on the context stream.
 template <int LAT, typename S, bool DEV>
-static lc_status do_observe(lc_ctx* c, uint32_t mask, int half_axis, double* host8) {
+static lc_status do_observe_async(lc_ctx* c, uint32_t mask, int half_axis, double* res) {
   const int want_u = (mask & LC_OBS_UMAX) ? 1 : 0;
   if (want_u) {
     lc_status st = compute_tau<LAT, S, DEV>(c);
@@ -257,17 +262,40 @@ static lc_status do_observe(lc_ctx* c, uint32_t mask, int half_axis, double* hos
   char* scr = static_cast<char*>(c->b.scratch);
   const S* tau = reinterpret_cast<const S*>(scr + c->L.off_tau);
   double* partial = reinterpret_cast<double*>(scr + c->L.off_partial);
-  double* res = reinterpret_cast<double*>(scr + c->L.off_obs);
   hipLaunchKernelGGL((observe_partial<LAT, S, DEV>), site_grid(c->g), site_block(), 0, c->stream,
                      static_cast<const S*>(c->b.f[c->parity]), static_cast<const S*>(c->b.Q[c->parity]), tau,
                      partial, gd, half_axis, want_u);
   hipLaunchKernelGGL(observe_final, dim3(1), dim3(256), 0, c->stream, partial, c->L.nblocks, res);
-  lc_status st = hip_check(hipGetLastError(), "observe launch");
+  return hip_check(hipGetLastError(), "observe launch");
+}
+
+template <int LAT, typename S, bool DEV>
+static lc_status do_observe(lc_ctx* c, uint32_t mask, int half_axis, double* host8) {
+  double* res = reinterpret_cast<double*>(static_cast<char*>(c->b.scratch) + c->L.off_obs);
+  lc_status st = do_observe_async<LAT, S, DEV>(c, mask, half_axis, res);
   if (st) return st;
   st = hip_check(hipMemcpyAsync(host8, res, OBS_W * sizeof(double), hipMemcpyDeviceToHost, c->stream),
                  "observe copy");
   if (st) return st;
   return hip_check(hipStreamSynchronize(c->stream), "observe sync");
+}
+
+static void fill_observables(const double* h, uint32_t mask, int half_axis, int64_t step, lc_observables* out) {
+  std::memset(out, 0, sizeof *out);
+  if (mask & LC_OBS_MASS) out->mass = h[0];
+  if (mask & LC_OBS_MOM) {
+    out->mom[0] = h[1];
+    out->mom[1] = h[2];
+    out->mom[2] = h[3];
+  }
+  if (mask & LC_OBS_UMAX) out->umax = h[4];
+  if (mask & LC_OBS_S) {
+    out->ssum = h[5];
+    out->ssum_half = h[6];
+  }
+  out->step = step;
+  out->half_axis = half_axis;
+  out->nonfinite = h[7] != 0.0 ? 1 : 0;
 }
 
 #define LC_DISPATCH(ctx, FN, ...)                                                   \
@@ -414,21 +442,7 @@ lc_status lc_observe(lc_ctx* c, uint32_t mask, int32_t half_axis, lc_observables
   double h[OBS_W];
   lc_status st = LC_DISPATCH(c, do_observe, mask, half_axis, h);
   if (st) return st;
-  std::memset(out, 0, sizeof *out);
-  if (mask & LC_OBS_MASS) out->mass = h[0];
-  if (mask & LC_OBS_MOM) {
-    out->mom[0] = h[1];
-    out->mom[1] = h[2];
-    out->mom[2] = h[3];
-  }
-  if (mask & LC_OBS_UMAX) out->umax = h[4];
-  if (mask & LC_OBS_S) {
-    out->ssum = h[5];
-    out->ssum_half = h[6];
-  }
-  out->step = c->step;
-  out->half_axis = half_axis;
-  out->nonfinite = h[7] != 0.0 ? 1 : 0;
+  fill_observables(h, mask, half_axis, c->step, out);
   if (out->nonfinite) return fail(LC_ENONFINITE, "state holds NaN or Inf at step %lld", (long long)c->step);
   return LC_OK;
 }
@@ -452,6 +466,467 @@ int64_t lc_step_count(const lc_ctx* c) { return c ? c->step : -1; }
 lc_status lc_free(lc_ctx* c) {
   clear_error();
   delete c;
+  return LC_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form.
+// ===========================================================================
+namespace lc {
+
+struct BatchLayout {
+  std::vector<size_t> f_off, q_off, u_off;  // byte offsets into the arenas / scratch u region
+  size_t f_bytes = 0, q_bytes = 0;
+  size_t off_desc = 0, off_map[BATCH_NV] = {0, 0, 0}, off_u = 0, off_view = 0, off_res = 0;
+  size_t scratch_bytes = 0;
+  int tiles[BATCH_NV] = {0, 0, 0};
+  std::vector<int> tile0[BATCH_NV], tiles_x[BATCH_NV];
+};
+
+static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B) {
+  if (n < 1 || !grids) return fail(LC_EINVAL, "need at least one grid");
+  for (int k = 0; k < n; k++) {
+    lc_status st = check_grid(&grids[k]);
+    if (st) return st;
+    if (grids[k].lattice != LC_D2Q9) return fail(LC_EUNSUPPORTED, "the batched form runs D2Q9 grids");
+    if (grids[k].precision != grids[0].precision) return fail(LC_EINVAL, "all grids must share one precision");
+  }
+  auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t es = grids[0].precision == LC_FP64 ? 8 : 4;
+  B.f_off.resize(n);
+  B.q_off.resize(n);
+  B.u_off.resize(n);
+  size_t fo = 0, qo = 0, uo = 0, view = 0;
+  for (int v = 0; v < BATCH_NV; v++) {
+    B.tile0[v].resize(n);
+    B.tiles_x[v].resize(n);
+    B.tiles[v] = 0;
+  }
+  for (int k = 0; k < n; k++) {
+    const size_t N = size_t(grids[k].nx) * grids[k].ny;
+    B.f_off[k] = fo;
+    fo = up(fo + 9 * N * es);
+    B.q_off[k] = qo;
+    qo = up(qo + 5 * N * es);
+    B.u_off[k] = uo;
+    uo = up(uo + 2 * N * es);
+    view = std::max(view, layout_of(grids[k]).scratch_bytes);
+    for (int v = 0; v < BATCH_NV; v++) {
+      const int tx = batch_tx(v), ty = batch_ty(v);
+      const int ntx = (grids[k].nx + tx - 1) / tx, nty = (grids[k].ny + ty - 1) / ty;
+      B.tile0[v][k] = B.tiles[v];
+      B.tiles_x[v][k] = ntx;
+      B.tiles[v] += ntx * nty;
+    }
+  }
+  B.f_bytes = fo;
+  B.q_bytes = qo;
+  size_t off = 0;
+  B.off_desc = off;
+  off = up(off + size_t(n) * sizeof(BatchDesc<double>));
+  for (int v = 0; v < BATCH_NV; v++) {
+    B.off_map[v] = off;
+    off = up(off + size_t(B.tiles[v]) * sizeof(int));
+  }
+  B.off_res = off;
+  off = up(off + size_t(n) * OBS_W * sizeof(double));
+  B.off_u = off;
+  off = up(off + uo);
+  B.off_view = off;
+  off = up(off + view);
+  B.scratch_bytes = off;
+  return LC_OK;
+}
+
+}  // namespace lc
+
+struct lc_batch {
+  int n;
+  std::vector<lc_grid> grids;
+  std::vector<lc_params> params;
+  lc_buffers arena;
+  hipStream_t stream;
+  hipStream_t cap;  // private stream used only to capture graphs
+  BatchLayout B;
+  std::vector<lc_ctx> views;  // single-grid contexts over the arenas
+  std::vector<char> host_desc;
+  std::vector<int> host_map[BATCH_NV];
+  int variant;
+  int parity;
+  int64_t step;
+  bool loaded;
+  static constexpr int G = 64;  // steps per captured graph (even)
+  hipGraphExec_t exec[2];
+  hipGraph_t graph[2];
+};
+
+namespace lc {
+
+template <typename S>
+static void batch_fill_desc(lc_batch* b) {
+  b->host_desc.assign(size_t(b->n) * sizeof(BatchDesc<S>), 0);
+  BatchDesc<S>* d = reinterpret_cast<BatchDesc<S>*>(b->host_desc.data());
+  const size_t es = sizeof(S);
+  for (int k = 0; k < b->n; k++) {
+    d[k].nx = b->grids[k].nx;
+    d[k].ny = b->grids[k].ny;
+    d[k].N = int64_t(b->grids[k].nx) * b->grids[k].ny;
+    d[k].f_off = int64_t(b->B.f_off[k] / es);
+    d[k].q_off = int64_t(b->B.q_off[k] / es);
+    d[k].u_off = int64_t(b->B.u_off[k] / es);
+    d[k].tile0 = b->B.tile0[b->variant][k];
+    d[k].tiles_x = b->B.tiles_x[b->variant][k];
+    d[k].c = make_coef<S>(b->params[k]);
+  }
+}
+
+// Upload the descriptor table for the current variant (asynchronous; the
+// host copy lives in the batch object).
+static lc_status batch_upload(lc_batch* b) {
+  if (b->grids[0].precision == LC_FP64)
+    batch_fill_desc<double>(b);
+  else
+    batch_fill_desc<float>(b);
+  char* scr = static_cast<char*>(b->arena.scratch);
+  return hip_check(hipMemcpyAsync(scr + b->B.off_desc, b->host_desc.data(), b->host_desc.size(),
+                                  hipMemcpyHostToDevice, b->stream),
+                   "batch descriptor upload");
+}
+
+template <typename S, bool DEV, int V>
+static void batch_launch_v(lc_batch* b, hipStream_t st, int parity) {
+  constexpr int TX = batch_tx(V), TY = batch_ty(V);
+  char* scr = static_cast<char*>(b->arena.scratch);
+  const BatchDesc<S>* desc = reinterpret_cast<const BatchDesc<S>*>(scr + b->B.off_desc);
+  const int* map = reinterpret_cast<const int*>(scr + b->B.off_map[V]);
+  S* u = reinterpret_cast<S*>(scr + b->B.off_u);
+  const S* f0 = static_cast<const S*>(b->arena.f[parity]);
+  S* f1 = static_cast<S*>(b->arena.f[parity ^ 1]);
+  const S* q0 = static_cast<const S*>(b->arena.Q[parity]);
+  S* q1 = static_cast<S*>(b->arena.Q[parity ^ 1]);
+  const unsigned nt = unsigned(b->B.tiles[V]);
+  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY>), dim3(nt), dim3(TX, TY), 0, st, desc, map, q0, f0, f1, u);
+  hipLaunchKernelGGL((batch_q<0, S, TX, TY>), dim3(nt), dim3(TX, TY), 0, st, desc, map, q0, u, q1);
+}
+
+template <typename S, bool DEV>
+static void batch_launch(lc_batch* b, hipStream_t st, int parity) {
+  if (b->variant == 0)
+    batch_launch_v<S, DEV, 0>(b, st, parity);
+  else if (b->variant == 1)
+    batch_launch_v<S, DEV, 1>(b, st, parity);
+  else
+    batch_launch_v<S, DEV, 2>(b, st, parity);
+}
+
+static void batch_launch_step(lc_batch* b, hipStream_t st, int parity) {
+  if (b->grids[0].precision == LC_FP64)
+    batch_launch<double, false>(b, st, parity);
+  else
+    batch_launch<float, true>(b, st, parity);
+}
+
+static void batch_drop_graphs(lc_batch* b) {
+  for (int p = 0; p < 2; p++) {
+    if (b->exec[p]) hipGraphExecDestroy(b->exec[p]);
+    if (b->graph[p]) hipGraphDestroy(b->graph[p]);
+    b->exec[p] = nullptr;
+    b->graph[p] = nullptr;
+  }
+}
+
+// Capture G steps starting from `parity` on the private stream.
+static lc_status batch_build_graph(lc_batch* b, int parity) {
+  lc_status st = hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "graph capture begin");
+  if (st) return st;
+  int p = parity;
+  for (int i = 0; i < lc_batch::G; i++) {
+    batch_launch_step(b, b->cap, p);
+    p ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  st = hip_check(hipStreamEndCapture(b->cap, &g), "graph capture end");
+  if (st) return st;
+  hipGraphExec_t e = nullptr;
+  st = hip_check(hipGraphInstantiate(&e, g, nullptr, nullptr, 0), "graph instantiate");
+  if (st) {
+    hipGraphDestroy(g);
+    return st;
+  }
+  b->graph[parity] = g;
+  b->exec[parity] = e;
+  return LC_OK;
+}
+
+static void batch_sync_views(lc_batch* b) {
+  for (auto& v : b->views) {
+    v.parity = b->parity;
+    v.step = b->step;
+  }
+}
+
+}  // namespace lc
+
+extern "C" {
+
+lc_status lc_batch_layout(int32_t ngrids, const lc_grid* grids, size_t* f_bytes, size_t* q_bytes,
+                          size_t* scratch_bytes, size_t* f_offsets, size_t* q_offsets) {
+  clear_error();
+  BatchLayout B;
+  lc_status st = batch_layout_of(ngrids, grids, B);
+  if (st) return st;
+  if (f_bytes) *f_bytes = B.f_bytes;
+  if (q_bytes) *q_bytes = B.q_bytes;
+  if (scratch_bytes) *scratch_bytes = B.scratch_bytes;
+  for (int k = 0; k < ngrids; k++) {
+    if (f_offsets) f_offsets[k] = B.f_off[k];
+    if (q_offsets) q_offsets[k] = B.q_off[k];
+  }
+  return LC_OK;
+}
+
+lc_status lc_batch_init(int32_t ngrids, const lc_grid* grids, const lc_params* params, const lc_buffers* arena,
+                        void* stream, lc_batch** out) {
+  clear_error();
+  if (!out) return fail(LC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!params || !arena) return fail(LC_EINVAL, "NULL argument");
+  BatchLayout B;
+  lc_status st = batch_layout_of(ngrids, grids, B);
+  if (st) return st;
+  for (int k = 0; k < ngrids; k++) {
+    st = check_params(&params[k]);
+    if (st) return st;
+  }
+  const void* ptrs[5] = {arena->f[0], arena->f[1], arena->Q[0], arena->Q[1], arena->scratch};
+  for (const void* p : ptrs) {
+    if (!p) return fail(LC_EINVAL, "an arena pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(p) & 255) return fail(LC_EINVAL, "arenas must be 256-byte aligned");
+  }
+  lc_batch* b = new (std::nothrow) lc_batch;
+  if (!b) return fail(LC_ENOMEM, "batch allocation failed");
+  b->n = ngrids;
+  b->grids.assign(grids, grids + ngrids);
+  b->params.assign(params, params + ngrids);
+  b->arena = *arena;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->B = B;
+  b->variant = 0;
+  b->parity = 0;
+  b->step = 0;
+  b->loaded = false;
+  for (int p = 0; p < 2; p++) {
+    b->exec[p] = nullptr;
+    b->graph[p] = nullptr;
+  }
+  st = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
+  if (st) {
+    delete b;
+    return st;
+  }
+  char* scr = static_cast<char*>(arena->scratch);
+  const size_t es = grids[0].precision == LC_FP64 ? 8 : 4;
+  b->views.resize(ngrids);
+  for (int k = 0; k < ngrids; k++) {
+    lc_ctx& v = b->views[k];
+    v.g = grids[k];
+    v.p = params[k];
+    v.b.f[0] = static_cast<char*>(arena->f[0]) + B.f_off[k];
+    v.b.f[1] = static_cast<char*>(arena->f[1]) + B.f_off[k];
+    v.b.Q[0] = static_cast<char*>(arena->Q[0]) + B.q_off[k];
+    v.b.Q[1] = static_cast<char*>(arena->Q[1]) + B.q_off[k];
+    v.b.scratch = scr + B.off_view;
+    v.stream = b->stream;
+    v.L = layout_of(grids[k]);
+    v.parity = 0;
+    v.step = 0;
+    v.loaded = false;
+    v.variant = LC_VARIANT_SPLIT;
+    v.zchunk = 0;
+    (void)es;
+  }
+  // tile -> grid maps for every tile shape
+  for (int vv = 0; vv < BATCH_NV; vv++) {
+    b->host_map[vv].resize(B.tiles[vv]);
+    for (int k = 0; k < ngrids; k++) {
+      const int t0 = B.tile0[vv][k];
+      const int t1 = k + 1 < ngrids ? B.tile0[vv][k + 1] : B.tiles[vv];
+      for (int t = t0; t < t1; t++) b->host_map[vv][t] = k;
+    }
+    st = hip_check(hipMemcpyAsync(scr + B.off_map[vv], b->host_map[vv].data(), b->host_map[vv].size() * sizeof(int),
+                                  hipMemcpyHostToDevice, b->stream),
+                   "tile map upload");
+    if (st) {
+      hipStreamDestroy(b->cap);
+      delete b;
+      return st;
+    }
+  }
+  st = batch_upload(b);
+  if (st) {
+    hipStreamDestroy(b->cap);
+    delete b;
+    return st;
+  }
+  // the host tables must stay valid until the uploads have run
+  st = hip_check(hipStreamSynchronize(b->stream), "batch init sync");
+  if (st) {
+    hipStreamDestroy(b->cap);
+    delete b;
+    return st;
+  }
+  *out = b;
+  return LC_OK;
+}
+
+lc_status lc_batch_load_state(lc_batch* b, int32_t k, const double* f_dev, const double* q_dev) {
+  clear_error();
+  if (!b) return fail(LC_EINVAL, "batch is NULL");
+  if (k < 0 || k >= b->n) return fail(LC_EINVAL, "grid index out of range");
+  if (!q_dev) return fail(LC_EINVAL, "Q_dev is NULL");
+  // every grid of the batch shares one parity and step counter
+  if (b->parity != 0 || b->step != 0) {
+    for (auto& v : b->views) v.loaded = false;
+    b->loaded = false;
+  }
+  b->parity = 0;
+  b->step = 0;
+  lc_ctx* c = &b->views[k];
+  c->parity = 0;
+  c->step = 0;
+  lc_status st = LC_DISPATCH(c, do_load, f_dev, q_dev);
+  if (st) return st;
+  c->loaded = true;
+  bool all = true;
+  for (auto& v : b->views) all = all && v.loaded;
+  b->loaded = all;
+  return LC_OK;
+}
+
+lc_status lc_batch_step(lc_batch* b, int64_t n) {
+  clear_error();
+  if (!b) return fail(LC_EINVAL, "batch is NULL");
+  if (n < 0) return fail(LC_EINVAL, "n must be >= 0");
+  if (!b->loaded) return fail(LC_ESTATE, "load every grid of the batch before stepping");
+  while (n >= lc_batch::G) {
+    if (!b->exec[b->parity]) {
+      lc_status st = batch_build_graph(b, b->parity);
+      if (st) return st;
+    }
+    lc_status st = hip_check(hipGraphLaunch(b->exec[b->parity], b->stream), "graph launch");
+    if (st) return st;
+    n -= lc_batch::G;
+    b->step += lc_batch::G;
+  }
+  for (int64_t i = 0; i < n; i++) {
+    batch_launch_step(b, b->stream, b->parity);
+    b->parity ^= 1;
+    b->step++;
+  }
+  batch_sync_views(b);
+  return hip_check(hipGetLastError(), "batch step launch");
+}
+
+lc_status lc_batch_set_tile(lc_batch* b, int32_t variant) {
+  clear_error();
+  if (!b) return fail(LC_EINVAL, "batch is NULL");
+  if (variant < 0 || variant >= BATCH_NV) return fail(LC_EINVAL, "tile variant out of range");
+  if (variant == b->variant) return LC_OK;
+  b->variant = variant;
+  batch_drop_graphs(b);
+  lc_status st = batch_upload(b);
+  if (st) return st;
+  return hip_check(hipStreamSynchronize(b->stream), "descriptor upload sync");
+}
+
+lc_status lc_batch_autotune(lc_batch* b, int32_t trial_steps, int32_t* chosen, double* ms_per_step) {
+  clear_error();
+  if (!b) return fail(LC_EINVAL, "batch is NULL");
+  if (trial_steps < 1) return fail(LC_EINVAL, "trial_steps must be >= 1");
+  if (!b->loaded) return fail(LC_ESTATE, "load every grid of the batch before tuning");
+  hipEvent_t e0, e1;
+  lc_status st = hip_check(hipEventCreate(&e0), "event");
+  if (st) return st;
+  st = hip_check(hipEventCreate(&e1), "event");
+  if (st) {
+    hipEventDestroy(e0);
+    return st;
+  }
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int v = 0; v < BATCH_NV && st == LC_OK; v++) {
+    st = lc_batch_set_tile(b, v);
+    if (st) break;
+    // one untimed step, then the timed trial
+    st = lc_batch_step(b, 1);
+    if (st) break;
+    hipEventRecord(e0, b->stream);
+    st = lc_batch_step(b, trial_steps);
+    if (st) break;
+    hipEventRecord(e1, b->stream);
+    st = hip_check(hipEventSynchronize(e1), "event sync");
+    if (st) break;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st) return st;
+  if (chosen) *chosen = best;
+  if (ms_per_step) *ms_per_step = double(best_ms) / trial_steps;
+  return lc_batch_set_tile(b, best);
+}
+
+lc_status lc_batch_observe(lc_batch* b, uint32_t mask, int32_t half_axis, lc_observables* out) {
+  clear_error();
+  if (!b || !out) return fail(LC_EINVAL, "NULL argument");
+  if (!b->loaded) return fail(LC_ESTATE, "batch not loaded");
+  if (half_axis < 0 || half_axis > 2) return fail(LC_EINVAL, "half_axis must be 0, 1 or 2");
+  batch_sync_views(b);
+  double* res = reinterpret_cast<double*>(static_cast<char*>(b->arena.scratch) + b->B.off_res);
+  for (int k = 0; k < b->n; k++) {
+    lc_ctx* c = &b->views[k];
+    lc_status st = LC_DISPATCH(c, do_observe_async, mask, half_axis, res + size_t(k) * OBS_W);
+    if (st) return st;
+  }
+  std::vector<double> h(size_t(b->n) * OBS_W);
+  lc_status st = hip_check(hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream),
+                           "batch observe copy");
+  if (st) return st;
+  st = hip_check(hipStreamSynchronize(b->stream), "batch observe sync");
+  if (st) return st;
+  bool bad = false;
+  for (int k = 0; k < b->n; k++) {
+    fill_observables(&h[size_t(k) * OBS_W], mask, half_axis, b->step, &out[k]);
+    bad = bad || out[k].nonfinite;
+  }
+  if (bad) return fail(LC_ENONFINITE, "a grid of the batch holds NaN or Inf");
+  return LC_OK;
+}
+
+lc_status lc_batch_export(lc_batch* b, int32_t k, int32_t field, double* dst) {
+  clear_error();
+  if (!b || !dst) return fail(LC_EINVAL, "NULL argument");
+  if (k < 0 || k >= b->n) return fail(LC_EINVAL, "grid index out of range");
+  if (field < LC_FIELD_F || field > LC_FIELD_S) return fail(LC_EINVAL, "unknown field %d", field);
+  batch_sync_views(b);
+  lc_ctx* c = &b->views[k];
+  if (!c->loaded) return fail(LC_ESTATE, "grid not loaded");
+  return LC_DISPATCH(c, do_export, field, dst);
+}
+
+lc_status lc_batch_free(lc_batch* b) {
+  clear_error();
+  if (!b) return LC_OK;
+  batch_drop_graphs(b);
+  hipStreamDestroy(b->cap);
+  delete b;
   return LC_OK;
 }
 

@@ -144,10 +144,10 @@ __device__ __forceinline__ void store_region(const RegionRegs<S, TX, TY, NC>& r,
 
 // ---------------------------------------------------------------------------
 // Sweep 1: stress in LDS, body force, moments, collision, streaming.
-template <int LAT, typename S, bool DEV, int TX, int TY, int WPE>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) split_lb(const S* __restrict__ Qin, const S* __restrict__ fin,
-                                                   S* __restrict__ fout, S* __restrict__ uout, GridDims g,
-                                                   Coef<S> c, int zc) {
+template <int LAT, typename S, bool DEV, int TX, int TY>
+__device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S* __restrict__ fin,
+                                              S* __restrict__ fout, S* __restrict__ uout, const GridDims& g,
+                                              const Coef<S>& c, int zc, int bx, int by, int bz) {
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
   constexpr int DIM = L::dim;
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
   __shared__ S sTy[NTP][DIM][NYA];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int x0 = bx * TX, y0 = by * TY;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < g.nx && y < g.ny;
   const int64_t N = g.N;
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
     __syncthreads();
     lb_site(0, 0, tz, tz, f);
   } else {
-    const int zb = blockIdx.z * zc;
+    const int zb = bz * zc;
     const int ze = min(zb + zc, g.nz);
     auto slot = [](int p) { return (p + 3) % 3; };  // p >= -3
     // software pipeline: the halo region of plane p+2 and the populations of
@@ -299,11 +299,19 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
   }
 }
 
+template <int LAT, typename S, bool DEV, int TX, int TY, int WPE>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
+    split_lb(const S* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ uout,
+             GridDims g, Coef<S> c, int zc) {
+  split_lb_body<LAT, S, DEV, TX, TY>(Qin, fin, fout, uout, g, c, zc, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ---------------------------------------------------------------------------
 // Sweep 2: predictor on tile + ring (LDS), corrector on the tile.
-template <int LAT, typename S, int TX, int TY, int WPE>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE))) split_q(const S* __restrict__ Qin, const S* __restrict__ uin,
-                                                  S* __restrict__ Qout, GridDims g, Coef<S> c, int zc) {
+template <int LAT, typename S, int TX, int TY>
+__device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S* __restrict__ uin,
+                                             S* __restrict__ Qout, const GridDims& g, const Coef<S>& c, int zc,
+                                             int bx, int by, int bz) {
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
   constexpr int DIM = L::dim;
@@ -314,7 +322,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
   __shared__ S sP[NPP][5][T::R1];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  const int x0 = bx * TX, y0 = by * TY;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < g.nx && y < g.ny;
   const int64_t N = g.N;
@@ -419,7 +427,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
     __syncthreads();
     corr_site(0, 0, st, qp, qp);
   } else {
-    const int zb = blockIdx.z * zc;
+    const int zb = bz * zc;
     const int ze = min(zb + zc, g.nz);
     auto slot = [](int p) { return (p + 3) % 3; };
     RegionRegs<S, TX, TY, NC> rq;
@@ -440,6 +448,13 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
       stB = stC;
     }
   }
+}
+
+template <int LAT, typename S, int TX, int TY, int WPE>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
+    split_q(const S* __restrict__ Qin, const S* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
+            int zc) {
+  split_q_body<LAT, S, TX, TY>(Qin, uin, Qout, g, c, zc, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 }  // namespace lc

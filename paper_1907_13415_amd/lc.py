@@ -74,6 +74,18 @@ def _load():
         "lc_sync": ([ctypes.c_void_p], ctypes.c_int32),
         "lc_step_count": ([ctypes.c_void_p], ctypes.c_int64),
         "lc_free": ([ctypes.c_void_p], ctypes.c_int32),
+        "lc_batch_layout": ([ctypes.c_int32, P(lc_grid), P(ctypes.c_size_t), P(ctypes.c_size_t),
+                             P(ctypes.c_size_t), P(ctypes.c_size_t), P(ctypes.c_size_t)], ctypes.c_int32),
+        "lc_batch_init": ([ctypes.c_int32, P(lc_grid), P(lc_params), P(lc_buffers), ctypes.c_void_p,
+                           P(ctypes.c_void_p)], ctypes.c_int32),
+        "lc_batch_load_state": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
+        "lc_batch_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
+        "lc_batch_set_tile": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+        "lc_batch_autotune": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)],
+                              ctypes.c_int32),
+        "lc_batch_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
+        "lc_batch_export": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
+        "lc_batch_free": ([ctypes.c_void_p], ctypes.c_int32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -256,3 +268,121 @@ class Solver:
 
     def sync(self):
         lc_sync(self.ctx)
+
+
+# ---------------------------------------------------------------- batched form
+def lc_batch_layout(grids):
+    n = len(grids)
+    ga = (lc_grid * n)(*grids)
+    fb, qb, sb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    fo = (ctypes.c_size_t * n)()
+    qo = (ctypes.c_size_t * n)()
+    _check(_lib.lc_batch_layout(n, ga, ctypes.byref(fb), ctypes.byref(qb), ctypes.byref(sb), fo, qo))
+    return fb.value, qb.value, sb.value, list(fo), list(qo)
+
+
+def lc_batch_init(grids, params, arena, stream):
+    n = len(grids)
+    ga = (lc_grid * n)(*grids)
+    pa = (lc_params * n)(*params)
+    b = ctypes.c_void_p()
+    _check(_lib.lc_batch_init(n, ga, pa, ctypes.byref(arena), ctypes.c_void_p(stream), ctypes.byref(b)))
+    return b
+
+
+def lc_batch_load_state(b, k, f_ptr, q_ptr):
+    _check(_lib.lc_batch_load_state(b, k, ctypes.c_void_p(f_ptr), ctypes.c_void_p(q_ptr)))
+
+
+def lc_batch_step(b, n):
+    _check(_lib.lc_batch_step(b, int(n)))
+
+
+def lc_batch_set_tile(b, v):
+    _check(_lib.lc_batch_set_tile(b, int(v)))
+
+
+def lc_batch_autotune(b, trial_steps):
+    ch = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(_lib.lc_batch_autotune(b, int(trial_steps), ctypes.byref(ch), ctypes.byref(ms)))
+    return ch.value, ms.value
+
+
+def lc_batch_observe(b, n, mask=LC_OBS_ALL, half_axis=0):
+    out = (lc_observables * n)()
+    _check(_lib.lc_batch_observe(b, mask, half_axis, out))
+    return [dict(mass=o.mass, mom=np.array(o.mom[:]), umax=o.umax, ssum=o.ssum, ssum_half=o.ssum_half,
+                 step=o.step, nonfinite=o.nonfinite) for o in out]
+
+
+def lc_batch_export(b, k, field, dst_ptr):
+    _check(_lib.lc_batch_export(b, k, field, ctypes.c_void_p(dst_ptr)))
+
+
+def lc_batch_free(b):
+    _check(_lib.lc_batch_free(b))
+
+
+class BatchSolver:
+    """Many independent D2Q9 grids advanced together.
+
+    shapes: list of (ny, nx); params: list of (A0, gamma, K, Gamma, xi, tau);
+    precision: "fp64" | "fp32dev".
+    """
+
+    def __init__(self, precision, shapes, params, device="cuda", stream=None):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shapes = [(1, ny, nx) for (ny, nx) in shapes]
+        self.n = len(shapes)
+        self.grids = [make_grid(LC_D2Q9, PRECISIONS[precision], nx, ny, 1) for (ny, nx) in shapes]
+        self.params = [make_params(*p) for p in params]
+        fb, qb, sb, self.f_off, self.q_off = lc_batch_layout(self.grids)
+        self._f = [torch.empty(fb, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self._Q = [torch.empty(qb, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self._scratch = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.arena = lc_buffers((ctypes.c_void_p * 2)(self._f[0].data_ptr(), self._f[1].data_ptr()),
+                                (ctypes.c_void_p * 2)(self._Q[0].data_ptr(), self._Q[1].data_ptr()),
+                                self._scratch.data_ptr())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.b = lc_batch_init(self.grids, self.params, self.arena, self.stream.cuda_stream)
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b:
+            try:
+                _lib.lc_batch_free(b)
+            except Exception:
+                pass
+            self.b = None
+
+    def load(self, k, q5, f=None):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            qd = torch.as_tensor(np.ascontiguousarray(q5, dtype=np.float64)).to(self.device)
+            fd = None if f is None else torch.as_tensor(np.ascontiguousarray(f, dtype=np.float64)).to(self.device)
+            lc_batch_load_state(self.b, k, None if fd is None else fd.data_ptr(), qd.data_ptr())
+            self.stream.synchronize()
+
+    def step(self, n):
+        lc_batch_step(self.b, n)
+
+    def set_tile(self, v):
+        lc_batch_set_tile(self.b, v)
+
+    def autotune(self, trial_steps=20):
+        return lc_batch_autotune(self.b, trial_steps)
+
+    def observe(self, mask=LC_OBS_ALL, half_axis=0):
+        return lc_batch_observe(self.b, self.n, mask, half_axis)
+
+    def export(self, k, field):
+        torch = self.torch
+        ncomp = {LC_FIELD_F: 9, LC_FIELD_Q: 5, LC_FIELD_RHO: 1, LC_FIELD_U: 3, LC_FIELD_FORCE: 3, LC_FIELD_S: 1}[field]
+        with torch.cuda.stream(self.stream):
+            out = torch.zeros((ncomp,) + self.shapes[k], dtype=torch.float64, device=self.device)
+            lc_batch_export(self.b, k, field, out.data_ptr())
+            self.stream.synchronize()
+        return out.cpu().numpy()

@@ -1,0 +1,147 @@
+"""GPU tests of the batched form: many grids of different sizes and gamma in
+one launch per sweep, replayed from a HIP graph.
+
+Every grid of a batch must reproduce the single-grid path exactly (the
+per-site arithmetic does not depend on tile shape or on which block runs a
+tile), across graph replays with eager work in between, and match the CPU
+oracle to the double-precision tolerance.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_13415_amd import inputs
+from gpu_util import SCALES, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _lc():
+    require_gpu()
+    from paper_1907_13415_amd import lc
+    return lc
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+SHAPES = [(23, 37), (64, 64), (40, 96), (16, 16), (70, 130)]
+
+
+def _batch_inputs(seed):
+    rng = np.random.default_rng(seed)
+    q5s, params = [], []
+    for k, (ny, nx) in enumerate(SHAPES):
+        q5s.append(inputs.random_q5((1, ny, nx), rng, amp=0.12))
+        params.append(inputs.with_gamma((1.0, 2.7, 0.05, 0.3, 0.7, 1.3), 2.66 + 0.03 * k))
+    return q5s, params
+
+
+@pytest.mark.parametrize("prec", ["fp32dev", "fp64"])
+def test_batch_equals_single_grid_across_graph_replays(prec):
+    lc = _lc()
+    _say("batch vs single %s" % prec)
+    q5s, params = _batch_inputs(1)
+    b = lc.BatchSolver(prec, SHAPES, params)
+    singles = []
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+        s = lc.Solver("D2Q9", prec, (1,) + SHAPES[k], params[k])
+        s.load(q5)
+        singles.append(s)
+    done = 0
+    for chunk in (64, 64, 11, 64):  # graph replay, replay, eager tail, replay from odd parity
+        b.step(chunk)
+        for s in singles:
+            s.step(chunk)
+        done += chunk
+        # eager work and synchronisation between replays
+        obs = b.observe()
+        for k, s in enumerate(singles):
+            fb, qb = b.export(k, lc.LC_FIELD_F), b.export(k, lc.LC_FIELD_Q)
+            fs, qs = s.export(lc.LC_FIELD_F), s.export(lc.LC_FIELD_Q)
+            assert np.array_equal(fb, fs) and np.array_equal(qb, qs), (k, done)
+            o = s.observe()
+            assert obs[k]["mass"] == o["mass"] and obs[k]["ssum_half"] == o["ssum_half"]
+            assert obs[k]["step"] == done
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_batch_every_tile_shape_matches_oracle_fp64(tile):
+    """Each tile shape (32x8, 64x4, 16x16) agrees with the double-precision
+    oracle; shapes differ from each other only by rounding (the compiler
+    contracts multiply-adds per instantiation)."""
+    lc = _lc()
+    q5s, params = _batch_inputs(2)
+    b = lc.BatchSolver("fp64", SHAPES, params)
+    b.set_tile(tile)
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+    b.step(70)
+    for k, q5 in enumerate(q5s):
+        f_ref, q_ref = oracle.run(0, oracle.rest_populations(0, (1,) + SHAPES[k]), q5, params[k], 70)
+        ef = rel_err(b.export(k, lc.LC_FIELD_F), f_ref, SCALES["f"])
+        eq = rel_err(b.export(k, lc.LC_FIELD_Q), q_ref, SCALES["q"])
+        assert ef < 1e-12 and eq < 1e-12, (tile, k, ef, eq)
+
+
+def test_batch_autotune_keeps_results():
+    lc = _lc()
+    q5s, params = _batch_inputs(2)
+    ref = lc.BatchSolver("fp32dev", SHAPES, params)
+    for k, q5 in enumerate(q5s):
+        ref.load(k, q5)
+    b = lc.BatchSolver("fp32dev", SHAPES, params)
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+    chosen, ms = b.autotune(5)
+    _say("autotune chose tile %d (%.3f ms/step)" % (chosen, ms))
+    assert chosen in (0, 1, 2) and ms > 0
+    ref.set_tile(chosen)
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+        ref.load(k, q5)
+    b.step(70)
+    ref.step(70)
+    for k in range(len(SHAPES)):
+        assert np.array_equal(ref.export(k, lc.LC_FIELD_Q), b.export(k, lc.LC_FIELD_Q))
+
+
+def test_batch_fp64_matches_oracle():
+    lc = _lc()
+    q5s, params = _batch_inputs(3)
+    b = lc.BatchSolver("fp64", SHAPES, params)
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+    b.step(70)
+    for k, q5 in enumerate(q5s):
+        f_ref, q_ref = oracle.run(0, oracle.rest_populations(0, (1,) + SHAPES[k]), q5, params[k], 70)
+        ef = rel_err(b.export(k, lc.LC_FIELD_F), f_ref, SCALES["f"])
+        eq = rel_err(b.export(k, lc.LC_FIELD_Q), q_ref, SCALES["q"])
+        assert ef < 1e-12 and eq < 1e-12, (k, ef, eq)
+
+
+def test_temperature_sweep_workload_full_size():
+    """The 64-grid sweep (sizes 64..512, gamma in [2.62, 2.78]) at full size:
+    sampled grids equal the single-grid path after 70 steps (graph path)."""
+    lc = _lc()
+    ws = inputs.config3()
+    shapes = [w.shape[1:] for w in ws]
+    b = lc.BatchSolver("fp32dev", shapes, [w.params for w in ws])
+    for k, w in enumerate(ws):
+        b.load(k, w.q5)
+    b.step(70)
+    sizes = [s[0] for s in shapes]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), len(ws) // 2})
+    for k in picks:
+        s = lc.Solver("D2Q9", "fp32dev", ws[k].shape, ws[k].params)
+        s.load(ws[k].q5)
+        s.step(70)
+        assert np.array_equal(b.export(k, lc.LC_FIELD_Q), s.export(lc.LC_FIELD_Q)), k
+        assert np.array_equal(b.export(k, lc.LC_FIELD_F), s.export(lc.LC_FIELD_F)), k
+    obs = b.observe()
+    assert all(o["nonfinite"] == 0 for o in obs)
