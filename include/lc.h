@@ -184,6 +184,22 @@ lc_status lc_observe(lc_ctx *ctx, uint32_t mask, int32_t half_axis, lc_observabl
  * size given by the field, N = nx*ny*nz).  Asynchronous. */
 lc_status lc_export(lc_ctx *ctx, int32_t field, double *dst_dev);
 
+/* Reverse-mode step (adjoint) for gradients of a loss of the final state
+ * with respect to the initial state and to gamma, K and Gamma.  Provided
+ * for D2Q9 in LC_FP64 (LC_EUNSUPPORTED otherwise).
+ *   f_n, Q_n : the state at step n, device arrays of double logical values
+ *              (as lc_export writes them: q*N and 5*N), read only;
+ *   adj_f, adj_Q : on entry the adjoint dL/d(state at n+1), on return
+ *              dL/d(state at n) (device, q*N and 5*N doubles, overwritten);
+ *   dparams  : device doubles [3]; dL/dgamma, dL/dK, dL/dGamma of this step
+ *              are ADDED to them.
+ * The step is differentiated exactly as the forward step computes it
+ * (Eqs. 1-9 with the readings of lc_step).  Asynchronous; uses the reverse
+ * fields of the scratch buffer, so reverse steps on one context must not
+ * overlap. */
+lc_status lc_vjp_step(lc_ctx *ctx, const double *f_n, const double *Q_n, double *adj_f, double *adj_Q,
+                      double *dparams);
+
 /* Wait for the context stream and report any pending device error. */
 lc_status lc_sync(lc_ctx *ctx);
 

@@ -1,0 +1,98 @@
+"""Gradients through many steps of the hybrid scheme: a torch.autograd.Function
+over the library's forward step (lc_step) and reverse step (lc_vjp_step),
+with checkpoint-and-recompute.
+
+Forward: the state is saved every `every` steps (logical f and Q in double,
+on the device).  Backward: segments are processed last to first; each is
+replayed from its checkpoint with every intermediate state kept, then the
+reverse step walks it backwards.  Memory: one checkpoint per segment plus
+`every` states of one segment.  All arithmetic runs in the HIP kernels;
+this module only schedules calls and owns buffers.
+
+Two-dimensional (D2Q9) grids in double precision.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import lc
+
+
+class LCSolve(torch.autograd.Function):
+    """q_final = LCSolve.apply(q0, gamma, K, Gamma, cfg)
+
+    q0: (5, 1, ny, nx) float64 CUDA tensor, the initial order tensor (the
+        fluid starts at rest, f = w_i);
+    gamma, K, Gamma: float64 scalar tensors;
+    cfg: dict(A0=, xi=, tau=, steps=, every=100).
+    Returns the order tensor after cfg["steps"] steps.
+    """
+
+    @staticmethod
+    def forward(ctx, q0, gamma, K, Gamma, cfg):
+        for name, t in (("q0", q0), ("gamma", gamma), ("K", K), ("Gamma", Gamma)):
+            if not torch.is_tensor(t) or t.dtype != torch.float64:
+                raise TypeError("%s must be a float64 tensor" % name)
+        steps = int(cfg["steps"])
+        every = int(cfg.get("every", 100))
+        params = (cfg["A0"], float(gamma), float(K), float(Gamma), cfg["xi"], cfg["tau"])
+        shape = tuple(q0.shape[1:])
+        s = lc.Solver("D2Q9", "fp64", shape, params, device=q0.device)
+        with torch.cuda.stream(s.stream):
+            q0c = q0.detach().contiguous()
+            lc.lc_load_state(s.ctx, None, q0c.data_ptr())
+            checkpoints = []
+            done = 0
+            while done < steps:
+                f_ck = torch.empty((9,) + shape, dtype=torch.float64, device=q0.device)
+                q_ck = torch.empty((5,) + shape, dtype=torch.float64, device=q0.device)
+                lc.lc_export(s.ctx, lc.LC_FIELD_F, f_ck.data_ptr())
+                lc.lc_export(s.ctx, lc.LC_FIELD_Q, q_ck.data_ptr())
+                n = min(every, steps - done)
+                checkpoints.append((f_ck, q_ck, n))
+                s.step(n)
+                done += n
+            q_final = torch.empty((5,) + shape, dtype=torch.float64, device=q0.device)
+            lc.lc_export(s.ctx, lc.LC_FIELD_Q, q_final.data_ptr())
+        s.stream.synchronize()
+        ctx.solver = s
+        ctx.checkpoints = checkpoints
+        ctx.shape = shape
+        return q_final
+
+    @staticmethod
+    def backward(ctx, grad_q):
+        s = ctx.solver
+        shape = ctx.shape
+        dev = grad_q.device
+        with torch.cuda.stream(s.stream):
+            adj_q = grad_q.detach().to(torch.float64).contiguous().clone()
+            adj_f = torch.zeros((9,) + shape, dtype=torch.float64, device=dev)
+            dparams = torch.zeros(3, dtype=torch.float64, device=dev)
+            every = max(n for _, _, n in ctx.checkpoints)
+            hist_f = torch.empty((every, 9) + shape, dtype=torch.float64, device=dev)
+            hist_q = torch.empty((every, 5) + shape, dtype=torch.float64, device=dev)
+            for f_ck, q_ck, n in reversed(ctx.checkpoints):
+                lc.lc_load_state(s.ctx, f_ck.data_ptr(), q_ck.data_ptr())
+                for j in range(n):
+                    lc.lc_export(s.ctx, lc.LC_FIELD_F, hist_f[j].data_ptr())
+                    lc.lc_export(s.ctx, lc.LC_FIELD_Q, hist_q[j].data_ptr())
+                    if j + 1 < n:
+                        s.step(1)
+                for j in reversed(range(n)):
+                    lc.lc_vjp_step(s.ctx, hist_f[j].data_ptr(), hist_q[j].data_ptr(), adj_f.data_ptr(),
+                                   adj_q.data_ptr(), dparams.data_ptr())
+        s.stream.synchronize()
+        return adj_q, dparams[0], dparams[1], dparams[2], None
+
+
+def solve(q0, gamma, K, Gamma, **cfg):
+    """Functional form of LCSolve.apply."""
+    return LCSolve.apply(q0, gamma, K, Gamma, cfg)
+
+
+def order_parameter(q5):
+    """S = sqrt(1.5 Q:Q) of a (5, ...) tensor of stored components."""
+    xx, xy, xz, yy, yz = q5
+    qq = xx * xx + yy * yy + (xx + yy) * (xx + yy) + 2 * (xy * xy + xz * xz + yz * yz)
+    return torch.sqrt(1.5 * qq)

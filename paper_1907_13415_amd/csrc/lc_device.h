@@ -10,6 +10,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Per-site helpers are usable from host code too (the adjoint unit checks
+// run them on the CPU).
+#define LC_HD __host__ __device__ __forceinline__
+
 namespace lc {
 
 // ---------------------------------------------------------------------------
@@ -77,22 +81,23 @@ struct Coef {
   T xi_m;    // (xi - 1)/2
   T omega;   // 1/tau
   T src;     // 1 - 1/(2 tau)
+  T A0;      // bulk coefficient (the adjoint needs d/dgamma of lin and quad)
 };
 
 template <typename T>
 struct Sym {
   T xx, xy, xz, yy, yz;
-  __device__ __forceinline__ T zz() const { return -xx - yy; }
+  LC_HD T zz() const { return -xx - yy; }
 };
 
 template <typename T>
-__device__ __forceinline__ Sym<T> sym_zero() {
+LC_HD Sym<T> sym_zero() {
   return Sym<T>{T(0), T(0), T(0), T(0), T(0)};
 }
 
 // Full contraction A:B of two symmetric traceless tensors.
 template <typename T>
-__device__ __forceinline__ T ddot(const Sym<T>& a, const Sym<T>& b) {
+LC_HD T ddot(const Sym<T>& a, const Sym<T>& b) {
   return a.xx * b.xx + a.yy * b.yy + (a.xx + a.yy) * (b.xx + b.yy) +
          T(2) * (a.xy * b.xy + a.xz * b.xz + a.yz * b.yz);
 }
@@ -100,7 +105,7 @@ __device__ __forceinline__ T ddot(const Sym<T>& a, const Sym<T>& b) {
 // Molecular field, Eq. (4), from Q and its Laplacian L:
 //   H = lin Q + quad (Q.Q - Tr(Q^2) I/3) - quad Tr(Q^2) Q + K L.
 template <typename T>
-__device__ __forceinline__ Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>& L,
+LC_HD Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>& L,
                                                   const Coef<T>& c) {
   const T zz = Q.zz();
   const T sxx = Q.xx * Q.xx + Q.xy * Q.xy + Q.xz * Q.xz;
@@ -127,7 +132,7 @@ __device__ __forceinline__ Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>&
 // With M = H Q this is 2 xi Qp q_h - (2xi/3) H - K E - (xi+1) M - (xi-1) M^T.
 // dQ[g] = d_g Q (g = x, y, z).
 template <typename T>
-__device__ __forceinline__ void stress(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
+LC_HD void stress(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
                                        const Coef<T>& c, T (&tau)[3][3]) {
   const T Qm[3][3] = {{Q.xx, Q.xy, Q.xz}, {Q.xy, Q.yy, Q.yz}, {Q.xz, Q.yz, Q.zz()}};
   const T Hm[3][3] = {{H.xx, H.xy, H.xz}, {H.xy, H.yy, H.yz}, {H.xz, H.yz, H.zz()}};
@@ -157,7 +162,7 @@ __device__ __forceinline__ void stress(const Sym<T>& Q, const Sym<T>& H, const S
 //   S = A + A^T - 2 xi (Q + I/3)(Q:G),  A = [xi D + W](Q + I/3),
 // with G[a][b] = d_b u_a, so xi D + W = (xi+1)/2 G + (xi-1)/2 G^T.
 template <typename T>
-__device__ __forceinline__ Sym<T> be_rate(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
+LC_HD Sym<T> be_rate(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
                                           const T (&u)[3], const T (&G)[3][3], const Coef<T>& c) {
   const T Qp[3][3] = {{Q.xx + T(1.0 / 3.0), Q.xy, Q.xz},
                       {Q.xy, Q.yy + T(1.0 / 3.0), Q.yz},

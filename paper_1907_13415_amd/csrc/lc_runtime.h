@@ -19,6 +19,7 @@ struct Layout {
   size_t f_bytes, q_bytes;
   size_t off_tau, off_u, off_qp, off_r;
   size_t off_partial, off_obs;
+  size_t off_vjp;  // reverse-step fields (D2Q9 double only; 0 bytes otherwise)
   int64_t nblocks;
   size_t scratch_bytes;
 };

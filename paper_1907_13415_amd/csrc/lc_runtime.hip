@@ -12,6 +12,7 @@
 #include "lc_aux.h"
 #include "lc_split.h"
 #include "lc_batch.h"
+#include "lc_vjp.h"
 
 #include <vector>
 #include "lc_runtime.h"
@@ -78,6 +79,7 @@ Coef<S> make_coef(const lc_params& p) {
   c.xi_m = S((p.xi - 1.0) / 2.0);
   c.omega = S(1.0 / p.tau);
   c.src = S(1.0 - 1.0 / (2.0 * p.tau));
+  c.A0 = S(p.A0);
   return c;
 }
 
@@ -108,6 +110,11 @@ Layout layout_of(const lc_grid& g) {
   off = up(off + size_t(L.nblocks) * OBS_W * 8);
   L.off_obs = off;
   off = up(off + OBS_W * 8);
+  L.off_vjp = off;
+  if (g.lattice == LC_D2Q9 && g.precision == LC_FP64) {
+    off = up(off + size_t(VJP_COMPS) * N * 8);
+    off = up(off + size_t(3) * L.nblocks * 3 * 8);
+  }
   L.scratch_bytes = off;
   return L;
 }
@@ -453,6 +460,59 @@ lc_status lc_export(lc_ctx* c, int32_t field, double* dst) {
   if (!c->loaded) return fail(LC_ESTATE, "lc_export before lc_load_state");
   if (field < LC_FIELD_F || field > LC_FIELD_S) return fail(LC_EINVAL, "unknown field %d", field);
   return LC_DISPATCH(c, do_export, field, dst);
+}
+
+lc_status lc_vjp_step(lc_ctx* c, const double* f_n, const double* q_n, double* adj_f, double* adj_q,
+                      double* dparams) {
+  clear_error();
+  if (!c || !f_n || !q_n || !adj_f || !adj_q || !dparams) return fail(LC_EINVAL, "NULL argument");
+  if (c->g.lattice != LC_D2Q9 || c->g.precision != LC_FP64)
+    return fail(LC_EUNSUPPORTED, "the reverse step is provided for D2Q9 in double precision");
+  const GridDims gd{c->g.nx, c->g.ny, 1, c->L.N};
+  const int64_t N = c->L.N;
+  const Coef<double> k = make_coef<double>(c->p);
+  double* base = reinterpret_cast<double*>(static_cast<char*>(c->b.scratch) + c->L.off_vjp);
+  VjpFields v;
+  double* p = base;
+  auto take = [&](int comps) {
+    double* r = p;
+    p += size_t(comps) * N;
+    return r;
+  };
+  v.tau = take(4);
+  v.rho = take(1);
+  v.u = take(2);
+  v.F = take(2);
+  v.qp = take(5);
+  v.r = take(5);
+  v.fbar = take(9);
+  v.qpb = take(5);
+  v.lpb = take(5);
+  v.dqpb = take(10);
+  v.ub = take(2);
+  v.gb = take(4);
+  v.rhob = take(1);
+  v.fb = take(2);
+  v.qb = take(5);
+  v.hb = take(5);
+  v.dqb = take(10);
+  v.fbar2 = take(2);
+  v.lb = take(5);
+  v.nblocks = c->L.nblocks;
+  v.part = base + size_t(VJP_COMPS) * N;
+  // keep the partials 256-byte aligned as laid out
+  v.part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(v.part) + 255) & ~uintptr_t(255));
+  const dim3 grid = site_grid(c->g), block = site_block();
+  hipLaunchKernelGGL((stage_tau<0, double>), grid, block, 0, c->stream, q_n, v.tau, gd, k);
+  hipLaunchKernelGGL(vjp_fwd_moments, grid, block, 0, c->stream, f_n, v.tau, v, gd);
+  hipLaunchKernelGGL((stage_pred<0, double>), grid, block, 0, c->stream, q_n, v.u, v.qp, v.r, gd, k);
+  hipLaunchKernelGGL(vjp_r1, grid, block, 0, c->stream, adj_f, adj_q, v, gd, k);
+  hipLaunchKernelGGL(vjp_r2, grid, block, 0, c->stream, q_n, adj_q, v, gd, k);
+  hipLaunchKernelGGL(vjp_r3, grid, block, 0, c->stream, adj_f, v, gd);
+  hipLaunchKernelGGL(vjp_r4, grid, block, 0, c->stream, q_n, v, gd, k);
+  hipLaunchKernelGGL(vjp_r5, grid, block, 0, c->stream, adj_q, v, gd);
+  hipLaunchKernelGGL(vjp_params, dim3(1), dim3(64), 0, c->stream, v.part, v.nblocks, dparams);
+  return hip_check(hipGetLastError(), "reverse step launch");
 }
 
 lc_status lc_sync(lc_ctx* c) {

@@ -1,0 +1,286 @@
+// lc_vjp.h -- one reverse-mode step of the hybrid scheme (D2Q9, double).
+//
+// Given the state (f, Q) at step n (logical populations, before collision)
+// and the adjoint (adj_f, adj_Q) of the state at step n+1, the kernels
+// below overwrite the adjoint with that of step n and accumulate the
+// derivatives with respect to gamma, K and Gamma.  The forward quantities
+// of the step (stress, density, velocity, body force, predictor) are
+// recomputed first; the reverse sweep then runs the chain backwards:
+//   streaming and collision -> corrector rate at Q^P (and its H, Laplacian
+//   and gradient stencils) -> predictor rate at Q -> velocity gradient and
+//   force-corrected velocity -> body force and stress -> molecular field.
+// Stencil adjoints are applied as gathers: the compact Laplacian is
+// self-adjoint and the central difference D has adjoint -D on a periodic
+// grid.  Each kernel handles one site per thread.
+#pragma once
+
+#include "lc_adjoint.h"
+#include "lc_aux.h"
+
+namespace lc {
+
+// Scratch fields of the reverse step (double, N values per component).
+struct VjpFields {
+  double *tau, *rho, *u, *F, *qp, *r;                 // forward recompute
+  double *fbar, *qpb, *lpb, *dqpb, *ub, *gb, *rhob;  // reverse
+  double *fb, *qb, *hb, *dqb, *fbar2, *lb;
+  double *part;  // [3 kernels][nblocks][3] parameter partials
+  int64_t nblocks;
+};
+constexpr int VJP_COMPS = 4 + 1 + 2 + 2 + 5 + 5 + 9 + 5 + 5 + 10 + 2 + 4 + 1 + 2 + 5 + 5 + 10 + 2 + 5;
+
+__device__ __forceinline__ void block_reduce3(double (&v)[3], double* __restrict__ dst) {
+  __shared__ double part[16][3];
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; k++) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) part[wid][k] = v[k];
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double acc = part[0][tid];
+    for (int w = 1; w < nw; w++) acc += part[w][tid];
+    dst[tid] = acc;
+  }
+}
+
+// Laplacian and minus-divergence gathers of adjoint fields at site s.
+__device__ __forceinline__ Sym<double> lap2(const double* __restrict__ A, int64_t N, int64_t s, const Nbr& nb) {
+  auto one = [&](int c) {
+    const double* a = A + c * N;
+    return (a[s + nb.xp] + a[s + nb.xm]) + (a[s + nb.yp] + a[s + nb.ym]) - 4.0 * a[s];
+  };
+  return Sym<double>{one(0), one(1), one(2), one(3), one(4)};
+}
+
+// -sum_g D_g(W_g) for W laid out [g][5][N], g = x, y
+__device__ __forceinline__ Sym<double> negdiv2(const double* __restrict__ W, int64_t N, int64_t s, const Nbr& nb) {
+  auto one = [&](int c) {
+    const double* wx = W + (0 * 5 + c) * N;
+    const double* wy = W + (1 * 5 + c) * N;
+    return -0.5 * ((wx[s + nb.xp] - wx[s + nb.xm]) + (wy[s + nb.yp] - wy[s + nb.ym]));
+  };
+  return Sym<double>{one(0), one(1), one(2), one(3), one(4)};
+}
+
+__device__ __forceinline__ void put5(double* __restrict__ A, int64_t N, int64_t s, const Sym<double>& v) {
+  A[s] = v.xx;
+  A[N + s] = v.xy;
+  A[2 * N + s] = v.xz;
+  A[3 * N + s] = v.yy;
+  A[4 * N + s] = v.yz;
+}
+
+__device__ __forceinline__ void velgrad2(const double* __restrict__ u, int64_t N, int64_t s, const Nbr& nb,
+                                         double (&G)[3][3], double (&uc)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    uc[a] = a < 2 ? u[a * N + s] : 0.0;
+    for (int b = 0; b < 3; b++) G[a][b] = 0.0;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; a++) {
+    G[a][0] = 0.5 * (u[a * N + s + nb.xp] - u[a * N + s + nb.xm]);
+    G[a][1] = 0.5 * (u[a * N + s + nb.yp] - u[a * N + s + nb.ym]);
+  }
+}
+
+#define LC_SITE_2D                                                       \
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;                   \
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;                   \
+  const bool in = x < g.nx && y < g.ny;                                  \
+  const int64_t N = g.N;                                                 \
+  const int64_t s = in ? x + (int64_t)g.nx * y : 0;                      \
+  const Nbr nb = neighbours(in ? x : 0, in ? y : 0, 0, g.nx, g.ny, 1);   \
+  const int64_t blk = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+
+// density, force-corrected velocity and body force from logical f and tau
+__global__ void __launch_bounds__(256) vjp_fwd_moments(const double* __restrict__ f, const double* __restrict__ tau,
+                                                       VjpFields v, GridDims g) {
+  LC_SITE_2D
+  (void)blk;
+  if (!in) return;
+  double F[3];
+  body_force<0, double>(tau, N, s, nb, F);
+  double ff[9];
+#pragma unroll
+  for (int i = 0; i < 9; i++) ff[i] = f[i * N + s];
+  double rho, u[3];
+  moments<0, double, false>(ff, F, rho, u);
+  v.rho[s] = rho;
+  v.u[s] = u[0];
+  v.u[N + s] = u[1];
+  v.F[s] = F[0];
+  v.F[N + s] = F[1];
+}
+
+// collision and corrector-rate adjoints
+__global__ void __launch_bounds__(256) vjp_r1(const double* __restrict__ adj_f, const double* __restrict__ adj_q,
+                                              VjpFields v, GridDims g, Coef<double> c) {
+  using L = Lattice<0>;
+  LC_SITE_2D
+  double d[3] = {0.0, 0.0, 0.0};
+  if (in) {
+    double fbs[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+      int64_t t = s;
+      if (L::cx(i) == 1) t += nb.xp;
+      if (L::cx(i) == -1) t += nb.xm;
+      if (L::cy(i) == 1) t += nb.yp;
+      if (L::cy(i) == -1) t += nb.ym;
+      fbs[i] = adj_f[i * N + t];  // f'_i(x + c_i) = f*_i(x)
+    }
+    const double rho = v.rho[s];
+    const double u3[3] = {v.u[s], v.u[N + s], 0.0};
+    const double F3[3] = {v.F[s], v.F[N + s], 0.0};
+    double fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, rhob = 0.0, ub[3] = {0, 0, 0}, Fb[3] = {0, 0, 0};
+    collide_vjp<0, double>(fbs, rho, u3, F3, c, fb, rhob, ub, Fb);
+    // corrector: Q' = Q + (R + R^P)/2
+    const Sym<double> aq = load_sym(adj_q, N, s);
+    const Sym<double> Rpb{0.5 * aq.xx, 0.5 * aq.xy, 0.5 * aq.xz, 0.5 * aq.yy, 0.5 * aq.yz};
+    Sym<double> P, dP[3], LP;
+    stencil<double, 2>(v.qp, N, s, nb, P, dP, LP);
+    const Sym<double> HP = molecular_field(P, LP, c);
+    double G[3][3], uc[3];
+    velgrad2(v.u, N, s, nb, G, uc);
+    Sym<double> Pb = sym_zero<double>(), HPb = sym_zero<double>(), LPb;
+    Sym<double> dPb[3] = {sym_zero<double>(), sym_zero<double>(), sym_zero<double>()};
+    double Gb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    be_rate_vjp(P, HP, dP, uc, G, Rpb, c, Pb, HPb, dPb, ub, Gb, d);
+    molecular_field_vjp(P, LP, HPb, c, Pb, LPb, d);
+#pragma unroll
+    for (int i = 0; i < 9; i++) v.fbar[i * N + s] = fb[i];
+    put5(v.qpb, N, s, Pb);
+    put5(v.lpb, N, s, LPb);
+    put5(v.dqpb, N, s, dPb[0]);
+    put5(v.dqpb + 5 * N, N, s, dPb[1]);
+    v.ub[s] = ub[0];
+    v.ub[N + s] = ub[1];
+    v.gb[s] = Gb[0][0];
+    v.gb[N + s] = Gb[0][1];
+    v.gb[2 * N + s] = Gb[1][0];
+    v.gb[3 * N + s] = Gb[1][1];
+    v.rhob[s] = rhob;
+    v.fb[s] = Fb[0];
+    v.fb[N + s] = Fb[1];
+  }
+  block_reduce3(d, v.part + (0 * v.nblocks + blk) * 3);
+}
+
+// predictor-rate adjoint at Q
+__global__ void __launch_bounds__(256) vjp_r2(const double* __restrict__ Q, const double* __restrict__ adj_q,
+                                              VjpFields v, GridDims g, Coef<double> c) {
+  LC_SITE_2D
+  double d[3] = {0.0, 0.0, 0.0};
+  if (in) {
+    Sym<double> qpb = load_sym(v.qpb, N, s);
+    add_to(qpb, lap2(v.lpb, N, s, nb));
+    add_to(qpb, negdiv2(v.dqpb, N, s, nb));
+    const Sym<double> aq = load_sym(adj_q, N, s);
+    const Sym<double> Rb{0.5 * aq.xx + qpb.xx, 0.5 * aq.xy + qpb.xy, 0.5 * aq.xz + qpb.xz, 0.5 * aq.yy + qpb.yy,
+                         0.5 * aq.yz + qpb.yz};
+    Sym<double> qb{aq.xx + qpb.xx, aq.xy + qpb.xy, aq.xz + qpb.xz, aq.yy + qpb.yy, aq.yz + qpb.yz};
+    Sym<double> q, dq[3], Lq;
+    stencil<double, 2>(Q, N, s, nb, q, dq, Lq);
+    const Sym<double> H = molecular_field(q, Lq, c);
+    double G[3][3], uc[3];
+    velgrad2(v.u, N, s, nb, G, uc);
+    Sym<double> Hb = sym_zero<double>();
+    Sym<double> dqb[3] = {sym_zero<double>(), sym_zero<double>(), sym_zero<double>()};
+    double ub[3] = {v.ub[s], v.ub[N + s], 0.0};
+    double Gb[3][3] = {{v.gb[s], v.gb[N + s], 0.0}, {v.gb[2 * N + s], v.gb[3 * N + s], 0.0}, {0, 0, 0}};
+    be_rate_vjp(q, H, dq, uc, G, Rb, c, qb, Hb, dqb, ub, Gb, d);
+    put5(v.qb, N, s, qb);
+    put5(v.hb, N, s, Hb);
+    put5(v.dqb, N, s, dqb[0]);
+    put5(v.dqb + 5 * N, N, s, dqb[1]);
+    v.ub[s] = ub[0];
+    v.ub[N + s] = ub[1];
+    v.gb[s] = Gb[0][0];
+    v.gb[N + s] = Gb[0][1];
+    v.gb[2 * N + s] = Gb[1][0];
+    v.gb[3 * N + s] = Gb[1][1];
+  }
+  block_reduce3(d, v.part + (1 * v.nblocks + blk) * 3);
+}
+
+// velocity-gradient and moment adjoints; writes the population adjoint
+__global__ void __launch_bounds__(256) vjp_r3(double* __restrict__ adj_f, VjpFields v, GridDims g) {
+  using L = Lattice<0>;
+  LC_SITE_2D
+  (void)blk;
+  if (!in) return;
+  double ub[2];
+#pragma unroll
+  for (int a = 0; a < 2; a++) {
+    const double* gx = v.gb + (a * 2 + 0) * N;  // G_{a x}
+    const double* gy = v.gb + (a * 2 + 1) * N;  // G_{a y}
+    ub[a] = v.ub[a * N + s] - 0.5 * ((gx[s + nb.xp] - gx[s + nb.xm]) + (gy[s + nb.yp] - gy[s + nb.ym]));
+  }
+  const double rho = v.rho[s];
+  const double u0 = v.u[s], u1 = v.u[N + s];
+  const double jb0 = ub[0] / rho, jb1 = ub[1] / rho;
+  const double rhob = v.rhob[s] - (ub[0] * u0 + ub[1] * u1) / rho;
+  v.fbar2[s] = v.fb[s] + 0.5 * jb0;
+  v.fbar2[N + s] = v.fb[N + s] + 0.5 * jb1;
+#pragma unroll
+  for (int i = 0; i < 9; i++) adj_f[i * N + s] = v.fbar[i * N + s] + rhob + L::cx(i) * jb0 + L::cy(i) * jb1;
+}
+
+// body-force, stress and molecular-field adjoints at Q
+__global__ void __launch_bounds__(256) vjp_r4(const double* __restrict__ Q, VjpFields v, GridDims g,
+                                              Coef<double> c) {
+  LC_SITE_2D
+  double d[3] = {0.0, 0.0, 0.0};
+  if (in) {
+    double tb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      const double* fa = v.fbar2 + a * N;
+      tb[a][0] = -0.5 * (fa[s + nb.xp] - fa[s + nb.xm]);
+      tb[a][1] = -0.5 * (fa[s + nb.yp] - fa[s + nb.ym]);
+    }
+    Sym<double> q, dq[3], Lq;
+    stencil<double, 2>(Q, N, s, nb, q, dq, Lq);
+    const Sym<double> H = molecular_field(q, Lq, c);
+    Sym<double> qb = load_sym(v.qb, N, s);
+    Sym<double> Hb = load_sym(v.hb, N, s);
+    Sym<double> dqb[3] = {load_sym(v.dqb, N, s), load_sym(v.dqb + 5 * N, N, s), sym_zero<double>()};
+    stress_vjp(q, H, dq, tb, c, qb, Hb, dqb, d);
+    Sym<double> Lb;
+    molecular_field_vjp(q, Lq, Hb, c, qb, Lb, d);
+    put5(v.qb, N, s, qb);
+    put5(v.lb, N, s, Lb);
+    put5(v.dqb, N, s, dqb[0]);
+    put5(v.dqb + 5 * N, N, s, dqb[1]);
+  }
+  block_reduce3(d, v.part + (2 * v.nblocks + blk) * 3);
+}
+
+// Laplacian and gradient gathers into the order-tensor adjoint
+__global__ void __launch_bounds__(256) vjp_r5(double* __restrict__ adj_q, VjpFields v, GridDims g) {
+  LC_SITE_2D
+  (void)blk;
+  if (!in) return;
+  Sym<double> qb = load_sym(v.qb, N, s);
+  add_to(qb, lap2(v.lb, N, s, nb));
+  add_to(qb, negdiv2(v.dqb, N, s, nb));
+  put5(adj_q, N, s, qb);
+}
+
+// parameter partials of the three kernels, added to dparams in fixed order
+__global__ void __launch_bounds__(64) vjp_params(const double* __restrict__ part, int64_t nblocks,
+                                                 double* __restrict__ dparams) {
+  const int k = threadIdx.x;
+  if (k >= 3) return;
+  double acc = 0.0;
+  for (int64_t b = 0; b < 3 * nblocks; b++) acc += part[b * 3 + k];
+  dparams[k] += acc;
+}
+
+}  // namespace lc

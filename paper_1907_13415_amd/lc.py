@@ -72,6 +72,7 @@ def _load():
         "lc_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
         "lc_export": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
         "lc_sync": ([ctypes.c_void_p], ctypes.c_int32),
+        "lc_vjp_step": ([ctypes.c_void_p] * 6, ctypes.c_int32),
         "lc_step_count": ([ctypes.c_void_p], ctypes.c_int64),
         "lc_free": ([ctypes.c_void_p], ctypes.c_int32),
         "lc_batch_layout": ([ctypes.c_int32, P(lc_grid), P(ctypes.c_size_t), P(ctypes.c_size_t),
@@ -171,6 +172,11 @@ def lc_observe(ctx, mask=LC_OBS_ALL, half_axis=0, allow_nonfinite=False):
 
 def lc_export(ctx, field, dst_ptr):
     _check(_lib.lc_export(ctx, field, ctypes.c_void_p(dst_ptr)))
+
+
+def lc_vjp_step(ctx, f_ptr, q_ptr, adj_f_ptr, adj_q_ptr, dparams_ptr):
+    _check(_lib.lc_vjp_step(ctx, ctypes.c_void_p(f_ptr), ctypes.c_void_p(q_ptr), ctypes.c_void_p(adj_f_ptr),
+                            ctypes.c_void_p(adj_q_ptr), ctypes.c_void_p(dparams_ptr)))
 
 
 def lc_sync(ctx):

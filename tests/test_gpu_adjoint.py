@@ -1,0 +1,158 @@
+"""GPU reverse step and checkpointed gradients.
+
+1. lc_vjp_step against torch autograd of the differentiable CPU twin (which
+   is itself pinned to the C oracle), on a ragged random state.
+2. Gradients of the droplet profile loss sum (S_final - S_target)^2 with
+   respect to gamma, K, Gamma and entries of the initial Q, through
+   checkpoint-and-recompute, against central finite differences of the GPU
+   forward with h = 1e-6: |g_adj - g_fd| <= 1e-6 |g_fd| + floor / h, where
+   the floor is the measured rounding noise of the loss (the second
+   difference L(+h) - 2 L(0) + L(-h), at least eps |L|); and against the
+   Richardson extrapolation of differences at h = 1e-4 and 2e-4.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import torch_step
+from paper_1907_13415_amd import inputs
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def test_vjp_step_matches_autograd_twin():
+    require_gpu()
+    from paper_1907_13415_amd import lc
+    shape = (1, 19, 13)
+    rng = np.random.default_rng(30)
+    p = (0.9, 2.72, 0.06, 0.31, 0.7, 1.3)
+    q5 = inputs.random_q5(shape, rng, amp=0.12)
+    f = oracle.rest_populations(oracle.D2Q9, shape, rel=inputs.random_rel(9, shape, rng, amp=2e-3))
+    af = rng.normal(size=(9,) + shape)
+    aq = rng.normal(size=(5,) + shape)
+    # CPU twin
+    ft = torch.tensor(f[:, 0], requires_grad=True)
+    qt = torch.tensor(q5[:, 0], requires_grad=True)
+    g = torch.tensor(p[1], dtype=torch.float64, requires_grad=True)
+    K = torch.tensor(p[2], dtype=torch.float64, requires_grad=True)
+    G = torch.tensor(p[3], dtype=torch.float64, requires_grad=True)
+    f1, q1 = torch_step.step(ft, qt, p[0], g, K, G, p[4], p[5])
+    ((torch.tensor(af[:, 0]) * f1).sum() + (torch.tensor(aq[:, 0]) * q1).sum()).backward()
+    # GPU
+    s = lc.Solver("D2Q9", "fp64", shape, p)
+    dev = s.device
+    fd = torch.tensor(f, device=dev)
+    qd = torch.tensor(q5, device=dev)
+    afd = torch.tensor(af, device=dev).contiguous()
+    aqd = torch.tensor(aq, device=dev).contiguous()
+    dp = torch.zeros(3, dtype=torch.float64, device=dev)
+    with torch.cuda.stream(s.stream):
+        lc.lc_vjp_step(s.ctx, fd.data_ptr(), qd.data_ptr(), afd.data_ptr(), aqd.data_ptr(), dp.data_ptr())
+    s.stream.synchronize()
+    ef = np.abs(afd.cpu().numpy()[:, 0] - ft.grad.numpy()).max() / np.abs(ft.grad.numpy()).max()
+    eq = np.abs(aqd.cpu().numpy()[:, 0] - qt.grad.numpy()).max() / np.abs(qt.grad.numpy()).max()
+    want = np.array([g.grad.item(), K.grad.item(), G.grad.item()])
+    ep = np.abs(dp.cpu().numpy() - want) / np.maximum(np.abs(want), 1e-12)
+    _say("vjp vs twin: f %.2e Q %.2e params %s" % (ef, eq, ep))
+    assert ef < 1e-12 and eq < 1e-12 and ep.max() < 1e-11
+
+
+def _loss_fn(s_target):
+    def loss(q_final):
+        from paper_1907_13415_amd.adjoint import order_parameter
+        xx, xy, xz, yy, yz = q_final
+        qq = xx * xx + yy * yy + (xx + yy) * (xx + yy) + 2 * (xy * xy + xz * xz + yz * yz)
+        S = torch.sqrt((1.5 * qq).clamp_min(1e-300))
+        return ((S - s_target) ** 2).sum()
+    return loss
+
+
+def _fd_check(n, steps, every, nprobe):
+    from paper_1907_13415_amd import adjoint
+    w = inputs.config4(n)
+    dev = torch.device("cuda:0")
+    A0, gam, K, Gam, xi, tau = w.params
+    cfg = dict(A0=A0, xi=xi, tau=tau, steps=steps, every=every)
+    q0 = torch.tensor(w.q5, device=dev, requires_grad=True)
+    tg = torch.tensor(gam, dtype=torch.float64, requires_grad=True)
+    tK = torch.tensor(K, dtype=torch.float64, requires_grad=True)
+    tG = torch.tensor(Gam, dtype=torch.float64, requires_grad=True)
+    loss = _loss_fn(torch.tensor(w.extra["s_target"], device=dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qf = adjoint.solve(q0, tg, tK, tG, **cfg)
+    L = loss(qf)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _say("n=%d steps=%d: L=%.6e forward %.3f s, backward %.3f s (ratio %.2f)"
+         % (n, steps, L.item(), t1 - t0, t2 - t1, (t2 - t1) / (t1 - t0)))
+
+    def L_of(qinit, g_, K_, G_):
+        with torch.no_grad():
+            f64 = dict(dtype=torch.float64)
+            return loss(adjoint.solve(qinit, torch.tensor(g_, **f64), torch.tensor(K_, **f64),
+                                      torch.tensor(G_, **f64), **cfg)).item()
+
+    L0 = L.item()
+    eps = np.finfo(np.float64).eps
+
+    def check(name, ga, Lp):
+        """Lp(h) evaluates the loss with the probed input moved by h."""
+        h = 1e-6
+        lp, lm = Lp(h), Lp(-h)
+        fd = (lp - lm) / (2 * h)
+        # measured rounding floor of this difference: the second difference
+        # is h^2 L'' (negligible) plus the trajectories' rounding noise
+        noise = max(eps * abs(L0), abs(lp - 2 * L0 + lm))
+        floor = noise / h
+        # Richardson recheck at larger steps: error O(H^4), floor noise/H
+        H = 1e-4
+        d1 = (Lp(H) - Lp(-H)) / (2 * H)
+        d2 = (Lp(2 * H) - Lp(-2 * H)) / (4 * H)
+        rich = (4 * d1 - d2) / 3
+        _say("  %-12s adj %.10e  fd(1e-6) %.10e (floor %.1e)  richardson %.10e" % (name, ga, fd, floor, rich))
+        assert abs(ga - fd) <= 1e-6 * abs(fd) + floor, (name, ga, fd, floor)
+        assert abs(ga - rich) <= 1e-6 * abs(rich) + 2 * noise / H, (name, ga, rich)
+        return abs(ga - rich) / max(abs(rich), 1e-300)
+
+    worst = 0.0
+    for (c, z, y, x) in w.extra["probes"][:nprobe]:
+        def Lp(h, c=c, z=z, y=y, x=x):
+            qp = q0.detach().clone()
+            qp[c, z, y, x] += h
+            return L_of(qp, gam, K, Gam)
+        worst = max(worst, check("Q[%d,%d,%d]" % (c, y, x), q0.grad[c, z, y, x].item(), Lp))
+    for i, (name, t) in enumerate((("gamma", tg), ("K", tK), ("Gamma", tG))):
+        def Lp(h, i=i):
+            args = [gam, K, Gam]
+            args[i] += h
+            return L_of(q0.detach(), *args)
+        worst = max(worst, check("d/d" + name, t.grad.item(), Lp))
+    _say("worst relative deviation from the Richardson estimate: %.2e" % worst)
+    return worst
+
+
+def test_checkpointed_gradients_small_droplet():
+    require_gpu()
+    _fd_check(64, 200, 50, 6)
+
+
+def test_checkpointed_gradients_adjoint_workload():
+    """The 256^2 droplet at delta gamma = 0.005, 2000 steps, checkpoints
+    every 100 steps, 16 seeded probes of the initial Q and all three
+    parameters."""
+    require_gpu()
+    _fd_check(256, 2000, 100, 16)
