@@ -1,19 +1,24 @@
 """Throughput of the hybrid LB / finite-difference step on one MI355X.
 
-Workload: the 256^3 D3Q19 planar nematic slab (random director, 1e-4 noise
-on Q, gamma = 2.7, A0 = 1, K = 0.04, Gamma = 0.3, xi = 0.7, tau = 1) in the
-FP32 deviation storage form; a "step" is one full lattice update (molecular
-field, stress, body force, moments, Heun update of Q, collision, streaming).
-The same grid is also timed in double precision for the FP32/FP64 ratio.
+Headline workload: the 256^3 D3Q19 planar nematic slab (random director,
+1e-4 noise on Q, gamma = 2.7, A0 = 1, K = 0.04, Gamma = 0.3, xi = 0.7,
+tau = 1) in the FP32 deviation storage form.  A step is one full lattice
+update (molecular field, stress, body force, moments, Heun update of Q,
+collision, streaming).  The same grid is timed in double precision for the
+FP32/FP64 ratio and the FP32 error in S.  Also reported: the 64-grid
+temperature sweep in the batched form, and the cost of the checkpointed
+reverse sweep on the 256^2 droplet.
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region;
-timing uses HIP events recorded on the stream the library launches on.
+timings use HIP events recorded on the stream the library launches on.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,6 +28,8 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & %HBM roofline, FP32-dev vs FP64 at stated error; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+COUNTERS = os.path.join(ROOT, "profiles", "split_sweeps_slab256_d3q19_fp32dev_counters.md")
+KERNEL_SOURCES = ["lc_device.h", "lc_staged.h", "lc_split.h"]
 
 
 def alg_bytes_per_site(q, es):
@@ -31,22 +38,30 @@ def alg_bytes_per_site(q, es):
     return 2 * (q + 5) * es
 
 
-def time_steps(lc, torch, solver, steps, warmup):
-    stream = solver.stream
-    solver.step(warmup)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    solver.step(steps)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps  # ms per step
+def kernel_hash():
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1907_13415_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
 
 
-def cpu_baseline(n=128, steps=6):
-    """The oracle (as written) on the host cores: the same slab recipe at
-    n^3 for a few steps."""
+def measured_traffic():
+    """HBM bytes per step from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    if not os.path.exists(COUNTERS):
+        return None
+    txt = open(COUNTERS).read()
+    m = re.search(r"kernel_sources_sha1:\s*([0-9a-f]+)", txt)
+    t = re.search(r"hbm_bytes_per_step:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(n=128, min_s=10.0, max_steps=200):
+    """The oracle (as written) on the host cores: the slab recipe at n^3,
+    one step at a time until about min_s seconds have passed."""
     import numpy as np
     import oracle
     from paper_1907_13415_amd import inputs
@@ -55,11 +70,98 @@ def cpu_baseline(n=128, steps=6):
     f = oracle.rest_populations(oracle.D3Q19, q5.shape[1:])
     oracle.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    steps = 0
     t = time.perf_counter()
-    oracle.run(oracle.D3Q19, f, q5, inputs.WORKLOAD_PARAMS, steps)
+    while steps < max_steps and time.perf_counter() - t < min_s:
+        f, q5 = oracle.run(oracle.D3Q19, f, q5, inputs.WORKLOAD_PARAMS, 1)
+        steps += 1
     dt = time.perf_counter() - t
     return dict(value=round(n ** 3 * steps / dt / 1e6, 4), unit="MLUPS", cores=threads, kind="oracle",
-                sample="oracle FP64, D3Q19 slab recipe at %d^3, %d steps (%.1f s)" % (n, steps, dt))
+                sample="oracle FP64 on the D3Q19 slab recipe at %d^3, %d steps in %.1f s" % (n, steps, dt))
+
+
+def run_slab(torch, lc, w, prec, steps, warmup, dev, stream):
+    with torch.cuda.stream(stream):
+        s = lc.Solver("D3Q19", prec, w.shape, w.params, device=dev, stream=stream)
+        s.load(w.q5)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        lc.lc_set_timing(s.ctx, True)
+        lc.lc_get_timing(s.ctx)  # clear
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        s.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = t0.elapsed_time(t1) / steps
+        ms_k, n_k = lc.lc_get_timing(s.ctx)
+        lc.lc_set_timing(s.ctx, False)
+        S = torch.empty((1,) + w.shape, dtype=torch.float64, device=dev)
+        lc.lc_export(s.ctx, lc.LC_FIELD_S, S.data_ptr())
+        obs = s.observe(half_axis=2)
+        torch.cuda.synchronize()
+        del s
+    return dict(ms=ms_step, kernel_ms=[ms_k[0] / max(n_k[0], 1), ms_k[1] / max(n_k[1], 1)], S=S, obs=obs)
+
+
+def run_batch(torch, lc, stream, dev, steps):
+    from paper_1907_13415_amd import inputs
+    ws = inputs.config3()
+    shapes = [w.shape[1:] for w in ws]
+    with torch.cuda.stream(stream):
+        b = lc.BatchSolver("fp32dev", shapes, [w.params for w in ws], device=dev, stream=stream)
+        for k, w in enumerate(ws):
+            b.load(k, w.q5)
+        tile, _ = b.autotune(10)
+        for k, w in enumerate(ws):
+            b.load(k, w.q5)
+        b.step(64)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        b.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        obs = b.observe()
+    sites = sum(w.shape[1] * w.shape[2] for w in ws)
+    return dict(grids=len(ws), sites=sites, tile=["32x8", "64x4", "16x16"][tile], ms_per_step=round(ms, 5),
+                mlups=round(sites / (ms * 1e-3) / 1e6, 2),
+                roofline_frac=round(alg_bytes_per_site(9, 4) * sites / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                nonfinite=int(sum(o["nonfinite"] for o in obs)))
+
+
+def run_adjoint(torch):
+    from paper_1907_13415_amd import adjoint, inputs
+    w = inputs.config4()
+    dev = torch.device("cuda:0")
+    A0, g, K, G, xi, tau = w.params
+    cfg = dict(A0=A0, xi=xi, tau=tau, steps=w.steps, every=100)
+    f64 = dict(dtype=torch.float64)
+    q0 = torch.tensor(w.q5, device=dev, requires_grad=True)
+    tg, tK, tG = (torch.tensor(v, requires_grad=True, **f64) for v in (g, K, G))
+    st = torch.tensor(w.extra["s_target"], device=dev)
+
+    def loss(qf):
+        xx, xy, xz, yy, yz = qf
+        qq = xx * xx + yy * yy + (xx + yy) * (xx + yy) + 2 * (xy * xy + xz * xz + yz * yz)
+        return ((torch.sqrt((1.5 * qq).clamp_min(1e-300)) - st) ** 2).sum()
+
+    loss(adjoint.solve(q0, tg, tK, tG, **cfg)).backward()  # warm-up
+    q0.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = loss(adjoint.solve(q0, tg, tK, tG, **cfg))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return dict(workload="adjoint_droplet256_d2q9_fp64", steps=w.steps, checkpoint_every=100,
+                forward_s=round(t1 - t0, 4), backward_s=round(t2 - t1, 4),
+                backward_over_forward=round((t2 - t1) / (t1 - t0), 2))
 
 
 def main():
@@ -69,8 +171,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=256, help="edge of the cubic grid")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -92,23 +193,22 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
         return
+
     w = inputs.config2(args.n)
-    res = {}
-    for prec in ("fp32dev",) + (() if args.no_fp64 else ("fp64",)):
-        with torch.cuda.stream(stream):
-            s = lc.Solver("D3Q19", prec, w.shape, w.params, device=dev, stream=stream, variant=args.variant)
-            s.load(w.q5)
-            steps = args.steps if prec == "fp32dev" else max(1, args.steps // 2)
-            ms = time_steps(lc, torch, s, steps, args.warmup)
-            obs = s.observe(half_axis=2)
-            res[prec] = dict(ms=ms, steps=steps, obs=obs)
-            del s
-            torch.cuda.empty_cache()
+    r32 = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream)
+    r64 = run_slab(torch, lc, w, "fp64", args.steps, args.warmup, dev, stream)
+    dS = float((r32["S"] - r64["S"]).abs().max().item())
+    del r32["S"], r64["S"]
+    torch.cuda.empty_cache()
+
     N = args.n ** 3
-    ms32 = res["fp32dev"]["ms"]
+    ms32 = r32["ms"]
     mlups32 = N / (ms32 * 1e-3) / 1e6
+    mlups64 = N / (r64["ms"] * 1e-3) / 1e6
     bytes_site = alg_bytes_per_site(19, 4)
-    achieved = bytes_site * N / (ms32 * 1e-3) / 1e9
+    kernel_ms = sum(r32["kernel_ms"])  # the two sweeps of one step
+    achieved = bytes_site * N / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
     out = {
         "metric": METRIC,
         "value": round(mlups32, 2),
@@ -125,17 +225,21 @@ def main():
         "config": {"workload": "slab%d^3_d3q19_fp32dev" % args.n, "lattice": "D3Q19", "grid": [args.n] * 3,
                    "storage": "fp32 deviation", "gamma": 2.7, "steps_in_config": 500},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_site": bytes_site, "kernel": "whole step"},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "split_lb + split_q (the two launches of one step)",
+                     "bytes_per_site": bytes_site, "sites_per_launch": N,
+                     "kernel_ms": [round(v, 5) for v in r32["kernel_ms"]]},
+        "fp64": {"mlups": round(mlups64, 2), "ms_per_step": round(r64["ms"], 5),
+                 "kernel_ms": [round(v, 5) for v in r64["kernel_ms"]],
+                 "roofline_frac": round(alg_bytes_per_site(19, 8) * N / (sum(r64["kernel_ms"]) * 1e-3) / 1e9
+                                        / HBM_PEAK_GBS, 4)},
+        "fp32_over_fp64": round(mlups32 / mlups64, 3),
+        "fp32_max_abs_dS_vs_fp64": dS,
+        "fp32_steps_compared": args.warmup + args.steps,
     }
-    if "fp64" in res:
-        ms64 = res["fp64"]["ms"]
-        mlups64 = N / (ms64 * 1e-3) / 1e6
-        out["fp64"] = {"mlups": round(mlups64, 2), "ms_per_step": round(ms64, 5),
-                       "roofline_frac": round(alg_bytes_per_site(19, 8) * N / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        out["fp32_over_fp64"] = round(mlups32 / mlups64, 3)
-    out["observables_fp32"] = {k: (float(v) if not hasattr(v, "tolist") else v.tolist())
-                               for k, v in res["fp32dev"]["obs"].items() if k in ("mass", "umax", "ssum_half")}
+    if not args.quick:
+        out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)
+        out["adjoint"] = run_adjoint(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -203,6 +203,14 @@ lc_status lc_vjp_step(lc_ctx *ctx, const double *f_n, const double *Q_n, double 
 /* Wait for the context stream and report any pending device error. */
 lc_status lc_sync(lc_ctx *ctx);
 
+/* Per-launch timing of the step kernels.  While enabled, lc_step records
+ * HIP events on the context stream around each of its two sweeps (split
+ * variant).  lc_get_timing synchronises, returns the summed durations in
+ * milliseconds of sweep 1 (LB update) and sweep 2 (Q update) since the last
+ * call and the number of launches of each, and resets the record. */
+lc_status lc_set_timing(lc_ctx *ctx, int32_t enable);
+lc_status lc_get_timing(lc_ctx *ctx, double *ms /*[2]*/, int64_t *launches /*[2]*/);
+
 /* Steps taken since the last load. */
 int64_t lc_step_count(const lc_ctx *ctx);
 

@@ -26,7 +26,7 @@ template <int LAT, typename S, bool DEV, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
     batch_lb(const BatchDesc<S>* __restrict__ desc, const int* __restrict__ tile_grid, const S* __restrict__ Qa,
              const S* __restrict__ fa, S* __restrict__ fb, S* __restrict__ ua) {
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int k = tile_grid[b];
   const BatchDesc<S> d = desc[k];
   const int t = b - d.tile0;
@@ -39,7 +39,7 @@ template <int LAT, typename S, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY)
     batch_q(const BatchDesc<S>* __restrict__ desc, const int* __restrict__ tile_grid, const S* __restrict__ Qa,
             const S* __restrict__ ua, S* __restrict__ Qb) {
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int k = tile_grid[b];
   const BatchDesc<S> d = desc[k];
   const int t = b - d.tile0;

@@ -141,7 +141,32 @@ struct lc_ctx {
   bool loaded;
   int variant;
   int zchunk;  // 0: default
+  // optional per-launch timing of the step kernels (events on the stream)
+  bool timing;
+  std::vector<hipEvent_t> ev;     // recorded around each launch, 3 per step
+  std::vector<hipEvent_t> pool;   // idle events for reuse
 };
+
+namespace lc {
+static hipEvent_t ctx_event(lc_ctx* c) {
+  hipEvent_t e = nullptr;
+  if (!c->pool.empty()) {
+    e = c->pool.back();
+    c->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+static void ctx_mark(lc_ctx* c) {
+  if (!c->timing) return;
+  hipEvent_t e = ctx_event(c);
+  if (e) {
+    hipEventRecord(e, c->stream);
+    c->ev.push_back(e);
+  }
+}
+}  // namespace lc
 
 // ---------------------------------------------------------------------------
 // Dispatch helpers.
@@ -199,10 +224,13 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
     S* f1 = static_cast<S*>(c->b.f[c->parity ^ 1]);
     const S* q0 = static_cast<const S*>(c->b.Q[c->parity]);
     S* q1 = static_cast<S*>(c->b.Q[c->parity ^ 1]);
+    ctx_mark(c);
     hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, c->stream, q0,
                        f0, f1, u, gd, k, zc);
+    ctx_mark(c);
     hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u, q1, gd,
                        k, zc);
+    ctx_mark(c);
     c->parity ^= 1;
     c->step++;
   }
@@ -385,6 +413,7 @@ lc_status lc_init(const lc_grid* grid, const lc_params* params, const lc_buffers
   c->loaded = false;
   c->variant = LC_VARIANT_SPLIT;
   c->zchunk = 0;
+  c->timing = false;
   *out = c;
   return LC_OK;
 }
@@ -523,8 +552,40 @@ lc_status lc_sync(lc_ctx* c) {
 
 int64_t lc_step_count(const lc_ctx* c) { return c ? c->step : -1; }
 
+lc_status lc_set_timing(lc_ctx* c, int32_t enable) {
+  clear_error();
+  if (!c) return fail(LC_EINVAL, "ctx is NULL");
+  c->timing = enable != 0;
+  return LC_OK;
+}
+
+lc_status lc_get_timing(lc_ctx* c, double* ms, int64_t* launches) {
+  clear_error();
+  if (!c || !ms || !launches) return fail(LC_EINVAL, "NULL argument");
+  ms[0] = ms[1] = 0.0;
+  launches[0] = launches[1] = 0;
+  lc_status st = hip_check(hipStreamSynchronize(c->stream), "timing sync");
+  if (st) return st;
+  // events come in triples per step: before sweep 1, between, after sweep 2
+  for (size_t i = 0; i + 2 < c->ev.size(); i += 3) {
+    float a = 0, b = 0;
+    hipEventElapsedTime(&a, c->ev[i], c->ev[i + 1]);
+    hipEventElapsedTime(&b, c->ev[i + 1], c->ev[i + 2]);
+    ms[0] += a;
+    ms[1] += b;
+    launches[0]++;
+    launches[1]++;
+  }
+  for (hipEvent_t e : c->ev) c->pool.push_back(e);
+  c->ev.clear();
+  return LC_OK;
+}
+
 lc_status lc_free(lc_ctx* c) {
   clear_error();
+  if (!c) return LC_OK;
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  for (hipEvent_t e : c->pool) hipEventDestroy(e);
   delete c;
   return LC_OK;
 }

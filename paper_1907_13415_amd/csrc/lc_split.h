@@ -20,6 +20,16 @@
 
 namespace lc {
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2):
+// hardware block b runs on XCD b % 8.  Remapping b to the logical tile
+// (b % 8) * (nb / 8) + b / 8 gives every XCD one contiguous range of tiles,
+// so neighbouring tiles (which share halo lines) meet in the same L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  if (nb % NUM_XCD != 0) return b;
+  return (b % NUM_XCD) * (nb / NUM_XCD) + b / NUM_XCD;
+}
+
 __device__ __forceinline__ int wrapi(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
@@ -303,7 +313,10 @@ template <int LAT, typename S, bool DEV, int TX, int TY, int WPE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_lb(const S* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ uout,
              GridDims g, Coef<S> c, int zc) {
-  split_lb_body<LAT, S, DEV, TX, TY>(Qin, fin, fout, uout, g, c, zc, blockIdx.x, blockIdx.y, blockIdx.z);
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+  split_lb_body<LAT, S, DEV, TX, TY>(Qin, fin, fout, uout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
+                                     t / (gridDim.x * gridDim.y));
 }
 
 // ---------------------------------------------------------------------------
@@ -454,7 +467,10 @@ template <int LAT, typename S, int TX, int TY, int WPE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_q(const S* __restrict__ Qin, const S* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
             int zc) {
-  split_q_body<LAT, S, TX, TY>(Qin, uin, Qout, g, c, zc, blockIdx.x, blockIdx.y, blockIdx.z);
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+  split_q_body<LAT, S, TX, TY>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
+                               t / (gridDim.x * gridDim.y));
 }
 
 }  // namespace lc

@@ -73,6 +73,8 @@ def _load():
         "lc_export": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
         "lc_sync": ([ctypes.c_void_p], ctypes.c_int32),
         "lc_vjp_step": ([ctypes.c_void_p] * 6, ctypes.c_int32),
+        "lc_set_timing": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+        "lc_get_timing": ([ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)], ctypes.c_int32),
         "lc_step_count": ([ctypes.c_void_p], ctypes.c_int64),
         "lc_free": ([ctypes.c_void_p], ctypes.c_int32),
         "lc_batch_layout": ([ctypes.c_int32, P(lc_grid), P(ctypes.c_size_t), P(ctypes.c_size_t),
@@ -177,6 +179,17 @@ def lc_export(ctx, field, dst_ptr):
 def lc_vjp_step(ctx, f_ptr, q_ptr, adj_f_ptr, adj_q_ptr, dparams_ptr):
     _check(_lib.lc_vjp_step(ctx, ctypes.c_void_p(f_ptr), ctypes.c_void_p(q_ptr), ctypes.c_void_p(adj_f_ptr),
                             ctypes.c_void_p(adj_q_ptr), ctypes.c_void_p(dparams_ptr)))
+
+
+def lc_set_timing(ctx, enable):
+    _check(_lib.lc_set_timing(ctx, 1 if enable else 0))
+
+
+def lc_get_timing(ctx):
+    ms = (ctypes.c_double * 2)()
+    n = (ctypes.c_int64 * 2)()
+    _check(_lib.lc_get_timing(ctx, ms, n))
+    return list(ms), list(n)
 
 
 def lc_sync(ctx):
