@@ -187,32 +187,31 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
   // stress of the whole region of plane slot m into sT[ts]; returns the
   // owner's tau_{a z}
   auto tau_plane = [&](int m, int zp, int zm, int ts, S (&tz)[3]) {
-    {
+    // pass 0: the owner's site; pass 1: a ring site (threads tid < RING).
+    // Both passes run the same code, so every site's stress is rounded the
+    // same way wherever it falls in a tile.
+#pragma unroll 1
+    for (int pass = 0; pass < 2; pass++) {
+      if (pass == 1 && tid >= T::RING) break;
+      int i = tx + 1, j = ty + 1;
+      if (pass == 1) T::ring(tid, i, j);
       S t[3][3];
-      const int i = tx + 1, j = ty + 1;
       tau_point(m, zp, zm, i, j, t);
-      const int kx = i + T::W1 * (j - 1), ky = (i - 1) + TX * j;
-#pragma unroll
-      for (int a = 0; a < DIM; a++) {
-        sTx[ts][a][kx] = t[a][0];
-        sTy[ts][a][ky] = t[a][1];
-      }
-#pragma unroll
-      for (int a = 0; a < 3; a++) tz[a] = t[a][2];
-    }
-    if (tid < T::RING) {
-      S t[3][3];
-      int i, j;
-      T::ring(tid, i, j);
-      tau_point(m, zp, zm, i, j, t);
-      if (j == 0 || j == TY + 1) {  // top and bottom rows feed d/dy
-        const int ky = (i - 1) + TX * j;
-#pragma unroll
-        for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
-      } else {  // left and right columns feed d/dx
+      const bool row_ring = pass == 1 && (j == 0 || j == TY + 1);
+      const bool col_ring = pass == 1 && !row_ring;
+      if (!row_ring) {
         const int kx = i + T::W1 * (j - 1);
 #pragma unroll
         for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = t[a][0];
+      }
+      if (!col_ring) {
+        const int ky = (i - 1) + TX * j;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
+      }
+      if (pass == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) tz[a] = t[a][2];
       }
     }
   };
@@ -379,17 +378,22 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     sP[ps][3][k1] = st.q.yy + st.r.yy;
     sP[ps][4][k1] = st.q.yz + st.r.yz;
   };
-  // predictor over the region; the owner keeps its stash and its Q^P
+  // predictor over the region (pass 0: the owner's site, pass 1: a ring
+  // site, same code for both); the owner keeps its stash and its Q^P
   auto pred_plane = [&](int m, int zp, int zm, int ps, Stash& st, Sym<S>& qp) {
-    pred_point(m, zp, zm, tx + 1, ty + 1, st);
-    store_pred(ps, tx + 1, ty + 1, st);
-    qp = Sym<S>{st.q.xx + st.r.xx, st.q.xy + st.r.xy, st.q.xz + st.r.xz, st.q.yy + st.r.yy, st.q.yz + st.r.yz};
-    if (tid < T::RING) {
-      int i, j;
-      T::ring(tid, i, j);
+#pragma unroll 1
+    for (int pass = 0; pass < 2; pass++) {
+      if (pass == 1 && tid >= T::RING) break;
+      int i = tx + 1, j = ty + 1;
+      if (pass == 1) T::ring(tid, i, j);
       Stash tmp;
       pred_point(m, zp, zm, i, j, tmp);
       store_pred(ps, i, j, tmp);
+      if (pass == 0) {
+        st = tmp;
+        qp = Sym<S>{tmp.q.xx + tmp.r.xx, tmp.q.xy + tmp.r.xy, tmp.q.xz + tmp.r.xz, tmp.q.yy + tmp.r.yy,
+                    tmp.q.yz + tmp.r.yz};
+      }
     }
   };
   // corrector at the owner's site of plane z

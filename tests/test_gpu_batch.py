@@ -145,3 +145,21 @@ def test_temperature_sweep_workload_full_size():
         assert np.array_equal(b.export(k, lc.LC_FIELD_F), s.export(lc.LC_FIELD_F)), k
     obs = b.observe()
     assert all(o["nonfinite"] == 0 for o in obs)
+
+
+def test_batch_tile_shapes_agree_bitwise():
+    """Every site runs the same code wherever it falls in a tile, so the three
+    tile shapes give identical results."""
+    lc = _lc()
+    q5s, params = _batch_inputs(4)
+    res = []
+    for v in range(3):
+        b = lc.BatchSolver("fp32dev", SHAPES, params)
+        b.set_tile(v)
+        for k, q5 in enumerate(q5s):
+            b.load(k, q5)
+        b.step(70)
+        res.append([b.export(k, lc.LC_FIELD_Q) for k in range(len(SHAPES))])
+    for v in (1, 2):
+        for k in range(len(SHAPES)):
+            assert np.array_equal(res[0][k], res[v][k]), (v, k)

@@ -240,3 +240,44 @@ def test_full_size_droplet_256sq_fp64(prec):
     s.step(200)
     f_ref, q_ref = oracle.run(0, oracle.rest_populations(0, w.shape), w.q5, w.params, 200)
     _compare_state(lc, s, f_ref, q_ref, TOL64, "droplet 256^2 step 200")
+
+
+@pytest.mark.parametrize("lat,shape", [(0, (1, 40, 56)), (1, (12, 10, 14))])
+def test_resume_from_export_is_bitexact(lat, shape):
+    """Checkpoint/resume: n steps equal n/2 steps, lc_export of (f, Q), a
+    fresh context, lc_load_state and n/2 more steps, bit for bit (FP64)."""
+    lc = _lc()
+    rng = np.random.default_rng(50 + lat)
+    q5 = inputs.random_q5(shape, rng, amp=0.1)
+    p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
+    name = "D2Q9" if lat == 0 else "D3Q19"
+    a = lc.Solver(name, "fp64", shape, p)
+    a.load(q5)
+    a.step(40)
+    b = lc.Solver(name, "fp64", shape, p)
+    b.load(q5)
+    b.step(20)
+    f_mid, q_mid = b.export(lc.LC_FIELD_F), b.export(lc.LC_FIELD_Q)
+    c = lc.Solver(name, "fp64", shape, p)
+    c.load(q_mid, f_mid)
+    c.step(20)
+    assert np.array_equal(a.export(lc.LC_FIELD_F), c.export(lc.LC_FIELD_F))
+    assert np.array_equal(a.export(lc.LC_FIELD_Q), c.export(lc.LC_FIELD_Q))
+    assert c.observe()["step"] == 20
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_shift_equivariance_on_gpu_bitexact(variant):
+    """A one-site periodic shift of the initial state shifts the result bit
+    for bit (per-site arithmetic does not depend on the tile position)."""
+    lc = _lc()
+    shape = (20, 24, 40)
+    rng = np.random.default_rng(60)
+    q5 = inputs.random_q5(shape, rng, amp=0.1)
+    out = []
+    for sh in (0, 1):
+        s = _solver(lc, 1, "fp64", shape, (1.0, 2.72, 0.05, 0.3, 0.7, 1.3), variant)
+        s.load(np.roll(q5, sh, axis=3))
+        s.step(6)
+        out.append(s.export(lc.LC_FIELD_Q))
+    assert np.array_equal(np.roll(out[0], 1, axis=3), out[1])
