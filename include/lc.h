@@ -200,6 +200,20 @@ lc_status lc_export(lc_ctx *ctx, int32_t field, double *dst_dev);
 lc_status lc_vjp_step(lc_ctx *ctx, const double *f_n, const double *Q_n, double *adj_f, double *adj_Q,
                       double *dparams);
 
+/* Bytes of the state history lc_vjp_segment needs for n steps (0 on bad
+ * arguments). */
+size_t lc_vjp_history_bytes(const lc_grid *grid, int32_t n);
+
+/* Reverse sweep over one checkpoint segment (D2Q9, LC_FP64): starting from
+ * the checkpoint state (f_ck, Q_ck: device arrays of double logical values),
+ * replay n - 1 steps keeping every state in `hist` (caller-owned device
+ * buffer of lc_vjp_history_bytes(grid, n) bytes, 256-byte aligned), then
+ * apply the n reverse steps n-1 .. 0 to (adj_f, adj_Q) in place, adding the
+ * parameter derivatives to dparams[3] as lc_vjp_step does.  The context's
+ * own state is not modified.  Asynchronous. */
+lc_status lc_vjp_segment(lc_ctx *ctx, const double *f_ck, const double *Q_ck, int32_t n, void *hist,
+                         double *adj_f, double *adj_Q, double *dparams);
+
 /* Wait for the context stream and report any pending device error. */
 lc_status lc_sync(lc_ctx *ctx);
 

@@ -70,18 +70,11 @@ class LCSolve(torch.autograd.Function):
             adj_f = torch.zeros((9,) + shape, dtype=torch.float64, device=dev)
             dparams = torch.zeros(3, dtype=torch.float64, device=dev)
             every = max(n for _, _, n in ctx.checkpoints)
-            hist_f = torch.empty((every, 9) + shape, dtype=torch.float64, device=dev)
-            hist_q = torch.empty((every, 5) + shape, dtype=torch.float64, device=dev)
+            hist = torch.empty(lc.lc_vjp_history_bytes(s.grid, every), dtype=torch.uint8, device=dev)
             for f_ck, q_ck, n in reversed(ctx.checkpoints):
-                lc.lc_load_state(s.ctx, f_ck.data_ptr(), q_ck.data_ptr())
-                for j in range(n):
-                    lc.lc_export(s.ctx, lc.LC_FIELD_F, hist_f[j].data_ptr())
-                    lc.lc_export(s.ctx, lc.LC_FIELD_Q, hist_q[j].data_ptr())
-                    if j + 1 < n:
-                        s.step(1)
-                for j in reversed(range(n)):
-                    lc.lc_vjp_step(s.ctx, hist_f[j].data_ptr(), hist_q[j].data_ptr(), adj_f.data_ptr(),
-                                   adj_q.data_ptr(), dparams.data_ptr())
+                # replay the segment from its checkpoint, then walk it back
+                lc.lc_vjp_segment(s.ctx, f_ck.data_ptr(), q_ck.data_ptr(), n, hist.data_ptr(), adj_f.data_ptr(),
+                                  adj_q.data_ptr(), dparams.data_ptr())
         s.stream.synchronize()
         return adj_q, dparams[0], dparams[1], dparams[2], None
 

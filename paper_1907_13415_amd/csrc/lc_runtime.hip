@@ -226,10 +226,10 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
     S* q1 = static_cast<S*>(c->b.Q[c->parity ^ 1]);
     ctx_mark(c);
     hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, c->stream, q0,
-                       f0, f1, u, gd, k, zc);
+                       f0, f1, u, gd, k, zc, static_cast<S*>(nullptr));
     ctx_mark(c);
     hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u, q1, gd,
-                       k, zc);
+                       k, zc, static_cast<S*>(nullptr));
     ctx_mark(c);
     c->parity ^= 1;
     c->step++;
@@ -491,15 +491,12 @@ lc_status lc_export(lc_ctx* c, int32_t field, double* dst) {
   return LC_DISPATCH(c, do_export, field, dst);
 }
 
-lc_status lc_vjp_step(lc_ctx* c, const double* f_n, const double* q_n, double* adj_f, double* adj_q,
-                      double* dparams) {
-  clear_error();
-  if (!c || !f_n || !q_n || !adj_f || !adj_q || !dparams) return fail(LC_EINVAL, "NULL argument");
-  if (c->g.lattice != LC_D2Q9 || c->g.precision != LC_FP64)
-    return fail(LC_EUNSUPPORTED, "the reverse step is provided for D2Q9 in double precision");
-  const GridDims gd{c->g.nx, c->g.ny, 1, c->L.N};
+}  // extern "C"
+
+namespace lc {
+
+static VjpFields vjp_fields(lc_ctx* c) {
   const int64_t N = c->L.N;
-  const Coef<double> k = make_coef<double>(c->p);
   double* base = reinterpret_cast<double*>(static_cast<char*>(c->b.scratch) + c->L.off_vjp);
   VjpFields v;
   double* p = base;
@@ -528,20 +525,130 @@ lc_status lc_vjp_step(lc_ctx* c, const double* f_n, const double* q_n, double* a
   v.fbar2 = take(2);
   v.lb = take(5);
   v.nblocks = c->L.nblocks;
-  v.part = base + size_t(VJP_COMPS) * N;
-  // keep the partials 256-byte aligned as laid out
-  v.part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(v.part) + 255) & ~uintptr_t(255));
+  // the partials follow at the next 256-byte boundary, as laid out
+  v.part = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(base + size_t(VJP_COMPS) * N) + 255) &
+                                     ~uintptr_t(255));
+  return v;
+}
+
+// The five reverse kernels of one step, given the forward quantities of
+// that step in v (rho, u, F, predictor); parameter partials accumulate.
+static void vjp_reverse(lc_ctx* c, const VjpFields& v, const double* q_n, double* adj_f, double* adj_q) {
+  const GridDims gd{c->g.nx, c->g.ny, 1, c->L.N};
+  const Coef<double> k = make_coef<double>(c->p);
   const dim3 grid = site_grid(c->g), block = site_block();
-  hipLaunchKernelGGL((stage_tau<0, double>), grid, block, 0, c->stream, q_n, v.tau, gd, k);
-  hipLaunchKernelGGL(vjp_fwd_moments, grid, block, 0, c->stream, f_n, v.tau, v, gd);
-  hipLaunchKernelGGL((stage_pred<0, double>), grid, block, 0, c->stream, q_n, v.u, v.qp, v.r, gd, k);
   hipLaunchKernelGGL(vjp_r1, grid, block, 0, c->stream, adj_f, adj_q, v, gd, k);
   hipLaunchKernelGGL(vjp_r2, grid, block, 0, c->stream, q_n, adj_q, v, gd, k);
   hipLaunchKernelGGL(vjp_r3, grid, block, 0, c->stream, adj_f, v, gd);
   hipLaunchKernelGGL(vjp_r4, grid, block, 0, c->stream, q_n, v, gd, k);
   hipLaunchKernelGGL(vjp_r5, grid, block, 0, c->stream, adj_q, v, gd);
-  hipLaunchKernelGGL(vjp_params, dim3(1), dim3(64), 0, c->stream, v.part, v.nblocks, dparams);
+}
+
+static void vjp_begin(lc_ctx* c, const VjpFields& v) {
+  hipLaunchKernelGGL(vjp_zero, dim3(8), dim3(256), 0, c->stream, v.part, 3 * v.nblocks * 3);
+}
+
+static void vjp_end(lc_ctx* c, const VjpFields& v, double* dparams) {
+  hipLaunchKernelGGL(vjp_params, dim3(1), dim3(256), 0, c->stream, v.part, v.nblocks, dparams);
+}
+
+// One reverse step from a logical state: recompute the forward quantities,
+// then reverse.
+static void vjp_launch(lc_ctx* c, const double* f_n, const double* q_n, double* adj_f, double* adj_q,
+                       double* dparams) {
+  const GridDims gd{c->g.nx, c->g.ny, 1, c->L.N};
+  const Coef<double> k = make_coef<double>(c->p);
+  VjpFields v = vjp_fields(c);
+  const dim3 grid = site_grid(c->g), block = site_block();
+  vjp_begin(c, v);
+  hipLaunchKernelGGL((stage_tau<0, double>), grid, block, 0, c->stream, q_n, v.tau, gd, k);
+  hipLaunchKernelGGL(vjp_fwd_moments, grid, block, 0, c->stream, f_n, 0, v.tau, v, gd);
+  hipLaunchKernelGGL((stage_pred<0, double>), grid, block, 0, c->stream, q_n, v.u, v.qp, v.r, gd, k);
+  vjp_reverse(c, v, q_n, adj_f, adj_q);
+  vjp_end(c, v, dparams);
+}
+
+// One forward step of the split sweeps between explicit buffers (pull-form
+// populations), using the context's velocity scratch.
+template <int LAT, typename S, bool DEV>
+static void step_split_ptrs(lc_ctx* c, const S* f0, const S* q0, S* f1, S* q1, S* u, S* rec_lb, S* rec_q) {
+  using C = SplitCfg<LAT, S>;
+  const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
+  const Coef<S> k = make_coef<S>(c->p);
+  const int zc = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC) : 1;
+  const unsigned gz = unsigned((c->g.nz + zc - 1) / zc);
+  const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY, gz);
+  const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY, gz);
+  hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0,
+                     c->stream, q0, f0, f1, u, gd, k, zc, rec_lb);
+  hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u,
+                     q1, gd, k, zc, rec_q);
+}
+
+static lc_status vjp_check(lc_ctx* c) {
+  if (c->g.lattice != LC_D2Q9 || c->g.precision != LC_FP64)
+    return fail(LC_EUNSUPPORTED, "the reverse step is provided for D2Q9 in double precision");
+  return LC_OK;
+}
+
+}  // namespace lc
+
+extern "C" {
+
+lc_status lc_vjp_step(lc_ctx* c, const double* f_n, const double* q_n, double* adj_f, double* adj_q,
+                      double* dparams) {
+  clear_error();
+  if (!c || !f_n || !q_n || !adj_f || !adj_q || !dparams) return fail(LC_EINVAL, "NULL argument");
+  lc_status st = vjp_check(c);
+  if (st) return st;
+  vjp_launch(c, f_n, q_n, adj_f, adj_q, dparams);
   return hip_check(hipGetLastError(), "reverse step launch");
+}
+
+size_t lc_vjp_history_bytes(const lc_grid* grid, int32_t n) {
+  if (!grid || n < 1 || check_grid(grid) != LC_OK) return 0;
+  const size_t N = size_t(grid->nx) * grid->ny * grid->nz;
+  const size_t q = size_t(lattice_q(grid->lattice));
+  const size_t es = grid->precision == LC_FP64 ? 8 : 4;
+  // per step: populations, Q, and the recorded u, rho, F and predictor
+  return size_t(n + 1) * (q + 5 + 10) * N * es;
+}
+
+lc_status lc_vjp_segment(lc_ctx* c, const double* f_ck, const double* q_ck, int32_t n, void* hist, double* adj_f,
+                         double* adj_q, double* dparams) {
+  clear_error();
+  if (!c || !f_ck || !q_ck || !hist || !adj_f || !adj_q || !dparams) return fail(LC_EINVAL, "NULL argument");
+  if (n < 1) return fail(LC_EINVAL, "n must be >= 1");
+  lc_status st = vjp_check(c);
+  if (st) return st;
+  if (reinterpret_cast<uintptr_t>(hist) & 255) return fail(LC_EINVAL, "history must be 256-byte aligned");
+  const int64_t N = c->L.N;
+  double* h = static_cast<double*>(hist);
+  // slot j: f (9N, pull form), Q (5N), u (2N), rho and F (3N), Q^P (5N)
+  auto slot = [&](int j) { return h + size_t(j) * 24 * N; };
+  auto fslot = [&](int j) { return slot(j); };
+  auto qslot = [&](int j) { return slot(j) + 9 * size_t(N); };
+  auto uslot = [&](int j) { return slot(j) + 14 * size_t(N); };
+  auto rslot = [&](int j) { return slot(j) + 16 * size_t(N); };
+  auto pslot = [&](int j) { return slot(j) + 19 * size_t(N); };
+  const GridDims gd{c->g.nx, c->g.ny, 1, N};
+  hipLaunchKernelGGL((load_state<0, double, false>), site_grid(c->g), site_block(), 0, c->stream, f_ck, q_ck,
+                     fslot(0), qslot(0), gd);
+  // replay every step of the segment, recording its forward quantities
+  for (int j = 0; j < n; j++)
+    step_split_ptrs<0, double, false>(c, fslot(j), qslot(j), fslot(j + 1), qslot(j + 1), uslot(j), rslot(j), pslot(j));
+  VjpFields v = vjp_fields(c);
+  vjp_begin(c, v);
+  for (int j = n - 1; j >= 0; j--) {
+    v.u = uslot(j);
+    v.rho = rslot(j);
+    v.F = rslot(j) + N;
+    v.qp = pslot(j);
+    vjp_reverse(c, v, qslot(j), adj_f, adj_q);
+  }
+  vjp_end(c, v, dparams);
+  // the context's own state is untouched
+  return hip_check(hipGetLastError(), "reverse segment launch");
 }
 
 lc_status lc_sync(lc_ctx* c) {

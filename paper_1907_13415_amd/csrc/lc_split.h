@@ -157,7 +157,8 @@ __device__ __forceinline__ void store_region(const RegionRegs<S, TX, TY, NC>& r,
 template <int LAT, typename S, bool DEV, int TX, int TY>
 __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S* __restrict__ fin,
                                               S* __restrict__ fout, S* __restrict__ uout, const GridDims& g,
-                                              const Coef<S>& c, int zc, int bx, int by, int bz) {
+                                              const Coef<S>& c, int zc, int bx, int by, int bz,
+                                              S* __restrict__ rec = nullptr) {
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
   constexpr int DIM = L::dim;
@@ -266,6 +267,11 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
     moments<LAT, S, DEV>(f, F, rho, u);
 #pragma unroll
     for (int a = 0; a < DIM; a++) (uout + size_t(a) * size_t(N))[s] = u[a];
+    if (rec) {  // record rho and F of this step (reverse-mode replay)
+      rec[s] = rho;
+#pragma unroll
+      for (int a = 0; a < DIM; a++) (rec + size_t(a + 1) * size_t(N))[s] = F[a];
+    }
     collide_pairs<LAT, S, DEV>(f, rho, u, F, c);
 #pragma unroll
     for (int i = 0; i < L::q; i++) (fout + size_t(i) * size_t(N))[s] = f[i];
@@ -311,11 +317,11 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
 template <int LAT, typename S, bool DEV, int TX, int TY, int WPE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_lb(const S* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ uout,
-             GridDims g, Coef<S> c, int zc) {
+             GridDims g, Coef<S> c, int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
   split_lb_body<LAT, S, DEV, TX, TY>(Qin, fin, fout, uout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
-                                     t / (gridDim.x * gridDim.y));
+                                     t / (gridDim.x * gridDim.y), rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -323,7 +329,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
 template <int LAT, typename S, int TX, int TY>
 __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S* __restrict__ uin,
                                              S* __restrict__ Qout, const GridDims& g, const Coef<S>& c, int zc,
-                                             int bx, int by, int bz) {
+                                             int bx, int by, int bz, S* __restrict__ rec = nullptr) {
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
   constexpr int DIM = L::dim;
@@ -428,6 +434,7 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     const Sym<S> H = molecular_field(p, Lp, c);
     const Sym<S> Rp = be_rate(p, H, d, st.u, st.G, c);
     const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+    if (rec) store_sym(rec, N, s, p);  // record the predictor (reverse-mode replay)
     Qout[s] = st.q.xx + S(0.5) * (st.r.xx + Rp.xx);
     Qout[N + s] = st.q.xy + S(0.5) * (st.r.xy + Rp.xy);
     Qout[2 * N + s] = st.q.xz + S(0.5) * (st.r.xz + Rp.xz);
@@ -470,11 +477,11 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
 template <int LAT, typename S, int TX, int TY, int WPE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_q(const S* __restrict__ Qin, const S* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
-            int zc) {
+            int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
   split_q_body<LAT, S, TX, TY>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
-                               t / (gridDim.x * gridDim.y));
+                               t / (gridDim.x * gridDim.y), rec);
 }
 
 }  // namespace lc

@@ -44,8 +44,14 @@ __device__ __forceinline__ void block_reduce3(double (&v)[3], double* __restrict
   if (tid < 3) {
     double acc = part[0][tid];
     for (int w = 1; w < nw; w++) acc += part[w][tid];
-    dst[tid] = acc;
+    dst[tid] += acc;  // accumulate over the reverse steps of one call
   }
+}
+
+// zero the per-block parameter partials before a reverse call
+__global__ void __launch_bounds__(256) vjp_zero(double* __restrict__ part, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    part[i] = 0.0;
 }
 
 // Laplacian and minus-divergence gathers of adjoint fields at site s.
@@ -98,17 +104,22 @@ __device__ __forceinline__ void velgrad2(const double* __restrict__ u, int64_t N
   const Nbr nb = neighbours(in ? x : 0, in ? y : 0, 0, g.nx, g.ny, 1);   \
   const int64_t blk = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
 
-// density, force-corrected velocity and body force from logical f and tau
-__global__ void __launch_bounds__(256) vjp_fwd_moments(const double* __restrict__ f, const double* __restrict__ tau,
-                                                       VjpFields v, GridDims g) {
+// density, force-corrected velocity and body force from f and tau; f is
+// either logical (pull == 0) or a population buffer in pull form
+__global__ void __launch_bounds__(256) vjp_fwd_moments(const double* __restrict__ f, int pull,
+                                                       const double* __restrict__ tau, VjpFields v, GridDims g) {
   LC_SITE_2D
   (void)blk;
   if (!in) return;
   double F[3];
   body_force<0, double>(tau, N, s, nb, F);
   double ff[9];
+  if (pull) {
+    gather_f<0, double>(f, N, s, nb, ff);
+  } else {
 #pragma unroll
-  for (int i = 0; i < 9; i++) ff[i] = f[i * N + s];
+    for (int i = 0; i < 9; i++) ff[i] = f[i * N + s];
+  }
   double rho, u[3];
   moments<0, double, false>(ff, F, rho, u);
   v.rho[s] = rho;
@@ -273,14 +284,22 @@ __global__ void __launch_bounds__(256) vjp_r5(double* __restrict__ adj_q, VjpFie
   put5(adj_q, N, s, qb);
 }
 
-// parameter partials of the three kernels, added to dparams in fixed order
-__global__ void __launch_bounds__(64) vjp_params(const double* __restrict__ part, int64_t nblocks,
-                                                 double* __restrict__ dparams) {
-  const int k = threadIdx.x;
-  if (k >= 3) return;
-  double acc = 0.0;
-  for (int64_t b = 0; b < 3 * nblocks; b++) acc += part[b * 3 + k];
-  dparams[k] += acc;
+// parameter partials of the three kernels, added to dparams: each thread
+// sums a fixed strided subset, then a fixed-order block reduction
+// (deterministic for a fixed launch shape).
+__global__ void __launch_bounds__(256) vjp_params(const double* __restrict__ part, int64_t nblocks,
+                                                  double* __restrict__ dparams) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int64_t b = threadIdx.x; b < 3 * nblocks; b += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) v[k] += part[b * 3 + k];
+  }
+  __shared__ double tot[3];
+  if (threadIdx.x < 3) tot[threadIdx.x] = 0.0;
+  __syncthreads();
+  block_reduce3(v, tot);
+  __syncthreads();
+  if (threadIdx.x < 3) dparams[threadIdx.x] += tot[threadIdx.x];
 }
 
 }  // namespace lc

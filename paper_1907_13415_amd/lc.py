@@ -73,6 +73,9 @@ def _load():
         "lc_export": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
         "lc_sync": ([ctypes.c_void_p], ctypes.c_int32),
         "lc_vjp_step": ([ctypes.c_void_p] * 6, ctypes.c_int32),
+        "lc_vjp_history_bytes": ([P(lc_grid), ctypes.c_int32], ctypes.c_size_t),
+        "lc_vjp_segment": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 4,
+                           ctypes.c_int32),
         "lc_set_timing": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
         "lc_get_timing": ([ctypes.c_void_p, P(ctypes.c_double), P(ctypes.c_int64)], ctypes.c_int32),
         "lc_step_count": ([ctypes.c_void_p], ctypes.c_int64),
@@ -179,6 +182,16 @@ def lc_export(ctx, field, dst_ptr):
 def lc_vjp_step(ctx, f_ptr, q_ptr, adj_f_ptr, adj_q_ptr, dparams_ptr):
     _check(_lib.lc_vjp_step(ctx, ctypes.c_void_p(f_ptr), ctypes.c_void_p(q_ptr), ctypes.c_void_p(adj_f_ptr),
                             ctypes.c_void_p(adj_q_ptr), ctypes.c_void_p(dparams_ptr)))
+
+
+def lc_vjp_history_bytes(grid, n):
+    return _lib.lc_vjp_history_bytes(ctypes.byref(grid), int(n))
+
+
+def lc_vjp_segment(ctx, f_ck_ptr, q_ck_ptr, n, hist_ptr, adj_f_ptr, adj_q_ptr, dparams_ptr):
+    _check(_lib.lc_vjp_segment(ctx, ctypes.c_void_p(f_ck_ptr), ctypes.c_void_p(q_ck_ptr), int(n),
+                               ctypes.c_void_p(hist_ptr), ctypes.c_void_p(adj_f_ptr), ctypes.c_void_p(adj_q_ptr),
+                               ctypes.c_void_p(dparams_ptr)))
 
 
 def lc_set_timing(ctx, enable):
