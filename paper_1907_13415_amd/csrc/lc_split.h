@@ -333,7 +333,12 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
   constexpr int DIM = L::dim;
-  constexpr int NP = DIM == 3 ? 3 : 1;
+  // In single precision a four-plane ring: the plane stored at iteration
+  // p+1 is never one the predictor of iteration p reads, so one barrier per
+  // plane suffices.  Double precision keeps three planes (LDS) and a second
+  // barrier.
+  constexpr bool RING4 = DIM == 3 && sizeof(S) == 4;
+  constexpr int NP = DIM == 3 ? (RING4 ? 4 : 3) : 1;
   constexpr int NC = 5 + DIM;  // Q components then u components
   constexpr int NPP = DIM == 3 ? 2 : 1;
   __shared__ S sQ[NP][NC][T::R2];
@@ -453,7 +458,7 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   } else {
     const int zb = bz * zc;
     const int ze = min(zb + zc, g.nz);
-    auto slot = [](int p) { return (p + 3) % 3; };
+    auto slot = [](int p) { return (p + NP) % NP; };  // p >= -NP
     RegionRegs<S, TX, TY, NC> rq;
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 2)][0][0], csrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 1)][0][0], csrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
@@ -461,11 +466,16 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     Stash stB, stC;  // planes p-1 and p
     Sym<S> qpA = sym_zero<S>(), qpB = sym_zero<S>(), qpC;
     for (int p = zb - 1; p <= ze; p++) {
+      // with four slots, slot(p+1) was last read by the predictor of
+      // iteration p-2, which every thread finished before the barrier of
+      // iteration p-1 (with three, the second barrier below protects it)
       store_region<S, TX, TY, NC>(rq, &sQ[slot(p + 1)][0][0], tid);
       if (p + 2 <= ze + 1) fetch_region<S, TX, TY, NC>(rq, csrc, x0, y0, wrapi(p + 2, g.nz), g, tid);
       __syncthreads();
+      // the predictor writes sP[p & 1], last read by the corrector of
+      // iteration p-1, which precedes the barrier above
       pred_plane(slot(p), slot(p + 1), slot(p - 1), p & 1, stC, qpC);
-      __syncthreads();
+      if constexpr (!RING4) __syncthreads();
       if (p - 1 >= zb) corr_site(p - 1, (p - 1) & 1, stB, qpC, qpA);
       qpA = qpB;
       qpB = qpC;
