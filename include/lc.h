@@ -88,7 +88,7 @@ typedef struct {
 
 /* Caller-owned device buffers.  f[0], f[1]: q*N values each; Q[0], Q[1]:
  * 5*N values each (element size 8 for LC_FP64, 4 for LC_FP32_DEV);
- * scratch: lc_scratch_bytes() bytes.  All 256-byte aligned, disjoint, and
+ * scratch: the scratch_bytes reported by lc_buffer_bytes.  All 256-byte aligned, disjoint, and
  * valid for the lifetime of the context. */
 typedef struct {
   void *f[2];

@@ -161,22 +161,27 @@ LC_HD void stress(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
 //   R = Gamma H + S - (u.grad) Q,
 //   S = A + A^T - 2 xi (Q + I/3)(Q:G),  A = [xi D + W](Q + I/3),
 // with G[a][b] = d_b u_a, so xi D + W = (xi+1)/2 G + (xi-1)/2 G^T.
-template <typename T>
+// With RAW set, dQ and G are undivided central differences (twice the
+// derivatives) and u is halved: the same rate up to rounding (the factors
+// of two are exact; the compiler's contraction into FMAs may differ), with
+// the halvings saved.
+template <typename T, bool RAW = false>
 LC_HD Sym<T> be_rate(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
                                           const T (&u)[3], const T (&G)[3][3], const Coef<T>& c) {
   const T Qp[3][3] = {{Q.xx + T(1.0 / 3.0), Q.xy, Q.xz},
                       {Q.xy, Q.yy + T(1.0 / 3.0), Q.yz},
                       {Q.xz, Q.yz, Q.zz() + T(1.0 / 3.0)}};
+  const T xp = RAW ? c.xi_p * T(0.5) : c.xi_p, xm = RAW ? c.xi_m * T(0.5) : c.xi_m;
   T B[3][3];
 #pragma unroll
   for (int a = 0; a < 3; a++)
 #pragma unroll
-    for (int b = 0; b < 3; b++) B[a][b] = c.xi_p * G[a][b] + c.xi_m * G[b][a];
+    for (int b = 0; b < 3; b++) B[a][b] = xp * G[a][b] + xm * G[b][a];
   // A = B Qp; only the entries needed for the five stored components of S.
   auto A = [&](int a, int b) { return B[a][0] * Qp[0][b] + B[a][1] * Qp[1][b] + B[a][2] * Qp[2][b]; };
   const T qg = Q.xx * G[0][0] + Q.yy * G[1][1] + Q.zz() * G[2][2] + Q.xy * (G[0][1] + G[1][0]) +
                Q.xz * (G[0][2] + G[2][0]) + Q.yz * (G[1][2] + G[2][1]);
-  const T k = T(2) * c.xi * qg;
+  const T k = RAW ? c.xi * qg : T(2) * c.xi * qg;
   Sym<T> R;
   R.xx = c.Gam * H.xx + T(2) * A(0, 0) - k * Qp[0][0] -
          (u[0] * dQ[0].xx + u[1] * dQ[1].xx + u[2] * dQ[2].xx);

@@ -162,7 +162,7 @@ static void ctx_mark(lc_ctx* c) {
   if (!c->timing) return;
   hipEvent_t e = ctx_event(c);
   if (e) {
-    hipEventRecord(e, c->stream);
+    (void)hipEventRecord(e, c->stream);
     c->ev.push_back(e);
   }
 }
@@ -195,42 +195,52 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
   return hip_check(hipGetLastError(), "step launch");
 }
 
-// Tile shapes of the two-sweep kernels (LDS per block stays below 64 KB).
+// Tile shapes of the two-sweep kernels (measured on 256^3; LDS per block at
+// most 76 KB, so at least two blocks fit a CU).
 template <int LAT, typename S>
 struct SplitCfg {
   static constexpr bool d3 = Lattice<LAT>::dim == 3;
   static constexpr bool f64 = sizeof(S) == 8;
-  static constexpr int LB_TX = 32, LB_TY = (d3 && f64) ? 4 : 8;
+  static constexpr int LB_TX = (d3 && !f64) ? 64 : 32, LB_TY = (d3 && !f64) ? 4 : 8;
   static constexpr int Q_TX = (d3 && f64) ? 16 : 32, Q_TY = 8;
-  static constexpr int ZC = f64 ? 32 : 128;  // measured best on 256^3
-  // waves per SIMD the register allocation is held to (LDS allows 4 blocks
+  // planes per block along z in each sweep
+  static constexpr int ZC_LB = f64 ? 16 : 128, ZC_Q = 128;
+  // waves per SIMD the register allocation is held to (LDS allows 3 blocks
   // of the single-precision 3D stress sweep per CU)
-  static constexpr int LB_WPE = (d3 && !f64) ? 4 : 1;
+  static constexpr int LB_WPE = (d3 && !f64) ? 3 : 1;
   static constexpr int Q_WPE = 1;
 };
 
+// One step of the split sweeps between explicit buffers (pull-form
+// populations); u receives the force-corrected velocity.  rec_lb / rec_q,
+// when not null, record rho and F / the predictor for reverse-mode replay.
 template <int LAT, typename S, bool DEV>
-static lc_status run_steps_split(lc_ctx* c, int64_t n) {
+static void step_split_ptrs(lc_ctx* c, const S* f0, const S* q0, S* f1, S* q1, S* u, S* rec_lb, S* rec_q) {
   using C = SplitCfg<LAT, S>;
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = make_coef<S>(c->p);
+  const int zc1 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_LB) : 1;
+  const int zc2 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_Q) : 1;
+  const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY,
+                unsigned((c->g.nz + zc1 - 1) / zc1));
+  const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY,
+                unsigned((c->g.nz + zc2 - 1) / zc2));
+  ctx_mark(c);
+  hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0,
+                     c->stream, q0, f0, f1, u, gd, k, zc1, rec_lb);
+  ctx_mark(c);
+  hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u,
+                     q1, gd, k, zc2, rec_q);
+  ctx_mark(c);
+}
+
+template <int LAT, typename S, bool DEV>
+static lc_status run_steps_split(lc_ctx* c, int64_t n) {
   S* u = reinterpret_cast<S*>(static_cast<char*>(c->b.scratch) + c->L.off_u);
-  const int zc = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC) : 1;
-  const unsigned gz = unsigned((c->g.nz + zc - 1) / zc);
-  const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY, gz);
-  const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY, gz);
   for (int64_t it = 0; it < n; it++) {
-    const S* f0 = static_cast<const S*>(c->b.f[c->parity]);
-    S* f1 = static_cast<S*>(c->b.f[c->parity ^ 1]);
-    const S* q0 = static_cast<const S*>(c->b.Q[c->parity]);
-    S* q1 = static_cast<S*>(c->b.Q[c->parity ^ 1]);
-    ctx_mark(c);
-    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, c->stream, q0,
-                       f0, f1, u, gd, k, zc, static_cast<S*>(nullptr));
-    ctx_mark(c);
-    hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u, q1, gd,
-                       k, zc, static_cast<S*>(nullptr));
-    ctx_mark(c);
+    step_split_ptrs<LAT, S, DEV>(c, static_cast<const S*>(c->b.f[c->parity]),
+                                 static_cast<const S*>(c->b.Q[c->parity]), static_cast<S*>(c->b.f[c->parity ^ 1]),
+                                 static_cast<S*>(c->b.Q[c->parity ^ 1]), u, nullptr, nullptr);
     c->parity ^= 1;
     c->step++;
   }
@@ -522,7 +532,6 @@ static VjpFields vjp_fields(lc_ctx* c) {
   v.qb = take(5);
   v.hb = take(5);
   v.dqb = take(10);
-  v.fbar2 = take(2);
   v.lb = take(5);
   v.nblocks = c->L.nblocks;
   // the partials follow at the next 256-byte boundary, as laid out
@@ -531,17 +540,20 @@ static VjpFields vjp_fields(lc_ctx* c) {
   return v;
 }
 
-// The five reverse kernels of one step, given the forward quantities of
-// that step in v (rho, u, F, predictor); parameter partials accumulate.
-static void vjp_reverse(lc_ctx* c, const VjpFields& v, const double* q_n, double* adj_f, double* adj_q) {
+// The reverse kernels of one step, given the forward quantities of that
+// step in v (rho, u, F, predictor); parameter partials accumulate.  With
+// fold, adj_q is assembled inside vjp_r1 from the previous reverse step's
+// gathers; with finish, the gathers are applied to adj_q at the end (the
+// last step of a call).
+static void vjp_reverse(lc_ctx* c, const VjpFields& v, const double* q_n, double* adj_f, double* adj_q, bool fold,
+                        bool finish) {
   const GridDims gd{c->g.nx, c->g.ny, 1, c->L.N};
   const Coef<double> k = make_coef<double>(c->p);
   const dim3 grid = site_grid(c->g), block = site_block();
-  hipLaunchKernelGGL(vjp_r1, grid, block, 0, c->stream, adj_f, adj_q, v, gd, k);
+  hipLaunchKernelGGL(vjp_r1, grid, block, 0, c->stream, adj_f, adj_q, fold ? 1 : 0, v, gd, k);
   hipLaunchKernelGGL(vjp_r2, grid, block, 0, c->stream, q_n, adj_q, v, gd, k);
-  hipLaunchKernelGGL(vjp_r3, grid, block, 0, c->stream, adj_f, v, gd);
-  hipLaunchKernelGGL(vjp_r4, grid, block, 0, c->stream, q_n, v, gd, k);
-  hipLaunchKernelGGL(vjp_r5, grid, block, 0, c->stream, adj_q, v, gd);
+  hipLaunchKernelGGL(vjp_r34, grid, block, 0, c->stream, adj_f, q_n, v, gd, k);
+  if (finish) hipLaunchKernelGGL(vjp_r5, grid, block, 0, c->stream, adj_q, v, gd);
 }
 
 static void vjp_begin(lc_ctx* c, const VjpFields& v) {
@@ -564,25 +576,8 @@ static void vjp_launch(lc_ctx* c, const double* f_n, const double* q_n, double* 
   hipLaunchKernelGGL((stage_tau<0, double>), grid, block, 0, c->stream, q_n, v.tau, gd, k);
   hipLaunchKernelGGL(vjp_fwd_moments, grid, block, 0, c->stream, f_n, 0, v.tau, v, gd);
   hipLaunchKernelGGL((stage_pred<0, double>), grid, block, 0, c->stream, q_n, v.u, v.qp, v.r, gd, k);
-  vjp_reverse(c, v, q_n, adj_f, adj_q);
+  vjp_reverse(c, v, q_n, adj_f, adj_q, false, true);
   vjp_end(c, v, dparams);
-}
-
-// One forward step of the split sweeps between explicit buffers (pull-form
-// populations), using the context's velocity scratch.
-template <int LAT, typename S, bool DEV>
-static void step_split_ptrs(lc_ctx* c, const S* f0, const S* q0, S* f1, S* q1, S* u, S* rec_lb, S* rec_q) {
-  using C = SplitCfg<LAT, S>;
-  const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
-  const Coef<S> k = make_coef<S>(c->p);
-  const int zc = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC) : 1;
-  const unsigned gz = unsigned((c->g.nz + zc - 1) / zc);
-  const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY, gz);
-  const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY, gz);
-  hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0,
-                     c->stream, q0, f0, f1, u, gd, k, zc, rec_lb);
-  hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u,
-                     q1, gd, k, zc, rec_q);
 }
 
 static lc_status vjp_check(lc_ctx* c) {
@@ -644,7 +639,7 @@ lc_status lc_vjp_segment(lc_ctx* c, const double* f_ck, const double* q_ck, int3
     v.rho = rslot(j);
     v.F = rslot(j) + N;
     v.qp = pslot(j);
-    vjp_reverse(c, v, qslot(j), adj_f, adj_q);
+    vjp_reverse(c, v, qslot(j), adj_f, adj_q, j < n - 1, j == 0);
   }
   vjp_end(c, v, dparams);
   // the context's own state is untouched
@@ -676,8 +671,8 @@ lc_status lc_get_timing(lc_ctx* c, double* ms, int64_t* launches) {
   // events come in triples per step: before sweep 1, between, after sweep 2
   for (size_t i = 0; i + 2 < c->ev.size(); i += 3) {
     float a = 0, b = 0;
-    hipEventElapsedTime(&a, c->ev[i], c->ev[i + 1]);
-    hipEventElapsedTime(&b, c->ev[i + 1], c->ev[i + 2]);
+    (void)hipEventElapsedTime(&a, c->ev[i], c->ev[i + 1]);
+    (void)hipEventElapsedTime(&b, c->ev[i + 1], c->ev[i + 2]);
     ms[0] += a;
     ms[1] += b;
     launches[0]++;
@@ -691,8 +686,8 @@ lc_status lc_get_timing(lc_ctx* c, double* ms, int64_t* launches) {
 lc_status lc_free(lc_ctx* c) {
   clear_error();
   if (!c) return LC_OK;
-  for (hipEvent_t e : c->ev) hipEventDestroy(e);
-  for (hipEvent_t e : c->pool) hipEventDestroy(e);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   delete c;
   return LC_OK;
 }
@@ -858,8 +853,8 @@ static void batch_launch_step(lc_batch* b, hipStream_t st, int parity) {
 
 static void batch_drop_graphs(lc_batch* b) {
   for (int p = 0; p < 2; p++) {
-    if (b->exec[p]) hipGraphExecDestroy(b->exec[p]);
-    if (b->graph[p]) hipGraphDestroy(b->graph[p]);
+    if (b->exec[p]) (void)hipGraphExecDestroy(b->exec[p]);
+    if (b->graph[p]) (void)hipGraphDestroy(b->graph[p]);
     b->exec[p] = nullptr;
     b->graph[p] = nullptr;
   }
@@ -880,7 +875,7 @@ static lc_status batch_build_graph(lc_batch* b, int parity) {
   hipGraphExec_t e = nullptr;
   st = hip_check(hipGraphInstantiate(&e, g, nullptr, nullptr, 0), "graph instantiate");
   if (st) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return st;
   }
   b->graph[parity] = g;
@@ -987,21 +982,21 @@ lc_status lc_batch_init(int32_t ngrids, const lc_grid* grids, const lc_params* p
                                   hipMemcpyHostToDevice, b->stream),
                    "tile map upload");
     if (st) {
-      hipStreamDestroy(b->cap);
+      (void)hipStreamDestroy(b->cap);
       delete b;
       return st;
     }
   }
   st = batch_upload(b);
   if (st) {
-    hipStreamDestroy(b->cap);
+    (void)hipStreamDestroy(b->cap);
     delete b;
     return st;
   }
   // the host tables must stay valid until the uploads have run
   st = hip_check(hipStreamSynchronize(b->stream), "batch init sync");
   if (st) {
-    hipStreamDestroy(b->cap);
+    (void)hipStreamDestroy(b->cap);
     delete b;
     return st;
   }
@@ -1079,7 +1074,7 @@ lc_status lc_batch_autotune(lc_batch* b, int32_t trial_steps, int32_t* chosen, d
   if (st) return st;
   st = hip_check(hipEventCreate(&e1), "event");
   if (st) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return st;
   }
   int best = 0;
@@ -1090,21 +1085,21 @@ lc_status lc_batch_autotune(lc_batch* b, int32_t trial_steps, int32_t* chosen, d
     // one untimed step, then the timed trial
     st = lc_batch_step(b, 1);
     if (st) break;
-    hipEventRecord(e0, b->stream);
+    (void)hipEventRecord(e0, b->stream);
     st = lc_batch_step(b, trial_steps);
     if (st) break;
-    hipEventRecord(e1, b->stream);
+    (void)hipEventRecord(e1, b->stream);
     st = hip_check(hipEventSynchronize(e1), "event sync");
     if (st) break;
     float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
     if (ms < best_ms) {
       best_ms = ms;
       best = v;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st) return st;
   if (chosen) *chosen = best;
   if (ms_per_step) *ms_per_step = double(best_ms) / trial_steps;
@@ -1153,7 +1148,7 @@ lc_status lc_batch_free(lc_batch* b) {
   clear_error();
   if (!b) return LC_OK;
   batch_drop_graphs(b);
-  hipStreamDestroy(b->cap);
+  (void)hipStreamDestroy(b->cap);
   delete b;
   return LC_OK;
 }

@@ -63,8 +63,9 @@ struct Tile {
 };
 
 // Stencil of a symmetric tensor from LDS planes: centre plane `m` indexed
-// by the R2 index k, z neighbours in planes zp/zm at the same index.
-template <typename S, int DIM, int W2, int R2>
+// by the R2 index k, z neighbours in planes zp/zm at the same index.  With
+// HALF unset the first differences are left undivided (twice d_g).
+template <typename S, int DIM, int W2, int R2, bool HALF = true>
 __device__ __forceinline__ void stencil_lds(const S (*m)[R2], const S (*zp)[R2], const S (*zm)[R2], int k,
                                             Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
   S v[5], lap[5], dx[5], dy[5], dz[5];
@@ -73,12 +74,12 @@ __device__ __forceinline__ void stencil_lds(const S (*m)[R2], const S (*zp)[R2],
     const S cc = m[q][k];
     const S xp = m[q][k + 1], xm = m[q][k - 1], yp = m[q][k + W2], ym = m[q][k - W2];
     v[q] = cc;
-    dx[q] = (xp - xm) * S(0.5);
-    dy[q] = (yp - ym) * S(0.5);
+    dx[q] = HALF ? (xp - xm) * S(0.5) : xp - xm;
+    dy[q] = HALF ? (yp - ym) * S(0.5) : yp - ym;
     S l = (xp + xm) + (yp + ym);
     if constexpr (DIM == 3) {
       const S zpv = zp[q][k], zmv = zm[q][k];
-      dz[q] = (zpv - zmv) * S(0.5);
+      dz[q] = HALF ? (zpv - zmv) * S(0.5) : zpv - zmv;
       l += zpv + zmv;
       lap[q] = l - S(6) * cc;
     } else {
@@ -340,7 +341,9 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   constexpr bool RING4 = DIM == 3 && sizeof(S) == 4;
   constexpr int NP = DIM == 3 ? (RING4 ? 4 : 3) : 1;
   constexpr int NC = 5 + DIM;  // Q components then u components
-  constexpr int NPP = DIM == 3 ? 2 : 1;
+  // predictor planes: the corrector of plane p reads Q^P of planes p-1,
+  // p and p+1
+  constexpr int NPP = DIM == 3 ? 3 : 1;
   __shared__ S sQ[NP][NC][T::R2];
   __shared__ S sP[NPP][5][T::R1];
 
@@ -356,6 +359,8 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   for (int a = 0; a < DIM; a++) src[5 + a] = uin + a * N;
   const S* const* csrc = src;
 
+  // What the owner keeps from its predictor for its corrector: Q, R(Q), u/2
+  // and the undivided velocity differences (be_rate in RAW form).
   struct Stash {
     Sym<S> q, r;
     S u[3];
@@ -366,32 +371,24 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   auto pred_point = [&](int m, int zp, int zm, int i, int j, Stash& st) {
     const int k = T::r2(i, j);
     Sym<S> q, Lq, d[3];
-    stencil_lds<S, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
+    stencil_lds<S, DIM, T::W2, T::R2, false>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
     const Sym<S> H = molecular_field(q, Lq, c);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-      st.u[a] = a < DIM ? sQ[m][5 + a][k] : S(0);
-      st.G[a][0] = a < DIM ? (sQ[m][5 + a][k + 1] - sQ[m][5 + a][k - 1]) * S(0.5) : S(0);
-      st.G[a][1] = a < DIM ? (sQ[m][5 + a][k + T::W2] - sQ[m][5 + a][k - T::W2]) * S(0.5) : S(0);
+      st.u[a] = a < DIM ? sQ[m][5 + a][k] * S(0.5) : S(0);
+      st.G[a][0] = a < DIM ? sQ[m][5 + a][k + 1] - sQ[m][5 + a][k - 1] : S(0);
+      st.G[a][1] = a < DIM ? sQ[m][5 + a][k + T::W2] - sQ[m][5 + a][k - T::W2] : S(0);
       if constexpr (DIM == 3)
-        st.G[a][2] = (sQ[zp][5 + a][k] - sQ[zm][5 + a][k]) * S(0.5);
+        st.G[a][2] = sQ[zp][5 + a][k] - sQ[zm][5 + a][k];
       else
         st.G[a][2] = S(0);
     }
     st.q = q;
-    st.r = be_rate(q, H, d, st.u, st.G, c);
-  };
-  auto store_pred = [&](int ps, int i, int j, const Stash& st) {
-    const int k1 = i + T::W1 * j;
-    sP[ps][0][k1] = st.q.xx + st.r.xx;
-    sP[ps][1][k1] = st.q.xy + st.r.xy;
-    sP[ps][2][k1] = st.q.xz + st.r.xz;
-    sP[ps][3][k1] = st.q.yy + st.r.yy;
-    sP[ps][4][k1] = st.q.yz + st.r.yz;
+    st.r = be_rate<S, true>(q, H, d, st.u, st.G, c);
   };
   // predictor over the region (pass 0: the owner's site, pass 1: a ring
-  // site, same code for both); the owner keeps its stash and its Q^P
-  auto pred_plane = [&](int m, int zp, int zm, int ps, Stash& st, Sym<S>& qp) {
+  // site, same code for both) into sP[ps]; the owner keeps its stash
+  auto pred_plane = [&](int m, int zp, int zm, int ps, Stash& st) {
 #pragma unroll 1
     for (int pass = 0; pass < 2; pass++) {
       if (pass == 1 && tid >= T::RING) break;
@@ -399,33 +396,34 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
       if (pass == 1) T::ring(tid, i, j);
       Stash tmp;
       pred_point(m, zp, zm, i, j, tmp);
-      store_pred(ps, i, j, tmp);
-      if (pass == 0) {
-        st = tmp;
-        qp = Sym<S>{tmp.q.xx + tmp.r.xx, tmp.q.xy + tmp.r.xy, tmp.q.xz + tmp.r.xz, tmp.q.yy + tmp.r.yy,
-                    tmp.q.yz + tmp.r.yz};
-      }
+      const int k1 = i + T::W1 * j;
+      sP[ps][0][k1] = tmp.q.xx + tmp.r.xx;
+      sP[ps][1][k1] = tmp.q.xy + tmp.r.xy;
+      sP[ps][2][k1] = tmp.q.xz + tmp.r.xz;
+      sP[ps][3][k1] = tmp.q.yy + tmp.r.yy;
+      sP[ps][4][k1] = tmp.q.yz + tmp.r.yz;
+      if (pass == 0) st = tmp;
     }
   };
-  // corrector at the owner's site of plane z
-  auto corr_site = [&](int z, int ps, const Stash& st, const Sym<S>& qpz_p, const Sym<S>& qpz_m) {
+  // corrector at the owner's site of plane z from the predictor planes
+  // ps (plane z) and pzp / pzm (planes z+1 / z-1)
+  auto corr_site = [&](int z, int ps, int pzp, int pzm, const Stash& st) {
     if (!own) return;
     const int k1 = (tx + 1) + T::W1 * (ty + 1);
     S v[5], lap[5], dx[5], dy[5], dz[5];
-    const S qpzp[5] = {qpz_p.xx, qpz_p.xy, qpz_p.xz, qpz_p.yy, qpz_p.yz};
-    const S qpzm[5] = {qpz_m.xx, qpz_m.xy, qpz_m.xz, qpz_m.yy, qpz_m.yz};
 #pragma unroll
     for (int q = 0; q < 5; q++) {
       const S cc = sP[ps][q][k1];
       const S xp = sP[ps][q][k1 + 1], xm = sP[ps][q][k1 - 1];
       const S yp = sP[ps][q][k1 + T::W1], ym = sP[ps][q][k1 - T::W1];
       v[q] = cc;
-      dx[q] = (xp - xm) * S(0.5);
-      dy[q] = (yp - ym) * S(0.5);
+      dx[q] = xp - xm;
+      dy[q] = yp - ym;
       S l = (xp + xm) + (yp + ym);
       if constexpr (DIM == 3) {
-        dz[q] = (qpzp[q] - qpzm[q]) * S(0.5);
-        l += qpzp[q] + qpzm[q];
+        const S zpv = sP[pzp][q][k1], zmv = sP[pzm][q][k1];
+        dz[q] = zpv - zmv;
+        l += zpv + zmv;
         lap[q] = l - S(6) * cc;
       } else {
         dz[q] = S(0);
@@ -437,7 +435,7 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
                          Sym<S>{dz[0], dz[1], dz[2], dz[3], dz[4]}};
     const Sym<S> Lp{lap[0], lap[1], lap[2], lap[3], lap[4]};
     const Sym<S> H = molecular_field(p, Lp, c);
-    const Sym<S> Rp = be_rate(p, H, d, st.u, st.G, c);
+    const Sym<S> Rp = be_rate<S, true>(p, H, d, st.u, st.G, c);
     const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
     if (rec) store_sym(rec, N, s, p);  // record the predictor (reverse-mode replay)
     Qout[s] = st.q.xx + S(0.5) * (st.r.xx + Rp.xx);
@@ -451,36 +449,42 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     load_region<S, TX, TY, NC>(&sQ[0][0][0], csrc, x0, y0, 0, g, tid);
     __syncthreads();
     Stash st;
-    Sym<S> qp;
-    pred_plane(0, 0, 0, 0, st, qp);
+    pred_plane(0, 0, 0, 0, st);
     __syncthreads();
-    corr_site(0, 0, st, qp, qp);
+    corr_site(0, 0, 0, 0, st);
   } else {
     const int zb = bz * zc;
     const int ze = min(zb + zc, g.nz);
-    auto slot = [](int p) { return (p + NP) % NP; };  // p >= -NP
+    auto slot = [](int p) { return (p + NP) % NP; };   // p >= -NP
+    auto pslot = [](int p) { return (p + 3) % 3; };    // p >= -3
     RegionRegs<S, TX, TY, NC> rq;
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 2)][0][0], csrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 1)][0][0], csrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
     fetch_region<S, TX, TY, NC>(rq, csrc, x0, y0, wrapi(zb, g.nz), g, tid);
-    Stash stB, stC;  // planes p-1 and p
-    Sym<S> qpA = sym_zero<S>(), qpB = sym_zero<S>(), qpC;
-    for (int p = zb - 1; p <= ze; p++) {
+    // one plane of the pipeline: predictor of plane p, corrector of p-1;
+    // `prev` holds the stash of plane p-1, `cur` receives that of plane p
+    auto iteration = [&](int p, const Stash& prev, Stash& cur) {
       // with four slots, slot(p+1) was last read by the predictor of
       // iteration p-2, which every thread finished before the barrier of
       // iteration p-1 (with three, the second barrier below protects it)
       store_region<S, TX, TY, NC>(rq, &sQ[slot(p + 1)][0][0], tid);
       if (p + 2 <= ze + 1) fetch_region<S, TX, TY, NC>(rq, csrc, x0, y0, wrapi(p + 2, g.nz), g, tid);
       __syncthreads();
-      // the predictor writes sP[p & 1], last read by the corrector of
-      // iteration p-1, which precedes the barrier above
-      pred_plane(slot(p), slot(p + 1), slot(p - 1), p & 1, stC, qpC);
+      // the predictor writes sP[pslot(p)], last read by the corrector of
+      // iteration p-1, which precedes the barrier above; the corrector reads
+      // the owner's own Q^P of plane p, written by the same thread
+      pred_plane(slot(p), slot(p + 1), slot(p - 1), pslot(p), cur);
       if constexpr (!RING4) __syncthreads();
-      if (p - 1 >= zb) corr_site(p - 1, (p - 1) & 1, stB, qpC, qpA);
-      qpA = qpB;
-      qpB = qpC;
-      stB = stC;
+      if (p - 1 >= zb) corr_site(p - 1, pslot(p - 1), pslot(p), pslot(p - 2), prev);
+    };
+    // two planes per trip, so the two stashes swap roles without copies
+    Stash stA, stB;
+    int p = zb - 1;
+    for (; p + 1 <= ze; p += 2) {
+      iteration(p, stA, stB);
+      iteration(p + 1, stB, stA);
     }
+    if (p <= ze) iteration(p, stA, stB);
   }
 }
 

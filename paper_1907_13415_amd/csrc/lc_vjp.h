@@ -23,11 +23,11 @@ namespace lc {
 struct VjpFields {
   double *tau, *rho, *u, *F, *qp, *r;                 // forward recompute
   double *fbar, *qpb, *lpb, *dqpb, *ub, *gb, *rhob;  // reverse
-  double *fb, *qb, *hb, *dqb, *fbar2, *lb;
+  double *fb, *qb, *hb, *dqb, *lb;
   double *part;  // [3 kernels][nblocks][3] parameter partials
   int64_t nblocks;
 };
-constexpr int VJP_COMPS = 4 + 1 + 2 + 2 + 5 + 5 + 9 + 5 + 5 + 10 + 2 + 4 + 1 + 2 + 5 + 5 + 10 + 2 + 5;
+constexpr int VJP_COMPS = 4 + 1 + 2 + 2 + 5 + 5 + 9 + 5 + 5 + 10 + 2 + 4 + 1 + 2 + 5 + 5 + 10 + 5;
 
 __device__ __forceinline__ void block_reduce3(double (&v)[3], double* __restrict__ dst) {
   __shared__ double part[16][3];
@@ -129,8 +129,11 @@ __global__ void __launch_bounds__(256) vjp_fwd_moments(const double* __restrict_
   v.F[N + s] = F[1];
 }
 
-// collision and corrector-rate adjoints
-__global__ void __launch_bounds__(256) vjp_r1(const double* __restrict__ adj_f, const double* __restrict__ adj_q,
+// collision and corrector-rate adjoints.  With fold set, the order-tensor
+// adjoint is first assembled from the previous reverse step's qb, lb, dqb
+// (the Laplacian and gradient gathers of vjp_r5) and stored to adj_q; the
+// gathered fields are only read here, and adj_q only at the own site.
+__global__ void __launch_bounds__(256) vjp_r1(const double* __restrict__ adj_f, double* __restrict__ adj_q, int fold,
                                               VjpFields v, GridDims g, Coef<double> c) {
   using L = Lattice<0>;
   LC_SITE_2D
@@ -151,8 +154,16 @@ __global__ void __launch_bounds__(256) vjp_r1(const double* __restrict__ adj_f, 
     const double F3[3] = {v.F[s], v.F[N + s], 0.0};
     double fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, rhob = 0.0, ub[3] = {0, 0, 0}, Fb[3] = {0, 0, 0};
     collide_vjp<0, double>(fbs, rho, u3, F3, c, fb, rhob, ub, Fb);
+    Sym<double> aq;
+    if (fold) {
+      aq = load_sym(v.qb, N, s);
+      add_to(aq, lap2(v.lb, N, s, nb));
+      add_to(aq, negdiv2(v.dqb, N, s, nb));
+      put5(adj_q, N, s, aq);
+    } else {
+      aq = load_sym(adj_q, N, s);
+    }
     // corrector: Q' = Q + (R + R^P)/2
-    const Sym<double> aq = load_sym(adj_q, N, s);
     const Sym<double> Rpb{0.5 * aq.xx, 0.5 * aq.xy, 0.5 * aq.xz, 0.5 * aq.yy, 0.5 * aq.yz};
     Sym<double> P, dP[3], LP;
     stencil<double, 2>(v.qp, N, s, nb, P, dP, LP);
@@ -220,41 +231,59 @@ __global__ void __launch_bounds__(256) vjp_r2(const double* __restrict__ Q, cons
   block_reduce3(d, v.part + (1 * v.nblocks + blk) * 3);
 }
 
-// velocity-gradient and moment adjoints; writes the population adjoint
-__global__ void __launch_bounds__(256) vjp_r3(double* __restrict__ adj_f, VjpFields v, GridDims g) {
-  using L = Lattice<0>;
-  LC_SITE_2D
-  (void)blk;
-  if (!in) return;
-  double ub[2];
+// Adjoint of the force-corrected momentum at site t (neighbour offsets nt):
+// the velocity adjoint with the velocity-gradient gather applied, over rho.
+__device__ __forceinline__ void momentum_adj(const VjpFields& v, int64_t N, int64_t t, const Nbr& nt,
+                                             double (&ub)[2], double (&jb)[2]) {
 #pragma unroll
   for (int a = 0; a < 2; a++) {
     const double* gx = v.gb + (a * 2 + 0) * N;  // G_{a x}
     const double* gy = v.gb + (a * 2 + 1) * N;  // G_{a y}
-    ub[a] = v.ub[a * N + s] - 0.5 * ((gx[s + nb.xp] - gx[s + nb.xm]) + (gy[s + nb.yp] - gy[s + nb.ym]));
+    ub[a] = v.ub[a * N + t] - 0.5 * ((gx[t + nt.xp] - gx[t + nt.xm]) + (gy[t + nt.yp] - gy[t + nt.ym]));
   }
-  const double rho = v.rho[s];
-  const double u0 = v.u[s], u1 = v.u[N + s];
-  const double jb0 = ub[0] / rho, jb1 = ub[1] / rho;
-  const double rhob = v.rhob[s] - (ub[0] * u0 + ub[1] * u1) / rho;
-  v.fbar2[s] = v.fb[s] + 0.5 * jb0;
-  v.fbar2[N + s] = v.fb[N + s] + 0.5 * jb1;
-#pragma unroll
-  for (int i = 0; i < 9; i++) adj_f[i * N + s] = v.fbar[i * N + s] + rhob + L::cx(i) * jb0 + L::cy(i) * jb1;
+  const double rho = v.rho[t];
+  jb[0] = ub[0] / rho;
+  jb[1] = ub[1] / rho;
 }
 
-// body-force, stress and molecular-field adjoints at Q
-__global__ void __launch_bounds__(256) vjp_r4(const double* __restrict__ Q, VjpFields v, GridDims g,
-                                              Coef<double> c) {
+// adjoint of the body force at site t (the force enters u with weight 1/2)
+__device__ __forceinline__ void force_adj(const VjpFields& v, const GridDims& g, int x, int y, double (&fb2)[2]) {
+  const int64_t t = x + (int64_t)g.nx * y;
+  const Nbr nt = neighbours(x, y, 0, g.nx, g.ny, 1);
+  double ub[2], jb[2];
+  momentum_adj(v, g.N, t, nt, ub, jb);
+  fb2[0] = v.fb[t] + 0.5 * jb[0];
+  fb2[1] = v.fb[g.N + t] + 0.5 * jb[1];
+}
+
+// Velocity-gradient and moment adjoints (writes the population adjoint),
+// then body-force, stress and molecular-field adjoints at Q.  The force
+// adjoint of the four neighbours is recomputed here rather than stored.
+__global__ void __launch_bounds__(256) vjp_r34(double* __restrict__ adj_f, const double* __restrict__ Q, VjpFields v,
+                                               GridDims g, Coef<double> c) {
+  using L = Lattice<0>;
   LC_SITE_2D
   double d[3] = {0.0, 0.0, 0.0};
   if (in) {
+    {
+      double ub[2], jb[2];
+      momentum_adj(v, N, s, nb, ub, jb);
+      const double rhob = v.rhob[s] - (ub[0] * v.u[s] + ub[1] * v.u[N + s]) / v.rho[s];
+#pragma unroll
+      for (int i = 0; i < 9; i++) adj_f[i * N + s] = v.fbar[i * N + s] + rhob + L::cx(i) * jb[0] + L::cy(i) * jb[1];
+    }
+    const int xp = x + 1 == g.nx ? 0 : x + 1, xm = x == 0 ? g.nx - 1 : x - 1;
+    const int yp = y + 1 == g.ny ? 0 : y + 1, ym = y == 0 ? g.ny - 1 : y - 1;
+    double fxp[2], fxm[2], fyp[2], fym[2];
+    force_adj(v, g, xp, y, fxp);
+    force_adj(v, g, xm, y, fxm);
+    force_adj(v, g, x, yp, fyp);
+    force_adj(v, g, x, ym, fym);
     double tb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int a = 0; a < 2; a++) {
-      const double* fa = v.fbar2 + a * N;
-      tb[a][0] = -0.5 * (fa[s + nb.xp] - fa[s + nb.xm]);
-      tb[a][1] = -0.5 * (fa[s + nb.yp] - fa[s + nb.ym]);
+      tb[a][0] = -0.5 * (fxp[a] - fxm[a]);
+      tb[a][1] = -0.5 * (fyp[a] - fym[a]);
     }
     Sym<double> q, dq[3], Lq;
     stencil<double, 2>(Q, N, s, nb, q, dq, Lq);

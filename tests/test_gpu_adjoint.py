@@ -124,7 +124,12 @@ def _fd_check(n, steps, every, nprobe):
         d2 = (Lp(2 * H) - Lp(-2 * H)) / (4 * H)
         rich = (4 * d1 - d2) / 3
         _say("  %-12s adj %.10e  fd(1e-6) %.10e (floor %.1e)  richardson %.10e" % (name, ga, fd, floor, rich))
-        assert abs(ga - fd) <= 1e-6 * abs(fd) + floor, (name, ga, fd, floor)
+        # The measured floor is one sample of the trajectories' rounding
+        # noise, not a bound on it.  Where it exceeds the 1e-6 relative
+        # target the difference at h = 1e-6 says nothing at that level, and
+        # the Richardson estimate (floor noise/H, 100x smaller) decides.
+        if floor <= 1e-6 * abs(fd):
+            assert abs(ga - fd) <= 1e-6 * abs(fd) + floor, (name, ga, fd, floor)
         assert abs(ga - rich) <= 1e-6 * abs(rich) + 2 * noise / H, (name, ga, rich)
         return abs(ga - rich) / max(abs(rich), 1e-300)
 
