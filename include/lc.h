@@ -206,13 +206,37 @@ size_t lc_vjp_history_bytes(const lc_grid *grid, int32_t n);
 
 /* Reverse sweep over one checkpoint segment (D2Q9, LC_FP64): starting from
  * the checkpoint state (f_ck, Q_ck: device arrays of double logical values),
- * replay n - 1 steps keeping every state in `hist` (caller-owned device
- * buffer of lc_vjp_history_bytes(grid, n) bytes, 256-byte aligned), then
- * apply the n reverse steps n-1 .. 0 to (adj_f, adj_Q) in place, adding the
- * parameter derivatives to dparams[3] as lc_vjp_step does.  The context's
- * own state is not modified.  Asynchronous. */
+ * replay the n steps, recording every state and the step's density, body
+ * force, velocity and predictor in `hist` (caller-owned device buffer of
+ * lc_vjp_history_bytes(grid, n) bytes, 256-byte aligned), then apply the n
+ * reverse steps n-1 .. 0 to (adj_f, adj_Q) in place, adding the parameter
+ * derivatives to dparams[3] as lc_vjp_step does.  The context's own state is
+ * not modified.  Asynchronous on the context stream.  (Checkpoint-and-
+ * recompute of the reverse mode; the paper has no adjoint.) */
 lc_status lc_vjp_segment(lc_ctx *ctx, const double *f_ck, const double *Q_ck, int32_t n, void *hist,
                          double *adj_f, double *adj_Q, double *dparams);
+
+/* Bytes of the history lc_vjp_backward needs when no segment is longer than
+ * n steps: two segment histories (0 on bad arguments). */
+size_t lc_vjp_backward_bytes(const lc_grid *grid, int32_t n);
+
+/* The whole reverse sweep over nseg checkpoint segments (D2Q9, LC_FP64).
+ * f_cks[k], Q_cks[k] (host arrays of nseg device pointers, double logical
+ * values) are the checkpoints in forward order, ns[k] (host array) the steps
+ * of segment k.  Segments are walked back from nseg-1 to 0 as
+ * lc_vjp_segment does, but the replay of segment k-1 runs on a second stream
+ * of the library while segment k is walked back on the context stream; the
+ * two alternate between the halves of `hist` (lc_vjp_backward_bytes(grid,
+ * max ns) bytes, 256-byte aligned).  adj_f, adj_Q are updated in place and
+ * the parameter derivatives added to dparams[3].  Work the caller queued on
+ * the context stream before the call is complete before any replay starts,
+ * and all of the call's work is complete once the context stream reaches
+ * the point after it.  The context's own state is not modified.
+ * Asynchronous.  LC_EINVAL on NULL pointers, nseg < 1, a segment with fewer
+ * than one step or a misaligned hist; LC_EDEVICE if the second stream or
+ * its events cannot be created. */
+lc_status lc_vjp_backward(lc_ctx *ctx, int32_t nseg, const double *const *f_cks, const double *const *Q_cks,
+                          const int32_t *ns, void *hist, double *adj_f, double *adj_Q, double *dparams);
 
 /* Wait for the context stream and report any pending device error. */
 lc_status lc_sync(lc_ctx *ctx);

@@ -3,11 +3,12 @@ over the library's forward step (lc_step) and reverse step (lc_vjp_step),
 with checkpoint-and-recompute.
 
 Forward: the state is saved every `every` steps (logical f and Q in double,
-on the device).  Backward: segments are processed last to first; each is
-replayed from its checkpoint with every intermediate state kept, then the
-reverse step walks it backwards.  Memory: one checkpoint per segment plus
-`every` states of one segment.  All arithmetic runs in the HIP kernels;
-this module only schedules calls and owns buffers.
+on the device).  Backward (lc_vjp_backward): segments are processed last to
+first; each is replayed from its checkpoint with every intermediate state
+kept, then the reverse steps walk it back, and the replay of the next
+segment overlaps that walk on a second stream.  Memory: one checkpoint per
+segment plus the histories of two segments.  All arithmetic runs in the HIP
+kernels; this module only owns buffers and passes pointers.
 
 Two-dimensional (D2Q9) grids in double precision.
 """
@@ -38,6 +39,7 @@ class LCSolve(torch.autograd.Function):
         params = (cfg["A0"], float(gamma), float(K), float(Gamma), cfg["xi"], cfg["tau"])
         shape = tuple(q0.shape[1:])
         s = lc.Solver("D2Q9", "fp64", shape, params, device=q0.device)
+        s.stream.wait_stream(torch.cuda.current_stream(q0.device))  # q0 may still be in flight
         with torch.cuda.stream(s.stream):
             q0c = q0.detach().contiguous()
             lc.lc_load_state(s.ctx, None, q0c.data_ptr())
@@ -65,16 +67,18 @@ class LCSolve(torch.autograd.Function):
         s = ctx.solver
         shape = ctx.shape
         dev = grad_q.device
+        s.stream.wait_stream(torch.cuda.current_stream(dev))  # grad_q may still be in flight
         with torch.cuda.stream(s.stream):
             adj_q = grad_q.detach().to(torch.float64).contiguous().clone()
             adj_f = torch.zeros((9,) + shape, dtype=torch.float64, device=dev)
             dparams = torch.zeros(3, dtype=torch.float64, device=dev)
             every = max(n for _, _, n in ctx.checkpoints)
-            hist = torch.empty(lc.lc_vjp_history_bytes(s.grid, every), dtype=torch.uint8, device=dev)
-            for f_ck, q_ck, n in reversed(ctx.checkpoints):
-                # replay the segment from its checkpoint, then walk it back
-                lc.lc_vjp_segment(s.ctx, f_ck.data_ptr(), q_ck.data_ptr(), n, hist.data_ptr(), adj_f.data_ptr(),
-                                  adj_q.data_ptr(), dparams.data_ptr())
+            hist = torch.empty(lc.lc_vjp_backward_bytes(s.grid, every), dtype=torch.uint8, device=dev)
+            # segments are replayed on a second stream of the library while
+            # the previous one is walked back
+            lc.lc_vjp_backward(s.ctx, [f.data_ptr() for f, _, _ in ctx.checkpoints],
+                               [q.data_ptr() for _, q, _ in ctx.checkpoints], [n for _, _, n in ctx.checkpoints],
+                               hist.data_ptr(), adj_f.data_ptr(), adj_q.data_ptr(), dparams.data_ptr())
         s.stream.synchronize()
         return adj_q, dparams[0], dparams[1], dparams[2], None
 

@@ -145,6 +145,10 @@ struct lc_ctx {
   bool timing;
   std::vector<hipEvent_t> ev;     // recorded around each launch, 3 per step
   std::vector<hipEvent_t> pool;   // idle events for reuse
+  // second stream and ordering events of the overlapped reverse sweep
+  // (created on first use)
+  hipStream_t aux = nullptr;
+  hipEvent_t vev[5] = {};
 };
 
 namespace lc {
@@ -212,10 +216,12 @@ struct SplitCfg {
 };
 
 // One step of the split sweeps between explicit buffers (pull-form
-// populations); u receives the force-corrected velocity.  rec_lb / rec_q,
-// when not null, record rho and F / the predictor for reverse-mode replay.
+// populations) on stream st; u receives the force-corrected velocity.
+// rec_lb / rec_q, when not null, record rho and F / the predictor for
+// reverse-mode replay.  With mark, timing events bracket the two sweeps.
 template <int LAT, typename S, bool DEV>
-static void step_split_ptrs(lc_ctx* c, const S* f0, const S* q0, S* f1, S* q1, S* u, S* rec_lb, S* rec_q) {
+static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const S* q0, S* f1, S* q1, S* u,
+                            S* rec_lb, S* rec_q) {
   using C = SplitCfg<LAT, S>;
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = make_coef<S>(c->p);
@@ -225,20 +231,20 @@ static void step_split_ptrs(lc_ctx* c, const S* f0, const S* q0, S* f1, S* q1, S
                 unsigned((c->g.nz + zc1 - 1) / zc1));
   const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY,
                 unsigned((c->g.nz + zc2 - 1) / zc2));
-  ctx_mark(c);
-  hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0,
-                     c->stream, q0, f0, f1, u, gd, k, zc1, rec_lb);
-  ctx_mark(c);
-  hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, c->stream, q0, u,
-                     q1, gd, k, zc2, rec_q);
-  ctx_mark(c);
+  if (mark) ctx_mark(c);
+  hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, st, q0,
+                     f0, f1, u, gd, k, zc1, rec_lb);
+  if (mark) ctx_mark(c);
+  hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1, gd,
+                     k, zc2, rec_q);
+  if (mark) ctx_mark(c);
 }
 
 template <int LAT, typename S, bool DEV>
 static lc_status run_steps_split(lc_ctx* c, int64_t n) {
   S* u = reinterpret_cast<S*>(static_cast<char*>(c->b.scratch) + c->L.off_u);
   for (int64_t it = 0; it < n; it++) {
-    step_split_ptrs<LAT, S, DEV>(c, static_cast<const S*>(c->b.f[c->parity]),
+    step_split_ptrs<LAT, S, DEV>(c, c->stream, true, static_cast<const S*>(c->b.f[c->parity]),
                                  static_cast<const S*>(c->b.Q[c->parity]), static_cast<S*>(c->b.f[c->parity ^ 1]),
                                  static_cast<S*>(c->b.Q[c->parity ^ 1]), u, nullptr, nullptr);
     c->parity ^= 1;
@@ -609,6 +615,47 @@ size_t lc_vjp_history_bytes(const lc_grid* grid, int32_t n) {
   return size_t(n + 1) * (q + 5 + 10) * N * es;
 }
 
+}  // extern "C"
+
+namespace lc {
+// History of one segment: slot j holds f (9N, pull form), Q (5N), u (2N),
+// rho and F (3N) and Q^P (5N) of step j.
+struct VjpHist {
+  double* h;
+  int64_t N;
+  double* slot(int j) const { return h + size_t(j) * 24 * N; }
+  double* f(int j) const { return slot(j); }
+  double* q(int j) const { return slot(j) + 9 * size_t(N); }
+  double* u(int j) const { return slot(j) + 14 * size_t(N); }
+  double* r(int j) const { return slot(j) + 16 * size_t(N); }
+  double* p(int j) const { return slot(j) + 19 * size_t(N); }
+};
+
+// Replay n steps from a checkpoint on stream st, recording every step.
+static void vjp_replay(lc_ctx* c, hipStream_t st, const double* f_ck, const double* q_ck, int n, const VjpHist& H) {
+  const GridDims gd{c->g.nx, c->g.ny, 1, c->L.N};
+  hipLaunchKernelGGL((load_state<0, double, false>), site_grid(c->g), site_block(), 0, st, f_ck, q_ck, H.f(0),
+                     H.q(0), gd);
+  for (int j = 0; j < n; j++)
+    step_split_ptrs<0, double, false>(c, st, false, H.f(j), H.q(j), H.f(j + 1), H.q(j + 1), H.u(j), H.r(j), H.p(j));
+}
+
+// The reverse steps n-1 .. 0 of a recorded segment on the context stream.
+static void vjp_walk(lc_ctx* c, VjpFields& v, int n, const VjpHist& H, double* adj_f, double* adj_q) {
+  for (int j = n - 1; j >= 0; j--) {
+    v.u = H.u(j);
+    v.rho = H.r(j);
+    v.F = H.r(j) + H.N;
+    v.qp = H.p(j);
+    vjp_reverse(c, v, H.q(j), adj_f, adj_q, j < n - 1, j == 0);
+  }
+}
+
+static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
+}  // namespace lc
+
+extern "C" {
+
 lc_status lc_vjp_segment(lc_ctx* c, const double* f_ck, const double* q_ck, int32_t n, void* hist, double* adj_f,
                          double* adj_q, double* dparams) {
   clear_error();
@@ -617,33 +664,73 @@ lc_status lc_vjp_segment(lc_ctx* c, const double* f_ck, const double* q_ck, int3
   lc_status st = vjp_check(c);
   if (st) return st;
   if (reinterpret_cast<uintptr_t>(hist) & 255) return fail(LC_EINVAL, "history must be 256-byte aligned");
-  const int64_t N = c->L.N;
-  double* h = static_cast<double*>(hist);
-  // slot j: f (9N, pull form), Q (5N), u (2N), rho and F (3N), Q^P (5N)
-  auto slot = [&](int j) { return h + size_t(j) * 24 * N; };
-  auto fslot = [&](int j) { return slot(j); };
-  auto qslot = [&](int j) { return slot(j) + 9 * size_t(N); };
-  auto uslot = [&](int j) { return slot(j) + 14 * size_t(N); };
-  auto rslot = [&](int j) { return slot(j) + 16 * size_t(N); };
-  auto pslot = [&](int j) { return slot(j) + 19 * size_t(N); };
-  const GridDims gd{c->g.nx, c->g.ny, 1, N};
-  hipLaunchKernelGGL((load_state<0, double, false>), site_grid(c->g), site_block(), 0, c->stream, f_ck, q_ck,
-                     fslot(0), qslot(0), gd);
-  // replay every step of the segment, recording its forward quantities
-  for (int j = 0; j < n; j++)
-    step_split_ptrs<0, double, false>(c, fslot(j), qslot(j), fslot(j + 1), qslot(j + 1), uslot(j), rslot(j), pslot(j));
+  const VjpHist H{static_cast<double*>(hist), c->L.N};
+  vjp_replay(c, c->stream, f_ck, q_ck, n, H);
   VjpFields v = vjp_fields(c);
   vjp_begin(c, v);
-  for (int j = n - 1; j >= 0; j--) {
-    v.u = uslot(j);
-    v.rho = rslot(j);
-    v.F = rslot(j) + N;
-    v.qp = pslot(j);
-    vjp_reverse(c, v, qslot(j), adj_f, adj_q, j < n - 1, j == 0);
-  }
+  vjp_walk(c, v, n, H, adj_f, adj_q);
   vjp_end(c, v, dparams);
   // the context's own state is untouched
   return hip_check(hipGetLastError(), "reverse segment launch");
+}
+
+size_t lc_vjp_backward_bytes(const lc_grid* grid, int32_t n) {
+  const size_t h = lc_vjp_history_bytes(grid, n);
+  return h ? 2 * up256(h) : 0;
+}
+
+lc_status lc_vjp_backward(lc_ctx* c, int32_t nseg, const double* const* f_cks, const double* const* q_cks,
+                          const int32_t* ns, void* hist, double* adj_f, double* adj_q, double* dparams) {
+  clear_error();
+  if (!c || !f_cks || !q_cks || !ns || !hist || !adj_f || !adj_q || !dparams) return fail(LC_EINVAL, "NULL argument");
+  if (nseg < 1) return fail(LC_EINVAL, "nseg must be >= 1");
+  lc_status st = vjp_check(c);
+  if (st) return st;
+  if (reinterpret_cast<uintptr_t>(hist) & 255) return fail(LC_EINVAL, "history must be 256-byte aligned");
+  int32_t nmax = 0;
+  for (int32_t k = 0; k < nseg; k++) {
+    if (!f_cks[k] || !q_cks[k]) return fail(LC_EINVAL, "checkpoint %d is NULL", k);
+    if (ns[k] < 1) return fail(LC_EINVAL, "segment %d has %d steps", k, ns[k]);
+    nmax = ns[k] > nmax ? ns[k] : nmax;
+  }
+  if (!c->aux) {
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+      c->aux = nullptr;
+      return fail(LC_EDEVICE, "cannot create the replay stream");
+    }
+    for (hipEvent_t& e : c->vev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(LC_EDEVICE, "event create");
+  }
+  const size_t half = up256(lc_vjp_history_bytes(&c->g, nmax));
+  const VjpHist H[2] = {{static_cast<double*>(hist), c->L.N},
+                        {reinterpret_cast<double*>(static_cast<char*>(hist) + half), c->L.N}};
+  // Segment k is replayed into half k & 1 on the replay stream while the
+  // context stream walks segment k + 1 back: events vev[0..1] mark a replay
+  // done, vev[2..3] a walk done (per half), vev[4] the caller's prior work.
+  hipEvent_t* rep = c->vev;
+  hipEvent_t* walk = c->vev + 2;
+  hipEvent_t entry = c->vev[4];
+  auto chk = [](hipError_t e) { return e == hipSuccess; };
+  bool ok = chk(hipEventRecord(entry, c->stream)) && chk(hipStreamWaitEvent(c->aux, entry, 0));
+  VjpFields v = vjp_fields(c);
+  vjp_begin(c, v);
+  for (int32_t k = nseg - 1; ok && k >= -1; k--) {
+    if (k >= 0) {
+      // replay segment k once the walk that last used its half is done
+      if (k + 2 < nseg) ok = ok && chk(hipStreamWaitEvent(c->aux, walk[k & 1], 0));
+      vjp_replay(c, c->aux, f_cks[k], q_cks[k], ns[k], H[k & 1]);
+      ok = ok && chk(hipEventRecord(rep[k & 1], c->aux));
+    }
+    const int32_t w = k + 1;  // the segment walked in this round
+    if (w < nseg) {
+      ok = ok && chk(hipStreamWaitEvent(c->stream, rep[w & 1], 0));
+      vjp_walk(c, v, ns[w], H[w & 1], adj_f, adj_q);
+      ok = ok && chk(hipEventRecord(walk[w & 1], c->stream));
+    }
+  }
+  vjp_end(c, v, dparams);
+  if (!ok) return fail(LC_EDEVICE, "stream ordering of the reverse sweep failed");
+  return hip_check(hipGetLastError(), "reverse sweep launch");
 }
 
 lc_status lc_sync(lc_ctx* c) {
@@ -688,6 +775,9 @@ lc_status lc_free(lc_ctx* c) {
   if (!c) return LC_OK;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->vev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
   return LC_OK;
 }

@@ -74,6 +74,9 @@ def _load():
         "lc_sync": ([ctypes.c_void_p], ctypes.c_int32),
         "lc_vjp_step": ([ctypes.c_void_p] * 6, ctypes.c_int32),
         "lc_vjp_history_bytes": ([P(lc_grid), ctypes.c_int32], ctypes.c_size_t),
+        "lc_vjp_backward_bytes": ([P(lc_grid), ctypes.c_int32], ctypes.c_size_t),
+        "lc_vjp_backward": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_void_p), P(ctypes.c_void_p),
+                             P(ctypes.c_int32)] + [ctypes.c_void_p] * 4, ctypes.c_int32),
         "lc_vjp_segment": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 4,
                            ctypes.c_int32),
         "lc_set_timing": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
@@ -192,6 +195,21 @@ def lc_vjp_segment(ctx, f_ck_ptr, q_ck_ptr, n, hist_ptr, adj_f_ptr, adj_q_ptr, d
     _check(_lib.lc_vjp_segment(ctx, ctypes.c_void_p(f_ck_ptr), ctypes.c_void_p(q_ck_ptr), int(n),
                                ctypes.c_void_p(hist_ptr), ctypes.c_void_p(adj_f_ptr), ctypes.c_void_p(adj_q_ptr),
                                ctypes.c_void_p(dparams_ptr)))
+
+
+def lc_vjp_backward_bytes(grid, n):
+    return _lib.lc_vjp_backward_bytes(ctypes.byref(grid), int(n))
+
+
+def lc_vjp_backward(ctx, f_ck_ptrs, q_ck_ptrs, ns, hist_ptr, adj_f_ptr, adj_q_ptr, dparams_ptr):
+    """f_ck_ptrs, q_ck_ptrs, ns: sequences (forward order) of checkpoint
+    device pointers and segment lengths."""
+    k = len(ns)
+    fa = (ctypes.c_void_p * k)(*f_ck_ptrs)
+    qa = (ctypes.c_void_p * k)(*q_ck_ptrs)
+    na = (ctypes.c_int32 * k)(*[int(n) for n in ns])
+    _check(_lib.lc_vjp_backward(ctx, k, fa, qa, na, ctypes.c_void_p(hist_ptr), ctypes.c_void_p(adj_f_ptr),
+                                ctypes.c_void_p(adj_q_ptr), ctypes.c_void_p(dparams_ptr)))
 
 
 def lc_set_timing(ctx, enable):
