@@ -13,6 +13,7 @@ Prints one JSON line.  Inputs are resident in HBM before the timed region;
 timings use HIP events recorded on the stream the library launches on.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+                  [--only batch|adjoint] [--calibrate]
 """
 import argparse
 import hashlib
@@ -29,7 +30,8 @@ if ROOT not in sys.path:
 METRIC = "MLUPS & %HBM roofline, FP32-dev vs FP64 at stated error; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 COUNTERS = os.path.join(ROOT, "profiles", "split_sweeps_slab256_d3q19_fp32dev_counters.md")
-KERNEL_SOURCES = ["lc_device.h", "lc_staged.h", "lc_split.h"]
+# what the two sweeps are compiled from (sources, tile configuration, flags)
+KERNEL_SOURCES = ["csrc/lc_device.h", "csrc/lc_staged.h", "csrc/lc_split.h", "build.py"]
 
 
 def alg_bytes_per_site(q, es):
@@ -41,7 +43,7 @@ def alg_bytes_per_site(q, es):
 def kernel_hash():
     h = hashlib.sha1()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1907_13415_amd", "csrc", name), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_1907_13415_amd", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
 
@@ -177,6 +179,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--only", choices=["batch", "adjoint"],
+                    help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -195,6 +199,13 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
+
+    if args.only == "batch":
+        print(json.dumps({"batch_sweep": run_batch(torch, lc, stream, dev, args.steps)}), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": run_adjoint(torch)}), flush=True)
         return
 
     w = inputs.config2(args.n)

@@ -199,21 +199,6 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
   return hip_check(hipGetLastError(), "step launch");
 }
 
-// Tile shapes of the two-sweep kernels (measured on 256^3; LDS per block at
-// most 76 KB, so at least two blocks fit a CU).
-template <int LAT, typename S>
-struct SplitCfg {
-  static constexpr bool d3 = Lattice<LAT>::dim == 3;
-  static constexpr bool f64 = sizeof(S) == 8;
-  static constexpr int LB_TX = (d3 && !f64) ? 64 : 32, LB_TY = (d3 && !f64) ? 4 : 8;
-  static constexpr int Q_TX = (d3 && f64) ? 16 : 32, Q_TY = 8;
-  // planes per block along z in each sweep
-  static constexpr int ZC_LB = f64 ? 16 : 128, ZC_Q = 128;
-  // waves per SIMD the register allocation is held to (LDS allows 3 blocks
-  // of the single-precision 3D stress sweep per CU)
-  static constexpr int LB_WPE = (d3 && !f64) ? 3 : 1;
-  static constexpr int Q_WPE = 1;
-};
 
 // One step of the split sweeps between explicit buffers (pull-form
 // populations) on stream st; u receives the force-corrected velocity.
