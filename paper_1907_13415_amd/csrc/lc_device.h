@@ -161,27 +161,49 @@ LC_HD void stress(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
 //   R = Gamma H + S - (u.grad) Q,
 //   S = A + A^T - 2 xi (Q + I/3)(Q:G),  A = [xi D + W](Q + I/3),
 // with G[a][b] = d_b u_a, so xi D + W = (xi+1)/2 G + (xi-1)/2 G^T.
+// The flow enters through terms that do not depend on Q (Flow): u, the
+// matrix B = xi D + W and the five sums g with Q:G = g . (Qxx, Qyy, Qxy,
+// Qxz, Qyz) (Qzz = -Qxx - Qyy).  They are formed once per site and serve
+// both Heun stages, which use the same u.
 // With RAW set, dQ and G are undivided central differences (twice the
 // derivatives) and u is halved: the same rate up to rounding (the factors
-// of two are exact; the compiler's contraction into FMAs may differ), with
-// the halvings saved.
+// of two are exact), with the halvings saved.
+template <typename T>
+struct Flow {
+  T u[3];
+  T B[3][3];
+  T g[5];
+};
+
 template <typename T, bool RAW = false>
-LC_HD Sym<T> be_rate(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
-                                          const T (&u)[3], const T (&G)[3][3], const Coef<T>& c) {
+LC_HD Flow<T> flow_terms(const T (&u)[3], const T (&G)[3][3], const Coef<T>& c) {
+  Flow<T> f;
+  const T xp = RAW ? c.xi_p * T(0.5) : c.xi_p, xm = RAW ? c.xi_m * T(0.5) : c.xi_m;
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    f.u[a] = u[a];
+#pragma unroll
+    for (int b = 0; b < 3; b++) f.B[a][b] = xp * G[a][b] + xm * G[b][a];
+  }
+  f.g[0] = G[0][0] - G[2][2];
+  f.g[1] = G[1][1] - G[2][2];
+  f.g[2] = G[0][1] + G[1][0];
+  f.g[3] = G[0][2] + G[2][0];
+  f.g[4] = G[1][2] + G[2][1];
+  return f;
+}
+
+template <typename T, bool RAW = false>
+LC_HD Sym<T> be_rate_flow(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3], const Flow<T>& f,
+                          const Coef<T>& c) {
   const T Qp[3][3] = {{Q.xx + T(1.0 / 3.0), Q.xy, Q.xz},
                       {Q.xy, Q.yy + T(1.0 / 3.0), Q.yz},
                       {Q.xz, Q.yz, Q.zz() + T(1.0 / 3.0)}};
-  const T xp = RAW ? c.xi_p * T(0.5) : c.xi_p, xm = RAW ? c.xi_m * T(0.5) : c.xi_m;
-  T B[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; a++)
-#pragma unroll
-    for (int b = 0; b < 3; b++) B[a][b] = xp * G[a][b] + xm * G[b][a];
   // A = B Qp; only the entries needed for the five stored components of S.
-  auto A = [&](int a, int b) { return B[a][0] * Qp[0][b] + B[a][1] * Qp[1][b] + B[a][2] * Qp[2][b]; };
-  const T qg = Q.xx * G[0][0] + Q.yy * G[1][1] + Q.zz() * G[2][2] + Q.xy * (G[0][1] + G[1][0]) +
-               Q.xz * (G[0][2] + G[2][0]) + Q.yz * (G[1][2] + G[2][1]);
+  auto A = [&](int a, int b) { return f.B[a][0] * Qp[0][b] + f.B[a][1] * Qp[1][b] + f.B[a][2] * Qp[2][b]; };
+  const T qg = Q.xx * f.g[0] + Q.yy * f.g[1] + Q.xy * f.g[2] + Q.xz * f.g[3] + Q.yz * f.g[4];
   const T k = RAW ? c.xi * qg : T(2) * c.xi * qg;
+  const T(&u)[3] = f.u;
   Sym<T> R;
   R.xx = c.Gam * H.xx + T(2) * A(0, 0) - k * Qp[0][0] -
          (u[0] * dQ[0].xx + u[1] * dQ[1].xx + u[2] * dQ[2].xx);
@@ -194,6 +216,12 @@ LC_HD Sym<T> be_rate(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
   R.yz = c.Gam * H.yz + A(1, 2) + A(2, 1) - k * Qp[1][2] -
          (u[0] * dQ[0].yz + u[1] * dQ[1].yz + u[2] * dQ[2].yz);
   return R;
+}
+
+template <typename T, bool RAW = false>
+LC_HD Sym<T> be_rate(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3], const T (&u)[3],
+                     const T (&G)[3][3], const Coef<T>& c) {
+  return be_rate_flow<T, RAW>(Q, H, dQ, flow_terms<T, RAW>(u, G, c), c);
 }
 
 // ---------------------------------------------------------------------------

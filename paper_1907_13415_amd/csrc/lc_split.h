@@ -359,56 +359,66 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   for (int a = 0; a < DIM; a++) src[5 + a] = uin + a * N;
   const S* const* csrc = src;
 
-  // What the owner keeps from its predictor for its corrector: Q, R(Q), u/2
-  // and the undivided velocity differences (be_rate in RAW form).
+  // What the owner keeps from its predictor for its corrector: R(Q) and the
+  // flow terms (from u/2 and the undivided velocity differences; RAW form).
+  // With the four-plane ring Q itself is read back from LDS (plane p-1 stays
+  // there until the barrier of iteration p+1); with three planes the next
+  // iteration overwrites it without a barrier, so the owner keeps it.
   struct Stash {
-    Sym<S> q, r;
-    S u[3];
-    S G[3][3];
+    Sym<S> r;
+    Flow<S> fl;
+    Sym<S> q;  // used without the four-plane ring only
   };
 
-  // rate and predictor at R1 point (i, j) of plane slot m
+  // rate and predictor at R1 point (i, j) of plane slot m; returns Q^P
   auto pred_point = [&](int m, int zp, int zm, int i, int j, Stash& st) {
     const int k = T::r2(i, j);
     Sym<S> q, Lq, d[3];
     stencil_lds<S, DIM, T::W2, T::R2, false>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
     const Sym<S> H = molecular_field(q, Lq, c);
+    S u[3], G[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-      st.u[a] = a < DIM ? sQ[m][5 + a][k] * S(0.5) : S(0);
-      st.G[a][0] = a < DIM ? sQ[m][5 + a][k + 1] - sQ[m][5 + a][k - 1] : S(0);
-      st.G[a][1] = a < DIM ? sQ[m][5 + a][k + T::W2] - sQ[m][5 + a][k - T::W2] : S(0);
+      u[a] = a < DIM ? sQ[m][5 + a][k] * S(0.5) : S(0);
+      G[a][0] = a < DIM ? sQ[m][5 + a][k + 1] - sQ[m][5 + a][k - 1] : S(0);
+      G[a][1] = a < DIM ? sQ[m][5 + a][k + T::W2] - sQ[m][5 + a][k - T::W2] : S(0);
       if constexpr (DIM == 3)
-        st.G[a][2] = sQ[zp][5 + a][k] - sQ[zm][5 + a][k];
+        G[a][2] = sQ[zp][5 + a][k] - sQ[zm][5 + a][k];
       else
-        st.G[a][2] = S(0);
+        G[a][2] = S(0);
     }
-    st.q = q;
-    st.r = be_rate<S, true>(q, H, d, st.u, st.G, c);
+    st.fl = flow_terms<S, true>(u, G, c);
+    st.r = be_rate_flow<S, true>(q, H, d, st.fl, c);
+    if constexpr (!RING4) st.q = q;
+    return Sym<S>{q.xx + st.r.xx, q.xy + st.r.xy, q.xz + st.r.xz, q.yy + st.r.yy, q.yz + st.r.yz};
   };
-  // predictor over the region (pass 0: the owner's site, pass 1: a ring
-  // site, same code for both) into sP[ps]; the owner keeps its stash
+  auto store_pred = [&](int ps, int i, int j, const Sym<S>& qp) {
+    const int k1 = i + T::W1 * j;
+    sP[ps][0][k1] = qp.xx;
+    sP[ps][1][k1] = qp.xy;
+    sP[ps][2][k1] = qp.xz;
+    sP[ps][3][k1] = qp.yy;
+    sP[ps][4][k1] = qp.yz;
+  };
+  // predictor over the region into sP[ps]: the owner's site (kept in st),
+  // then a ring site for threads tid < RING.  The two calls inline the same
+  // expressions, and contraction into FMAs happens only within a source
+  // expression, so a site's predictor rounds the same as owner or ring.
   auto pred_plane = [&](int m, int zp, int zm, int ps, Stash& st) {
-#pragma unroll 1
-    for (int pass = 0; pass < 2; pass++) {
-      if (pass == 1 && tid >= T::RING) break;
-      int i = tx + 1, j = ty + 1;
-      if (pass == 1) T::ring(tid, i, j);
+    store_pred(ps, tx + 1, ty + 1, pred_point(m, zp, zm, tx + 1, ty + 1, st));
+    if (tid < T::RING) {
+      int i, j;
+      T::ring(tid, i, j);
       Stash tmp;
-      pred_point(m, zp, zm, i, j, tmp);
-      const int k1 = i + T::W1 * j;
-      sP[ps][0][k1] = tmp.q.xx + tmp.r.xx;
-      sP[ps][1][k1] = tmp.q.xy + tmp.r.xy;
-      sP[ps][2][k1] = tmp.q.xz + tmp.r.xz;
-      sP[ps][3][k1] = tmp.q.yy + tmp.r.yy;
-      sP[ps][4][k1] = tmp.q.yz + tmp.r.yz;
-      if (pass == 0) st = tmp;
+      store_pred(ps, i, j, pred_point(m, zp, zm, i, j, tmp));
     }
   };
   // corrector at the owner's site of plane z from the predictor planes
   // ps (plane z) and pzp / pzm (planes z+1 / z-1)
-  auto corr_site = [&](int z, int ps, int pzp, int pzm, const Stash& st) {
+  auto corr_site = [&](int z, int m, int ps, int pzp, int pzm, const Stash& st) {
     if (!own) return;
+    const int kq = T::r2(tx + 1, ty + 1);
+    const Sym<S> q = RING4 ? Sym<S>{sQ[m][0][kq], sQ[m][1][kq], sQ[m][2][kq], sQ[m][3][kq], sQ[m][4][kq]} : st.q;
     const int k1 = (tx + 1) + T::W1 * (ty + 1);
     S v[5], lap[5], dx[5], dy[5], dz[5];
 #pragma unroll
@@ -435,14 +445,14 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
                          Sym<S>{dz[0], dz[1], dz[2], dz[3], dz[4]}};
     const Sym<S> Lp{lap[0], lap[1], lap[2], lap[3], lap[4]};
     const Sym<S> H = molecular_field(p, Lp, c);
-    const Sym<S> Rp = be_rate<S, true>(p, H, d, st.u, st.G, c);
+    const Sym<S> Rp = be_rate_flow<S, true>(p, H, d, st.fl, c);
     const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
     if (rec) store_sym(rec, N, s, p);  // record the predictor (reverse-mode replay)
-    Qout[s] = st.q.xx + S(0.5) * (st.r.xx + Rp.xx);
-    Qout[N + s] = st.q.xy + S(0.5) * (st.r.xy + Rp.xy);
-    Qout[2 * N + s] = st.q.xz + S(0.5) * (st.r.xz + Rp.xz);
-    Qout[3 * N + s] = st.q.yy + S(0.5) * (st.r.yy + Rp.yy);
-    Qout[4 * N + s] = st.q.yz + S(0.5) * (st.r.yz + Rp.yz);
+    Qout[s] = q.xx + S(0.5) * (st.r.xx + Rp.xx);
+    Qout[N + s] = q.xy + S(0.5) * (st.r.xy + Rp.xy);
+    Qout[2 * N + s] = q.xz + S(0.5) * (st.r.xz + Rp.xz);
+    Qout[3 * N + s] = q.yy + S(0.5) * (st.r.yy + Rp.yy);
+    Qout[4 * N + s] = q.yz + S(0.5) * (st.r.yz + Rp.yz);
   };
 
   if constexpr (DIM == 2) {
@@ -451,7 +461,7 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     Stash st;
     pred_plane(0, 0, 0, 0, st);
     __syncthreads();
-    corr_site(0, 0, 0, 0, st);
+    corr_site(0, 0, 0, 0, 0, st);
   } else {
     const int zb = bz * zc;
     const int ze = min(zb + zc, g.nz);
@@ -475,7 +485,7 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
       // the owner's own Q^P of plane p, written by the same thread
       pred_plane(slot(p), slot(p + 1), slot(p - 1), pslot(p), cur);
       if constexpr (!RING4) __syncthreads();
-      if (p - 1 >= zb) corr_site(p - 1, pslot(p - 1), pslot(p), pslot(p - 2), prev);
+      if (p - 1 >= zb) corr_site(p - 1, slot(p - 1), pslot(p - 1), pslot(p), pslot(p - 2), prev);
     };
     // two planes per trip, so the two stashes swap roles without copies
     Stash stA, stB;
