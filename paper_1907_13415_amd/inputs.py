@@ -83,6 +83,27 @@ def flat_slab_2d(nx, ny, theta, half_width=None, width=4.0, s_n=1.0 / 3.0):
     return uniaxial_q5(S, n)
 
 
+def paper_flat(nx, ny, half_width=None):
+    """Sec. 2.1 setup: nematic slab in the middle of a periodic box, director
+    vertical (along y), isotropic elsewhere, tanh edges of width 2 lambda = 4
+    at S_n = 1/3."""
+    return flat_slab_2d(nx, ny, math.pi / 2, half_width=half_width)
+
+
+def paper_circle(n=100, radius=25.0, angle_deg=0.0, width=4.0, s_n=1.0 / 3.0):
+    """Sec. 2.2 setup: a nematic disc of the given radius centred in an n x n
+    periodic box, uniform director n = (sin a, cos a, 0) (a = 0: vertical),
+    tanh edge of width 2 lambda = 4."""
+    y, x = np.meshgrid(np.arange(n, dtype=np.float64), np.arange(n, dtype=np.float64), indexing="ij")
+    r = np.hypot(x - n / 2.0, y - n / 2.0)
+    S = tanh_edge(r - radius, width, s_n)[None]
+    a = math.radians(angle_deg)
+    nvec = np.zeros((3, 1, n, n))
+    nvec[0] = math.sin(a)
+    nvec[1] = math.cos(a)
+    return uniaxial_q5(S, nvec)
+
+
 def config0():
     """128 x 16 D2Q9 flat interface, director angle theta ~ U[0, pi)."""
     rng = np.random.default_rng(0)
