@@ -51,6 +51,10 @@ def _load():
         lib.lco_lattice.restype = ctypes.c_int
         lib.lco_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_long]
         lib.lco_run.restype = ctypes.c_int
+        lib.lco_run_coll.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, _dp, ctypes.c_long]
+        lib.lco_run_coll.restype = ctypes.c_int
+        lib.lco_mrt_basis.argtypes = [ctypes.c_int, _dp]
+        lib.lco_mrt_basis.restype = ctypes.c_int
         lib.lco_fields.argtypes = [ctypes.c_int] * 4 + [_dp] * 12
         lib.lco_fields.restype = ctypes.c_int
         lib.lco_rate.argtypes = [ctypes.c_int] * 3 + [_dp] * 6
@@ -96,16 +100,55 @@ def _dims(q5):
     return nx, ny, nz
 
 
-def run(lat, f, q5, params, nsteps):
-    """Advance (f, q5) by nsteps; returns new arrays."""
+def run(lat, f, q5, params, nsteps, rates=None):
+    """Advance (f, q5) by nsteps; returns new arrays.  With rates (q values,
+    one per moment of the MRT basis, see mrt_basis) the collision is MRT,
+    else BGK."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     q5 = np.array(q5, dtype=np.float64, order="C", copy=True)
     nx, ny, nz = _dims(q5)
     p = _params(params)
-    rc = _load().lco_run(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(nsteps))
+    if rates is None:
+        rc = _load().lco_run(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(nsteps))
+    else:
+        r = np.ascontiguousarray(np.asarray(rates, dtype=np.float64))
+        assert r.shape == (f.shape[0],), "one rate per moment"
+        rc = _load().lco_run_coll(lat, nx, ny, nz, _ptr(p), _ptr(r), _ptr(f), _ptr(q5), int(nsteps))
     if rc != 0:
         raise ValueError("lco_run failed: %d" % rc)
     return f, q5
+
+
+def mrt_basis(lat):
+    """The MRT moment matrix M (q, q): row k = moment k at each velocity.
+    D2Q9: rho, e, eps, jx, qx, jy, qy, pxx, pxy; D3Q19: rho, e, eps, jx, qx,
+    jy, qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz, pxz, mx, my, mz."""
+    q = 9 if lat == D2Q9 else 19
+    M = np.zeros((q, q))
+    assert _load().lco_mrt_basis(lat, _ptr(M)) == q
+    return M
+
+
+# moment groups of the MRT bases: conserved, shear (relaxed at 1/tau) and the
+# other (non-hydrodynamic) groups in the order the library takes their rates
+MRT_GROUPS = {
+    D2Q9: dict(conserved=[0, 3, 5], shear=[7, 8], ghosts=[[1], [2], [4, 6]]),
+    D3Q19: dict(conserved=[0, 3, 5, 7], shear=[9, 11, 13, 14, 15],
+                ghosts=[[1], [2], [4, 6, 8], [10, 12], [16, 17, 18]]),
+}
+
+
+def mrt_rates(lat, tau, ghost_rates):
+    """Per-moment rate vector: conserved and shear moments at 1/tau, each
+    non-hydrodynamic group at its rate (D2Q9: s_e, s_eps, s_q; D3Q19: s_e,
+    s_eps, s_q, s_pi, s_m)."""
+    g = MRT_GROUPS[lat]
+    q = 9 if lat == D2Q9 else 19
+    r = np.full(q, 1.0 / tau)
+    assert len(ghost_rates) == len(g["ghosts"])
+    for ks, v in zip(g["ghosts"], ghost_rates):
+        r[ks] = v
+    return r
 
 
 def fields(lat, f, q5, params):

@@ -20,7 +20,9 @@
  *   parameters p[6] = (A0, gamma, K, Gamma, xi, tau).
  *
  * Readings of the paper used here (where it is silent):
- *   - The collision is BGK with the BGK forcing term printed in Sec. 1.2.1.
+ *   - The collision is BGK with the BGK forcing term printed in Sec. 1.2.1;
+ *     lco_run_coll also offers the MRT operator on the standard moment
+ *     bases (the paper's operator, whose matrix and rates it does not give).
  *   - The Laplacian is the compact (2d+1)-point second difference summed over
  *     the axes; first derivatives are the central differences of Sec. 1.2.2.
  *   - One step is Jacobi in time: F, rho and u come from the state at step n;
@@ -461,11 +463,138 @@ int lco_stress(int nx, int ny, int nz, const double *p, const double *q5,
   return 0;
 }
 
+/* ---- multiple-relaxation-time collision (MRT) ------------------------------
+ * The paper ran an MRT operator but defers its matrix and rates to another
+ * paper (Sec. 1.2.1).  Here the standard orthogonal moment bases: for D2Q9
+ * the nine moments of Lallemand and Luo (Phys. Rev. E 61, 6546 (2000)),
+ * for D3Q19 the nineteen of d'Humieres et al. (Phil. Trans. R. Soc. A 360,
+ * 437 (2002)), each row a polynomial in the lattice velocity c (c2 = |c|^2),
+ * listed in the published order:
+ *   D2Q9 : rho, e, eps, jx, qx, jy, qy, pxx, pxy
+ *   D3Q19: rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww,
+ *          pxy, pyz, pxz, mx, my, mz.
+ * The collision acts in moment space, m = M f:
+ *   m* = m - S (m - M f_eq) + (I - S/2) M G,   f* = M^-1 m*,
+ * where S = diag(s_k) and G is the forcing term of Sec. 1.2.1 without its
+ * factor (1 - 1/(2 tau)).  With every s_k = 1/tau this is the BGK step
+ * above. */
+static double basis_row(int lattice, int k, const int c[3]) {
+  const double cx = c[0], cy = c[1], cz = c[2];
+  const double c2 = cx * cx + cy * cy + cz * cz;
+  if (lattice == LCO_D2Q9) {
+    switch (k) {
+      case 0: return 1.0;
+      case 1: return 3.0 * c2 - 4.0;
+      case 2: return (9.0 * c2 * c2 - 21.0 * c2 + 8.0) / 2.0;
+      case 3: return cx;
+      case 4: return (3.0 * c2 - 5.0) * cx;
+      case 5: return cy;
+      case 6: return (3.0 * c2 - 5.0) * cy;
+      case 7: return cx * cx - cy * cy;
+      case 8: return cx * cy;
+    }
+    return 0.0;
+  }
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return cx;
+    case 4: return (5.0 * c2 - 9.0) * cx;
+    case 5: return cy;
+    case 6: return (5.0 * c2 - 9.0) * cy;
+    case 7: return cz;
+    case 8: return (5.0 * c2 - 9.0) * cz;
+    case 9: return 3.0 * cx * cx - c2;
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * cx * cx - c2);
+    case 11: return cy * cy - cz * cz;
+    case 12: return (3.0 * c2 - 5.0) * (cy * cy - cz * cz);
+    case 13: return cx * cy;
+    case 14: return cy * cz;
+    case 15: return cx * cz;
+    case 16: return (cy * cy - cz * cz) * cx;
+    case 17: return (cz * cz - cx * cx) * cy;
+    case 18: return (cx * cx - cy * cy) * cz;
+  }
+  return 0.0;
+}
+
+/* M[k*q + i] = row k at velocity i.  Returns q, or -1. */
+int lco_mrt_basis(int lattice, double *M) {
+  lattice_t L;
+  if (get_lattice(lattice, &L)) return -1;
+  for (int k = 0; k < L.q; k++)
+    for (int i = 0; i < L.q; i++) M[k * L.q + i] = basis_row(lattice, k, L.c[i]);
+  return L.q;
+}
+
+/* Inverse of a q x q matrix by Gauss-Jordan elimination with partial
+ * pivoting.  Returns 0, or -1 if singular. */
+static int invert(int q, const double *A, double *Ainv) {
+  double a[19 * 38];
+  for (int r = 0; r < q; r++)
+    for (int k = 0; k < 2 * q; k++) a[r * 2 * q + k] = k < q ? A[r * q + k] : (k - q == r ? 1.0 : 0.0);
+  for (int col = 0; col < q; col++) {
+    int piv = col;
+    for (int r = col + 1; r < q; r++)
+      if (fabs(a[r * 2 * q + col]) > fabs(a[piv * 2 * q + col])) piv = r;
+    if (a[piv * 2 * q + col] == 0.0) return -1;
+    if (piv != col)
+      for (int k = 0; k < 2 * q; k++) {
+        double t = a[col * 2 * q + k];
+        a[col * 2 * q + k] = a[piv * 2 * q + k];
+        a[piv * 2 * q + k] = t;
+      }
+    double d = a[col * 2 * q + col];
+    for (int k = 0; k < 2 * q; k++) a[col * 2 * q + k] /= d;
+    for (int r = 0; r < q; r++) {
+      if (r == col) continue;
+      double m = a[r * 2 * q + col];
+      for (int k = 0; k < 2 * q; k++) a[r * 2 * q + k] -= m * a[col * 2 * q + k];
+    }
+  }
+  for (int r = 0; r < q; r++)
+    for (int k = 0; k < q; k++) Ainv[r * q + k] = a[r * 2 * q + q + k];
+  return 0;
+}
+
+typedef struct {
+  double M[19 * 19], Minv[19 * 19], s[19];
+} mrt_t;
+
+/* Post-collision populations at one site with the MRT operator. */
+static void collide_mrt(const lattice_t *L, const mrt_t *op, const double *fin, double rho, const double u[3],
+                        const double F[3], double *out) {
+  const int q = L->q;
+  double feq[19], G[19], ms[19];
+  for (int i = 0; i < q; i++) {
+    feq[i] = feq_i(L, i, rho, u);
+    double cu = 0.0, g = 0.0;
+    for (int a = 0; a < 3; a++) cu += L->c[i][a] * u[a];
+    for (int a = 0; a < 3; a++) g += (L->c[i][a] / CS2 * (1.0 + cu / CS2) - u[a] / CS2) * F[a];
+    G[i] = L->w[i] * g;
+  }
+  for (int k = 0; k < q; k++) {
+    double mk = 0.0, mek = 0.0, mgk = 0.0;
+    for (int i = 0; i < q; i++) {
+      mk += op->M[k * q + i] * fin[i];
+      mek += op->M[k * q + i] * feq[i];
+      mgk += op->M[k * q + i] * G[i];
+    }
+    ms[k] = mk - op->s[k] * (mk - mek) + (1.0 - op->s[k] / 2.0) * mgk;
+  }
+  for (int i = 0; i < q; i++) {
+    double v = 0.0;
+    for (int k = 0; k < q; k++) v += op->Minv[i * q + k] * ms[k];
+    out[i] = v;
+  }
+}
+
 /* ---- one full time step ---------------------------------------------------
  * Molecular field and stress from Q(n); body force; rho and force-corrected
  * u; Heun predictor-corrector for Q (Sec. 1.2.2 steps 1-5) with u, grad u
  * frozen; BGK collision with forcing; periodic streaming. */
-static void one_step(const grid_t *g, const lattice_t *L, const double *p,
+static void one_step(const grid_t *g, const lattice_t *L, const double *p, const mrt_t *op,
                      const double *f, const double *q5, double *f_out, double *q5_out,
                      double *tau9, double *F3, double *rho, double *u3,
                      double *R5, double *qp, double *Rp5) {
@@ -487,21 +616,36 @@ static void one_step(const grid_t *g, const lattice_t *L, const double *p,
     }
     long x, y, z;
     coords(g, s, &x, &y, &z);
+    double fin[19], post[19];
+    for (int i = 0; i < L->q; i++) fin[i] = f[(size_t)i * N + s];
+    if (op) {
+      collide_mrt(L, op, fin, rho[s], u, F, post);
+    } else {
+      for (int i = 0; i < L->q; i++)
+        post[i] = fin[i] - (fin[i] - feq_i(L, i, rho[s], u)) / tau + source_i(L, i, tau, u, F);
+    }
     for (int i = 0; i < L->q; i++) {
-      double fi = f[(size_t)i * N + s];
-      double post = fi - (fi - feq_i(L, i, rho[s], u)) / tau + source_i(L, i, tau, u, F);
       size_t d = site(g, x + L->c[i][0], y + L->c[i][1], z + L->c[i][2]);
-      f_out[(size_t)i * N + d] = post;
+      f_out[(size_t)i * N + d] = post[i];
     }
   }
 }
 
-/* Advance (f, q5) by nsteps in place.  Returns 0, -1 bad args, -2 no memory. */
-int lco_run(int lattice, int nx, int ny, int nz, const double *p, double *f, double *q5,
-            long nsteps) {
+/* Advance (f, q5) by nsteps in place with the MRT collision when rates
+ * (q relaxation rates in the basis order above) is not NULL, else BGK.
+ * Returns 0, -1 bad args, -2 no memory. */
+int lco_run_coll(int lattice, int nx, int ny, int nz, const double *p, const double *rates, double *f,
+                 double *q5, long nsteps) {
   lattice_t L;
   grid_t g;
   if (check_args(lattice, nx, ny, nz, p, &L, &g) || nsteps < 0) return -1;
+  mrt_t op, *opp = NULL;
+  if (rates) {
+    lco_mrt_basis(lattice, op.M);
+    if (invert(L.q, op.M, op.Minv)) return -1;
+    for (int k = 0; k < L.q; k++) op.s[k] = rates[k];
+    opp = &op;
+  }
   const size_t N = g.N;
   double *f2 = malloc((size_t)L.q * N * sizeof(double));
   double *q2 = malloc(5 * N * sizeof(double));
@@ -514,12 +658,17 @@ int lco_run(int lattice, int nx, int ny, int nz, const double *p, double *f, dou
   double *Rp5 = malloc(5 * N * sizeof(double));
   if (!f2 || !q2 || !tau9 || !F3 || !rho || !u3 || !R5 || !qp || !Rp5) return -2;
   for (long n = 0; n < nsteps; n++) {
-    one_step(&g, &L, p, f, q5, f2, q2, tau9, F3, rho, u3, R5, qp, Rp5);
+    one_step(&g, &L, p, opp, f, q5, f2, q2, tau9, F3, rho, u3, R5, qp, Rp5);
     memcpy(f, f2, (size_t)L.q * N * sizeof(double));
     memcpy(q5, q2, 5 * N * sizeof(double));
   }
   free(f2); free(q2); free(tau9); free(F3); free(rho); free(u3); free(R5); free(qp); free(Rp5);
   return 0;
+}
+
+/* Advance (f, q5) by nsteps with the BGK collision. */
+int lco_run(int lattice, int nx, int ny, int nz, const double *p, double *f, double *q5, long nsteps) {
+  return lco_run_coll(lattice, nx, ny, nz, p, NULL, f, q5, nsteps);
 }
 
 /* ---- observables ----------------------------------------------------------
