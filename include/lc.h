@@ -61,6 +61,10 @@ typedef int32_t lc_status;
 #define LC_FP64 0
 #define LC_FP32_DEV 1
 
+/* Collision operators for lc_set_collision. */
+#define LC_COLL_BGK 0 /* single relaxation time (default) */
+#define LC_COLL_MRT 1 /* multiple relaxation times, standard orthogonal moment bases */
+
 /* Kernel variants for lc_set_variant. */
 #define LC_VARIANT_AUTO 0
 #define LC_VARIANT_STAGED 1 /* one kernel per stage, intermediates in scratch */
@@ -159,6 +163,22 @@ lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 /* Choose the kernel variant (LC_VARIANT_*); AUTO picks the fastest the
  * build provides for this grid.  LC_EUNSUPPORTED if not available. */
 lc_status lc_set_variant(lc_ctx *ctx, int32_t variant);
+
+/* Collision operator of the lattice-Boltzmann update.  LC_COLL_BGK (the
+ * default): relaxation at 1/tau with the forcing term of Sec. 1.2.1.
+ * LC_COLL_MRT: the multiple-relaxation-time operator the paper ran
+ * (Sec. 1.2.1 names it but leaves its matrix and rates to another paper),
+ * on the standard orthogonal moment bases (Lallemand and Luo 2000 for D2Q9,
+ * d'Humieres et al. 2002 for D3Q19) with the same forcing in moment space:
+ * m* = m - S (m - m_eq) + (I - S/2) M G.  Density, momentum and the
+ * traceless stress relax at 1/tau (so the viscosity stays (tau - 1/2)/3);
+ * rates[nrates] (host array) gives the rate of each other moment group:
+ * D2Q9 (s_e, s_eps, s_q), D3Q19 (s_e, s_eps, s_q, s_pi, s_m), each in
+ * (0, 2).  With every rate 1/tau, MRT equals BGK up to rounding.  Applies to
+ * the steps enqueued after the call.  LC_EINVAL for an unknown kind, a
+ * wrong count or a rate outside (0, 2).  The reverse step supports BGK
+ * only (LC_EUNSUPPORTED otherwise). */
+lc_status lc_set_collision(lc_ctx *ctx, int32_t kind, const double *rates, int32_t nrates);
 
 /* Planes each block marches through along z in the two-sweep kernels
  * (>= 1; larger chunks recompute fewer boundary planes, smaller chunks give

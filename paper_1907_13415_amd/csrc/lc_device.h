@@ -69,6 +69,65 @@ struct Lattice<1> {  // D3Q19
 };
 
 // ---------------------------------------------------------------------------
+// Non-hydrodynamic ("ghost") moments of the standard orthogonal MRT bases:
+// Lallemand and Luo (2000) for D2Q9, d'Humieres et al. (2002) for D3Q19.
+// Each is a polynomial in the lattice velocity (c2 = |c|^2); the remaining
+// moments of those bases are density, momentum and the traceless stress,
+// which the collision treats as in BGK (stress relaxed at 1/tau).  A ghost
+// belongs to a rate group; even ghosts do not change sign under c -> -c,
+// odd ones do.
+template <int LAT>
+struct Ghosts;
+
+template <>
+struct Ghosts<0> {  // e, eps, qx, qy; groups e, eps, q
+  static constexpr int n = 4;
+  static constexpr int ngroups = 3;
+  __host__ __device__ static constexpr int group(int k) { return k < 2 ? k : 2; }
+  __host__ __device__ static constexpr bool odd(int k) { return k >= 2; }
+  __host__ __device__ static constexpr int m(int k, int i) {
+    using L = Lattice<0>;
+    const int cx = L::cx(i), cy = L::cy(i), c2 = cx * cx + cy * cy;
+    return k == 0 ? 3 * c2 - 4 : (k == 1 ? (9 * c2 * c2 - 21 * c2 + 8) / 2 : (3 * c2 - 5) * (k == 2 ? cx : cy));
+  }
+};
+
+template <>
+struct Ghosts<1> {  // e, eps, qx, qy, qz, 3pixx, piww, mx, my, mz; groups e, eps, q, pi, m
+  static constexpr int n = 10;
+  static constexpr int ngroups = 5;
+  __host__ __device__ static constexpr int group(int k) {
+    return k < 2 ? k : (k < 5 ? 2 : (k < 7 ? 3 : 4));
+  }
+  __host__ __device__ static constexpr bool odd(int k) { return (k >= 2 && k < 5) || k >= 7; }
+  __host__ __device__ static constexpr int m(int k, int i) {
+    using L = Lattice<1>;
+    const int cx = L::cx(i), cy = L::cy(i), cz = L::cz(i);
+    const int xx = cx * cx, yy = cy * cy, zz = cz * cz, c2 = xx + yy + zz;
+    switch (k) {
+      case 0: return 19 * c2 - 30;
+      case 1: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+      case 2: return (5 * c2 - 9) * cx;
+      case 3: return (5 * c2 - 9) * cy;
+      case 4: return (5 * c2 - 9) * cz;
+      case 5: return (3 * c2 - 5) * (3 * xx - c2);
+      case 6: return (3 * c2 - 5) * (yy - zz);
+      case 7: return (yy - zz) * cx;
+      case 8: return (zz - xx) * cy;
+      default: return (xx - yy) * cz;
+    }
+  }
+};
+
+// Squared norm of ghost k over the velocity set.
+template <int LAT>
+__host__ __device__ constexpr int ghost_norm(int k) {
+  int s = 0;
+  for (int i = 0; i < Lattice<LAT>::q; i++) s += Ghosts<LAT>::m(k, i) * Ghosts<LAT>::m(k, i);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
 // Per-launch constants derived from lc_params (in the arithmetic type).
 template <typename T>
 struct Coef {
@@ -82,6 +141,8 @@ struct Coef {
   T omega;   // 1/tau
   T src;     // 1 - 1/(2 tau)
   T A0;      // bulk coefficient (the adjoint needs d/dgamma of lin and quad)
+  // MRT: rate of each ghost group minus 1/tau (unused by the BGK kernels)
+  T mrt[5];
 };
 
 template <typename T>

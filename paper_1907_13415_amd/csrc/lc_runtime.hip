@@ -80,6 +80,7 @@ Coef<S> make_coef(const lc_params& p) {
   c.omega = S(1.0 / p.tau);
   c.src = S(1.0 - 1.0 / (2.0 * p.tau));
   c.A0 = S(p.A0);
+  for (int g = 0; g < 5; g++) c.mrt[g] = S(0);
   return c;
 }
 
@@ -141,6 +142,8 @@ struct lc_ctx {
   bool loaded;
   int variant;
   int zchunk;  // 0: default
+  int coll;        // LC_COLL_*
+  double mrt[5];   // MRT rates of the ghost groups
   // optional per-launch timing of the step kernels (events on the stream)
   bool timing;
   std::vector<hipEvent_t> ev;     // recorded around each launch, 3 per step
@@ -162,6 +165,16 @@ static hipEvent_t ctx_event(lc_ctx* c) {
   }
   return e;
 }
+// Kernel constants of the context: parameters plus, for MRT, each ghost
+// group's rate minus 1/tau.
+template <typename S>
+static Coef<S> ctx_coef(const lc_ctx* c) {
+  Coef<S> k = make_coef<S>(c->p);
+  if (c->coll == LC_COLL_MRT)
+    for (int g = 0; g < 5; g++) k.mrt[g] = S(c->mrt[g] - 1.0 / c->p.tau);
+  return k;
+}
+
 static void ctx_mark(lc_ctx* c) {
   if (!c->timing) return;
   hipEvent_t e = ctx_event(c);
@@ -177,7 +190,7 @@ static void ctx_mark(lc_ctx* c) {
 template <int LAT, typename S, bool DEV>
 static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
-  const Coef<S> k = make_coef<S>(c->p);
+  const Coef<S> k = ctx_coef<S>(c);
   char* scr = static_cast<char*>(c->b.scratch);
   S* tau = reinterpret_cast<S*>(scr + c->L.off_tau);
   S* u = reinterpret_cast<S*>(scr + c->L.off_u);
@@ -190,7 +203,10 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
     const S* q0 = static_cast<const S*>(c->b.Q[c->parity]);
     S* q1 = static_cast<S*>(c->b.Q[c->parity ^ 1]);
     hipLaunchKernelGGL((stage_tau<LAT, S>), grid, block, 0, c->stream, q0, tau, gd, k);
-    hipLaunchKernelGGL((stage_lb<LAT, S, DEV>), grid, block, 0, c->stream, f0, tau, f1, u, gd, k);
+    if (c->coll == LC_COLL_MRT)
+      hipLaunchKernelGGL((stage_lb<LAT, S, DEV, true>), grid, block, 0, c->stream, f0, tau, f1, u, gd, k);
+    else
+      hipLaunchKernelGGL((stage_lb<LAT, S, DEV>), grid, block, 0, c->stream, f0, tau, f1, u, gd, k);
     hipLaunchKernelGGL((stage_pred<LAT, S>), grid, block, 0, c->stream, q0, u, qp, rq, gd, k);
     hipLaunchKernelGGL((stage_corr<LAT, S>), grid, block, 0, c->stream, q0, qp, rq, u, q1, gd, k);
     c->parity ^= 1;
@@ -209,7 +225,7 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
                             S* rec_lb, S* rec_q) {
   using C = SplitCfg<LAT, S>;
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
-  const Coef<S> k = make_coef<S>(c->p);
+  const Coef<S> k = ctx_coef<S>(c);
   const int zc1 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_LB) : 1;
   const int zc2 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_Q) : 1;
   const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY,
@@ -217,8 +233,12 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY,
                 unsigned((c->g.nz + zc2 - 1) / zc2));
   if (mark) ctx_mark(c);
-  hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, st, q0,
-                     f0, f1, u, gd, k, zc1, rec_lb);
+  if (c->coll == LC_COLL_MRT)
+    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, true>), g1, dim3(C::LB_TX, C::LB_TY), 0,
+                       st, q0, f0, f1, u, gd, k, zc1, rec_lb);
+  else
+    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, st,
+                       q0, f0, f1, u, gd, k, zc1, rec_lb);
   if (mark) ctx_mark(c);
   hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1, gd,
                      k, zc2, rec_q);
@@ -413,6 +433,8 @@ lc_status lc_init(const lc_grid* grid, const lc_params* params, const lc_buffers
   c->step = 0;
   c->loaded = false;
   c->variant = LC_VARIANT_SPLIT;
+  c->coll = LC_COLL_BGK;
+  for (double& r : c->mrt) r = 0.0;
   c->zchunk = 0;
   c->timing = false;
   *out = c;
@@ -441,6 +463,24 @@ lc_status lc_set_variant(lc_ctx* c, int32_t variant) {
   }
   if (variant == LC_VARIANT_FUSED) return fail(LC_EUNSUPPORTED, "variant %d not available", variant);
   return fail(LC_EINVAL, "unknown variant %d", variant);
+}
+
+lc_status lc_set_collision(lc_ctx* c, int32_t kind, const double* rates, int32_t nrates) {
+  clear_error();
+  if (!c) return fail(LC_EINVAL, "ctx is NULL");
+  if (kind == LC_COLL_BGK) {
+    c->coll = LC_COLL_BGK;
+    return LC_OK;
+  }
+  if (kind != LC_COLL_MRT) return fail(LC_EINVAL, "unknown collision %d", kind);
+  const int ng = c->g.lattice == LC_D2Q9 ? Ghosts<0>::ngroups : Ghosts<1>::ngroups;
+  if (!rates) return fail(LC_EINVAL, "rates is NULL");
+  if (nrates != ng) return fail(LC_EINVAL, "this lattice takes %d MRT rates (got %d)", ng, nrates);
+  for (int g = 0; g < ng; g++)
+    if (!(rates[g] > 0.0 && rates[g] < 2.0)) return fail(LC_EINVAL, "MRT rate %d = %g outside (0, 2)", g, rates[g]);
+  for (int g = 0; g < 5; g++) c->mrt[g] = g < ng ? rates[g] : 0.0;
+  c->coll = LC_COLL_MRT;
+  return LC_OK;
 }
 
 lc_status lc_set_chunk(lc_ctx* c, int32_t planes) {
@@ -574,6 +614,7 @@ static void vjp_launch(lc_ctx* c, const double* f_n, const double* q_n, double* 
 static lc_status vjp_check(lc_ctx* c) {
   if (c->g.lattice != LC_D2Q9 || c->g.precision != LC_FP64)
     return fail(LC_EUNSUPPORTED, "the reverse step is provided for D2Q9 in double precision");
+  if (c->coll != LC_COLL_BGK) return fail(LC_EUNSUPPORTED, "the reverse step is provided for the BGK collision");
   return LC_OK;
 }
 

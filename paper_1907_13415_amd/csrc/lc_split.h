@@ -155,7 +155,7 @@ __device__ __forceinline__ void store_region(const RegionRegs<S, TX, TY, NC>& r,
 
 // ---------------------------------------------------------------------------
 // Sweep 1: stress in LDS, body force, moments, collision, streaming.
-template <int LAT, typename S, bool DEV, int TX, int TY>
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false>
 __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S* __restrict__ fin,
                                               S* __restrict__ fout, S* __restrict__ uout, const GridDims& g,
                                               const Coef<S>& c, int zc, int bx, int by, int bz,
@@ -273,7 +273,10 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
 #pragma unroll
       for (int a = 0; a < DIM; a++) (rec + size_t(a + 1) * size_t(N))[s] = F[a];
     }
-    collide_pairs<LAT, S, DEV>(f, rho, u, F, c);
+    if constexpr (MRT)
+      collide_mrt<LAT, S, DEV>(f, rho, u, F, c);
+    else
+      collide_pairs<LAT, S, DEV>(f, rho, u, F, c);
 #pragma unroll
     for (int i = 0; i < L::q; i++) (fout + size_t(i) * size_t(N))[s] = f[i];
   };
@@ -315,14 +318,14 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
   }
 }
 
-template <int LAT, typename S, bool DEV, int TX, int TY, int WPE>
+template <int LAT, typename S, bool DEV, int TX, int TY, int WPE, bool MRT = false>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_lb(const S* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ uout,
              GridDims g, Coef<S> c, int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  split_lb_body<LAT, S, DEV, TX, TY>(Qin, fin, fout, uout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
-                                     t / (gridDim.x * gridDim.y), rec);
+  split_lb_body<LAT, S, DEV, TX, TY, MRT>(Qin, fin, fout, uout, g, c, zc, t % gridDim.x,
+                                          (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y), rec);
 }
 
 // ---------------------------------------------------------------------------

@@ -151,6 +151,85 @@ __device__ __forceinline__ void collide_pairs(S (&f)[Lattice<LAT>::q], S rho, co
   }
 }
 
+// Multiple-relaxation-time collision with the same forcing.  In moment
+// space the step is m* = m - S (m - m_eq) + (I - S/2) M G (G: the forcing
+// term without its factor 1 - 1/(2 tau)); with h = f - f_eq + G/2 this is
+//   f* = f + G - sum_k s_k P_k h,
+// P_k the projector on moment k.  Density, momentum and stress relax at
+// omega = 1/tau (h has no density or momentum moment), so
+//   f* = [f + G - omega h] - sum_ghosts (s_g - omega) P_k h,
+// the bracket being the BGK result.  The ghost projections use the pair
+// sums h_i + h_-i for even ghosts and differences for odd ones.
+template <int LAT, typename S, bool DEV>
+__device__ __forceinline__ void collide_mrt(S (&f)[Lattice<LAT>::q], S rho, const S (&u)[3], const S (&F)[3],
+                                            const Coef<S>& c) {
+  using L = Lattice<LAT>;
+  using Gh = Ghosts<LAT>;
+  const S uu15 = S(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const S uF3 = S(3) * (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]);
+  const S base = DEV ? rho - S(1) : rho;
+  S hs[L::q], hd[L::q];  // per pair representative i: h_i + h_-i, h_i - h_-i; hs[0] = h_0
+  {
+    const S w = S(L::w(0));
+    const S feq = w * (base - rho * uu15);
+    const S G = -w * uF3;
+    hs[0] = f[0] - feq + S(0.5) * G;
+    f[0] = f[0] + G - c.omega * hs[0];
+  }
+#pragma unroll
+  for (int i = 1; i < L::q; i++) {
+    if (L::opp(i) < i) continue;
+    const int j = L::opp(i);
+    const S w = S(L::w(i));
+    const S cu = S(L::cx(i)) * u[0] + S(L::cy(i)) * u[1] + S(L::cz(i)) * u[2];
+    const S cF = S(L::cx(i)) * F[0] + S(L::cy(i)) * F[1] + S(L::cz(i)) * F[2];
+    const S eq_e = w * (base + rho * (S(4.5) * cu * cu - uu15));
+    const S eq_o = w * S(3) * rho * cu;
+    const S g_e = w * (S(9) * cF * cu - uF3);
+    const S g_o = w * S(3) * cF;
+    const S hi = f[i] - (eq_e + eq_o) + S(0.5) * (g_e + g_o);
+    const S hj = f[j] - (eq_e - eq_o) + S(0.5) * (g_e - g_o);
+    f[i] = f[i] + (g_e + g_o) - c.omega * hi;
+    f[j] = f[j] + (g_e - g_o) - c.omega * hj;
+    hs[i] = hi + hj;
+    hd[i] = hi - hj;
+  }
+  // coefficient of each ghost: (s_g - omega) (m_k . h) / |m_k|^2
+  S a[Gh::n];
+#pragma unroll
+  for (int k = 0; k < Gh::n; k++) {
+    S acc = Gh::odd(k) ? S(0) : S(Gh::m(k, 0)) * hs[0];
+#pragma unroll
+    for (int i = 1; i < L::q; i++) {
+      if (L::opp(i) < i || Gh::m(k, i) == 0) continue;
+      acc += S(Gh::m(k, i)) * (Gh::odd(k) ? hd[i] : hs[i]);
+    }
+    a[k] = acc * (c.mrt[Gh::group(k)] * S(1.0 / ghost_norm<LAT>(k)));
+  }
+  {
+    S e = S(0);
+#pragma unroll
+    for (int k = 0; k < Gh::n; k++)
+      if (!Gh::odd(k)) e += a[k] * S(Gh::m(k, 0));
+    f[0] -= e;
+  }
+#pragma unroll
+  for (int i = 1; i < L::q; i++) {
+    if (L::opp(i) < i) continue;
+    S e = S(0), o = S(0);
+#pragma unroll
+    for (int k = 0; k < Gh::n; k++) {
+      if (Gh::m(k, i) == 0) continue;
+      if (Gh::odd(k))
+        o += a[k] * S(Gh::m(k, i));
+      else
+        e += a[k] * S(Gh::m(k, i));
+    }
+    f[i] -= e + o;
+    f[L::opp(i)] -= e - o;
+  }
+}
+
 // Storage convention of the population buffers ("pull" form): the buffer
 // of step n holds at site y the post-collision values of step n-1 before
 // streaming, so the populations at x are f_i(x) = buf_i(x - c_i).  Kernels
@@ -173,7 +252,7 @@ __device__ __forceinline__ void gather_f(const S* __restrict__ buf, int64_t N, i
   }
 }
 
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, bool MRT = false>
 __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const S* __restrict__ tau,
                                                 S* __restrict__ fout, S* __restrict__ uout,
                                                 GridDims g, Coef<S> c) {
@@ -193,7 +272,10 @@ __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const
   moments<LAT, S, DEV>(f, F, rho, u);
 #pragma unroll
   for (int a = 0; a < L::dim; a++) uout[a * N + s] = u[a];
-  collide<LAT, S, DEV>(f, rho, u, F, c);
+  if constexpr (MRT)
+    collide_mrt<LAT, S, DEV>(f, rho, u, F, c);
+  else
+    collide<LAT, S, DEV>(f, rho, u, F, c);
 #pragma unroll
   for (int i = 0; i < L::q; i++) fout[i * N + s] = f[i];
 }

@@ -21,6 +21,7 @@ LC_OK, LC_EINVAL, LC_ENOMEM, LC_EDEVICE, LC_ENONFINITE, LC_ESTATE, LC_EUNSUPPORT
 LC_D2Q9, LC_D3Q19 = 0, 1
 LC_FP64, LC_FP32_DEV = 0, 1
 LC_VARIANT_AUTO, LC_VARIANT_STAGED, LC_VARIANT_SPLIT, LC_VARIANT_FUSED = 0, 1, 2, 3
+LC_COLL_BGK, LC_COLL_MRT = 0, 1
 LC_OBS_MASS, LC_OBS_MOM, LC_OBS_UMAX, LC_OBS_S, LC_OBS_ALL = 1, 2, 4, 8, 15
 LC_FIELD_F, LC_FIELD_Q, LC_FIELD_RHO, LC_FIELD_U, LC_FIELD_FORCE, LC_FIELD_S = range(6)
 
@@ -74,6 +75,7 @@ def _load():
         "lc_sync": ([ctypes.c_void_p], ctypes.c_int32),
         "lc_vjp_step": ([ctypes.c_void_p] * 6, ctypes.c_int32),
         "lc_vjp_history_bytes": ([P(lc_grid), ctypes.c_int32], ctypes.c_size_t),
+        "lc_set_collision": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32], ctypes.c_int32),
         "lc_vjp_backward_bytes": ([P(lc_grid), ctypes.c_int32], ctypes.c_size_t),
         "lc_vjp_backward": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_void_p), P(ctypes.c_void_p),
                              P(ctypes.c_int32)] + [ctypes.c_void_p] * 4, ctypes.c_int32),
@@ -197,6 +199,12 @@ def lc_vjp_segment(ctx, f_ck_ptr, q_ck_ptr, n, hist_ptr, adj_f_ptr, adj_q_ptr, d
                                ctypes.c_void_p(dparams_ptr)))
 
 
+def lc_set_collision(ctx, kind, rates=()):
+    n = len(rates)
+    arr = (ctypes.c_double * max(n, 1))(*[float(r) for r in rates])
+    _check(_lib.lc_set_collision(ctx, int(kind), arr if n else None, n))
+
+
 def lc_vjp_backward_bytes(grid, n):
     return _lib.lc_vjp_backward_bytes(ctypes.byref(grid), int(n))
 
@@ -282,6 +290,9 @@ class Solver:
 
     def set_variant(self, v):
         lc_set_variant(self.ctx, v)
+
+    def set_collision(self, kind, rates=()):
+        lc_set_collision(self.ctx, kind, rates)
 
     def set_chunk(self, planes):
         lc_set_chunk(self.ctx, planes)

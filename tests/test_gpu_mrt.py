@@ -1,0 +1,174 @@
+"""GPU parity of the MRT collision (lc_set_collision) against the oracle's
+moment-space MRT step.
+
+The library applies MRT as the BGK step plus projections on the
+non-hydrodynamic moments; the oracle transforms to moments, relaxes and
+inverts the moment matrix.  Double precision must agree to 1e-12 in the
+normwise metric of gpu_util.rel_err; the FP32 deviation form must keep S
+within 1e-5 of the double-precision oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_13415_amd import inputs
+from gpu_util import SCALES, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+GHOSTS = {0: (1.19, 1.4, 1.1), 1: (1.19, 1.4, 1.2, 1.4, 1.98)}
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def _lc():
+    require_gpu()
+    from paper_1907_13415_amd import lc
+    return lc
+
+
+def _state(lc, lat, shape, seed):
+    rng = np.random.default_rng(seed)
+    q = 9 if lat == 0 else 19
+    q5 = inputs.random_q5(shape, rng, amp=0.12)
+    rel = inputs.random_rel(q, shape, rng, amp=2e-3)
+    _, w = lc.lc_lattice_info(lat)
+    return q5, rel, w.reshape((q, 1, 1, 1)) * (1.0 + rel)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("lat,shape", [(0, (1, 23, 37)), (0, (1, 70, 130)), (1, (9, 11, 13)), (1, (17, 6, 67))])
+def test_mrt_parity_random_state_ragged(variant, lat, shape):
+    lc = _lc()
+    _say("mrt parity lat %d shape %s variant %d" % (lat, shape, variant))
+    q5, rel, f_gpu = _state(lc, lat, shape, 300 + lat)
+    p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
+    s = lc.Solver("D2Q9" if lat == 0 else "D3Q19", "fp64", shape, p)
+    s.set_variant(variant)
+    s.set_collision(lc.LC_COLL_MRT, GHOSTS[lat])
+    s.load(q5, f_gpu)
+    s.step(12)
+    f_ref, q_ref = oracle.run(lat, oracle.rest_populations(lat, shape, rel=rel), q5, p, 12,
+                              rates=oracle.mrt_rates(lat, p[5], GHOSTS[lat]))
+    ef = rel_err(s.export(lc.LC_FIELD_F), f_ref, SCALES["f"])
+    eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
+    _say("  err f %.3e  Q %.3e" % (ef, eq))
+    assert ef < TOL64 and eq < TOL64
+
+
+def test_mrt_flat_interface_1000_steps_fp64_and_fp32():
+    """The flat-interface workload (128 x 16, paper parameters) for 1000
+    steps with MRT: FP64 to 1e-12, FP32 deviation form within 1e-5 on S."""
+    lc = _lc()
+    w = inputs.config0()
+    p = inputs.PAPER_PARAMS
+    r = oracle.mrt_rates(0, p[5], GHOSTS[0])
+    f_ref, q_ref = oracle.run(0, oracle.rest_populations(0, w.shape), w.q5, p, 1000, rates=r)
+    S_ref = np.sqrt(1.5 * (q_ref[0] ** 2 + q_ref[3] ** 2 + (q_ref[0] + q_ref[3]) ** 2
+                           + 2 * (q_ref[1] ** 2 + q_ref[2] ** 2 + q_ref[4] ** 2)))
+    for prec in ("fp64", "fp32dev"):
+        s = lc.Solver("D2Q9", prec, w.shape, p)
+        s.set_collision(lc.LC_COLL_MRT, GHOSTS[0])
+        s.load(w.q5)
+        s.step(1000)
+        if prec == "fp64":
+            ef = rel_err(s.export(lc.LC_FIELD_F), f_ref, SCALES["f"])
+            eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
+            _say("mrt flat fp64: err f %.3e  Q %.3e" % (ef, eq))
+            assert ef < TOL64 and eq < TOL64
+        else:
+            err = np.abs(s.export(lc.LC_FIELD_S)[0] - S_ref).max()
+            _say("mrt flat fp32dev: max |dS| %.3e" % err)
+            assert err < 1e-5
+
+
+@pytest.mark.parametrize("lat,shape", [(0, (1, 30, 41)), (1, (10, 12, 14))])
+def test_mrt_with_equal_rates_matches_bgk(lat, shape):
+    lc = _lc()
+    q5, rel, f_gpu = _state(lc, lat, shape, 310 + lat)
+    p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
+    out = []
+    for mrt in (False, True):
+        s = lc.Solver("D2Q9" if lat == 0 else "D3Q19", "fp64", shape, p)
+        if mrt:
+            s.set_collision(lc.LC_COLL_MRT, [1 / p[5]] * len(GHOSTS[lat]))
+        s.load(q5, f_gpu)
+        s.step(20)
+        out.append((s.export(lc.LC_FIELD_F), s.export(lc.LC_FIELD_Q)))
+    ef = rel_err(out[1][0], out[0][0], SCALES["f"])
+    eq = rel_err(out[1][1], out[0][1], SCALES["q"])
+    _say("mrt(1/tau) vs bgk: f %.2e Q %.2e" % (ef, eq))
+    assert ef < 1e-13 and eq < 1e-13
+
+
+def test_mrt_collision_validation():
+    lc = _lc()
+    s = lc.Solver("D3Q19", "fp64", (4, 5, 6), inputs.WORKLOAD_PARAMS)
+    for rates in ((1.1, 1.2, 1.3), (1.0, 1.0, 1.0, 1.0, 2.0), (1.0, 1.0, 1.0, 1.0, 0.0)):
+        with pytest.raises(lc.LCError) as e:
+            s.set_collision(lc.LC_COLL_MRT, rates)
+        assert e.value.code == lc.LC_EINVAL
+    with pytest.raises(lc.LCError):
+        s.set_collision(7)
+    s.set_collision(lc.LC_COLL_MRT, (1.2, 1.2, 1.2, 1.2, 1.2))
+    s.set_collision(lc.LC_COLL_BGK)
+    d = lc.Solver("D2Q9", "fp64", (1, 8, 8), inputs.WORKLOAD_PARAMS)
+    d.set_collision(lc.LC_COLL_MRT, (1.1, 1.2, 1.3))
+    import torch
+    z = torch.zeros(9 * 64, dtype=torch.float64, device="cuda")
+    zq = torch.zeros(5 * 64, dtype=torch.float64, device="cuda")
+    dp = torch.zeros(3, dtype=torch.float64, device="cuda")
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_vjp_step(d.ctx, z.data_ptr(), zq.data_ptr(), z.clone().data_ptr(), zq.clone().data_ptr(), dp.data_ptr())
+    assert e.value.code == lc.LC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32dev", 2e-6), ("fp64", 1e-12)])
+def test_mrt_full_size_slab_256cubed_sampled_sites(prec, tol):
+    """The 256^3 D3Q19 slab in the benchmark's launch configuration with MRT:
+    one GPU step from a developed state against the oracle on periodic
+    patches of radius 6 around sampled sites."""
+    import torch
+    lc = _lc()
+    _say("mrt full-size 256^3 %s" % prec)
+    w = inputs.config2(256)
+    s = lc.Solver("D3Q19", prec, w.shape, w.params)
+    s.set_collision(lc.LC_COLL_MRT, GHOSTS[1])
+    s.load(w.q5)
+    s.step(3)
+
+    def dev(field, n):
+        out = torch.empty((n,) + s.shape, dtype=torch.float64, device=s.device)
+        with torch.cuda.stream(s.stream):
+            lc.lc_export(s.ctx, field, out.data_ptr())
+        s.stream.synchronize()
+        return out
+
+    def patch(t, z, y, x, r):
+        nz, ny, nx = t.shape[1:]
+        iz = torch.tensor([(z + d) % nz for d in range(-r, r + 1)], device=t.device)
+        iy = torch.tensor([(y + d) % ny for d in range(-r, r + 1)], device=t.device)
+        ix = torch.tensor([(x + d) % nx for d in range(-r, r + 1)], device=t.device)
+        return t[:, iz][:, :, iy][:, :, :, ix].cpu().numpy()
+
+    f0, q0 = dev(lc.LC_FIELD_F, 19), dev(lc.LC_FIELD_Q, 5)
+    s.step(1)
+    f1, q1 = dev(lc.LC_FIELD_F, 19), dev(lc.LC_FIELD_Q, 5)
+    rng = np.random.default_rng(43)
+    sites = [(0, 0, 0), (255, 255, 255), (127, 128, 64), (64, 3, 63)]
+    sites += [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(20)]
+    r = 6
+    rates = oracle.mrt_rates(1, w.params[5], GHOSTS[1])
+    worst = 0.0
+    for (z, y, x) in sites:
+        fr, qr = oracle.run(1, patch(f0, z, y, x, r), patch(q0, z, y, x, r), w.params, 1, rates=rates)
+        worst = max(worst, np.abs(f1[:, z, y, x].cpu().numpy() - fr[:, r, r, r]).max() / (1 / 3),
+                    np.abs(q1[:, z, y, x].cpu().numpy() - qr[:, r, r, r]).max() / (1 / 3))
+    _say("  sampled: err %.3e" % worst)
+    assert worst < tol
