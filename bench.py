@@ -115,6 +115,13 @@ def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False):
     return dict(ms=ms_step, kernel_ms=[ms_k[0] / max(n_k[0], 1), ms_k[1] / max(n_k[1], 1)], S=S, obs=obs)
 
 
+def mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site):
+    rm = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream, mrt=True)
+    return {"mlups": round(N / (rm["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(rm["ms"], 5),
+            "kernel_ms": [round(v, 5) for v in rm["kernel_ms"]], "rates": list(MRT_RATES),
+            "roofline_frac": round(bytes_site * N / (sum(rm["kernel_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def run_batch(torch, lc, stream, dev, steps):
     from paper_1907_13415_amd import inputs
     ws = inputs.config3()
@@ -187,7 +194,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
-    ap.add_argument("--only", choices=["batch", "adjoint"],
+    ap.add_argument("--only", choices=["batch", "adjoint", "mrt"],
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -217,17 +224,20 @@ def main():
         return
 
     w = inputs.config2(args.n)
+    N = args.n ** 3
+    bytes_site = alg_bytes_per_site(19, 4)
+    if args.only == "mrt":
+        print(json.dumps({"mrt_fp32": mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)}), flush=True)
+        return
     r32 = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream)
     r64 = run_slab(torch, lc, w, "fp64", args.steps, args.warmup, dev, stream)
     dS = float((r32["S"] - r64["S"]).abs().max().item())
     del r32["S"], r64["S"]
     torch.cuda.empty_cache()
 
-    N = args.n ** 3
     ms32 = r32["ms"]
     mlups32 = N / (ms32 * 1e-3) / 1e6
     mlups64 = N / (r64["ms"] * 1e-3) / 1e6
-    bytes_site = alg_bytes_per_site(19, 4)
     kernel_ms = sum(r32["kernel_ms"])  # the two sweeps of one step
     achieved = bytes_site * N / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic()
@@ -260,12 +270,7 @@ def main():
         "fp32_steps_compared": args.warmup + args.steps,
     }
     if not args.quick:
-        rm = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream, mrt=True)
-        del rm["S"]
-        out["mrt_fp32"] = {"mlups": round(N / (rm["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(rm["ms"], 5),
-                           "kernel_ms": [round(v, 5) for v in rm["kernel_ms"]], "rates": list(MRT_RATES),
-                           "roofline_frac": round(bytes_site * N / (sum(rm["kernel_ms"]) * 1e-3) / 1e9
-                                                  / HBM_PEAK_GBS, 4)}
+        out["mrt_fp32"] = mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)
         out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)
         out["adjoint"] = run_adjoint(torch)
     if not args.no_cpu:
