@@ -19,6 +19,7 @@ timings use HIP events recorded on the stream the library launches on.
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -79,8 +80,15 @@ def cpu_baseline(n=128, min_s=10.0, max_steps=200):
         f, q5 = oracle.run(oracle.D3Q19, f, q5, inputs.WORKLOAD_PARAMS, 1)
         steps += 1
     dt = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=round(n ** 3 * steps / dt / 1e6, 4), unit="MLUPS", cores=threads, kind="oracle",
-                sample="oracle FP64 on the D3Q19 slab recipe at %d^3, %d steps in %.1f s" % (n, steps, dt))
+                sample="oracle FP64 on the D3Q19 slab recipe at %d^3, %d steps in %.1f s" % (n, steps, dt),
+                cpu_model=model, nproc=os.cpu_count())
 
 
 # ghost-group rates of the MRT leg (s_e, s_eps, s_q, s_pi, s_m); the paper's
@@ -122,6 +130,72 @@ def mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site):
             "roofline_frac": round(bytes_site * N / (sum(rm["kernel_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def s_nematic(g):
+    """Nematic minimum of the uniaxial bulk free energy (Eq. 3), for
+    converting sums of S into lengths and areas (0 below gamma = 8/3)."""
+    return 0.25 + 0.75 * math.sqrt(1.0 - 8.0 / (3.0 * g)) if g >= 8.0 / 3.0 else 0.0
+
+
+def run_droplets(torch, lc, dev, stream, steps=20000):
+    """256^2 droplet at gamma = 2.7, 2.705, 2.71 for 20000 steps in FP64 and
+    FP32: max |u|, radius drift and the FP32 errors."""
+    from paper_1907_13415_amd import inputs
+    recs = []
+    for dg in (0.0, 0.005, 0.01):
+        w = inputs.config1(dg)
+        g = w.params[1]
+        sn = s_nematic(g)
+        res = {}
+        for prec in ("fp64", "fp32dev"):
+            with torch.cuda.stream(stream):
+                s = lc.Solver("D2Q9", prec, w.shape, w.params, device=dev, stream=stream)
+                s.load(w.q5)
+                r0 = math.sqrt(s.observe()["ssum"] / (math.pi * sn))
+                t0 = time.perf_counter()
+                s.step(steps)
+                o = s.observe()
+                dt = time.perf_counter() - t0
+                res[prec] = dict(umax=o["umax"], r0=r0, r1=math.sqrt(o["ssum"] / (math.pi * sn)),
+                                 S=s.export(lc.LC_FIELD_S), mlups=w.shape[1] * w.shape[2] * steps / dt / 1e6)
+                del s
+        a, b = res["fp64"], res["fp32dev"]
+        recs.append({"gamma": round(g, 4), "umax": a["umax"], "radius": [round(a["r0"], 4), round(a["r1"], 4)],
+                     "radius_drift_per_step": (a["r1"] - a["r0"]) / steps,
+                     "fp32_max_abs_dS": float(abs(a["S"] - b["S"]).max()),
+                     "fp32_umax_rel_err": abs(b["umax"] - a["umax"]) / a["umax"],
+                     "fp32_radius_err": abs(b["r1"] - a["r1"]),
+                     "mlups_fp64": round(a["mlups"], 1), "mlups_fp32": round(b["mlups"], 1)})
+    return dict(workload="droplet256_d2q9", steps=steps, runs=recs)
+
+
+def batch_velocities(b, ws, t0=1000, t1=5000):
+    """Per-grid interface velocity of the sweep (the right interface of each
+    slab, from the half-domain sum of S) between steps t0 and t1, and the
+    grids that melt (gamma < 8/3, or all isotropic by t1) or fill instead."""
+    for k, w in enumerate(ws):
+        b.load(k, w.q5)
+    b.step(t0)
+    o0 = b.observe(half_axis=0)
+    b.step(t1 - t0)
+    o1 = b.observe(half_axis=0)
+    vel, melted, filled = [], 0, 0
+    for w, a, c in zip(ws, o0, o1):
+        L = w.shape[2]
+        g = w.params[1]
+        sn = s_nematic(g)
+        if sn == 0.0 or c["ssum"] < 1e-6 * L * L:  # below 8/3 the nematic is unstable
+            melted += 1
+            vel.append(None)
+        elif sn > 0 and c["ssum"] > 0.99 * sn * L * L:
+            filled += 1
+            vel.append(None)
+        else:
+            vel.append(round((c["ssum_half"] - a["ssum_half"]) / (sn * L) / (t1 - t0), 8))
+    return dict(steps=[t0, t1], melted=melted, filled=filled,
+                velocity_per_grid=[{"gamma": round(w.params[1], 5), "L": w.shape[2], "v": v}
+                                   for w, v in zip(ws, vel)])
+
+
 def run_batch(torch, lc, stream, dev, steps):
     from paper_1907_13415_amd import inputs
     ws = inputs.config3()
@@ -143,11 +217,12 @@ def run_batch(torch, lc, stream, dev, steps):
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1) / steps
         obs = b.observe()
+        physics = batch_velocities(b, ws)
     sites = sum(w.shape[1] * w.shape[2] for w in ws)
     return dict(grids=len(ws), sites=sites, tile=["32x8", "64x4", "16x16"][tile], ms_per_step=round(ms, 5),
                 mlups=round(sites / (ms * 1e-3) / 1e6, 2),
                 roofline_frac=round(alg_bytes_per_site(9, 4) * sites / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                nonfinite=int(sum(o["nonfinite"] for o in obs)))
+                nonfinite=int(sum(o["nonfinite"] for o in obs)), sweep=physics)
 
 
 def run_adjoint(torch):
@@ -272,6 +347,7 @@ def main():
     if not args.quick:
         out["mrt_fp32"] = mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)
         out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)
+        out["droplets"] = run_droplets(torch, lc, dev, stream)
         out["adjoint"] = run_adjoint(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
