@@ -520,7 +520,7 @@ struct SplitCfg {
   static constexpr int LB_TX = (d3 && !f64) ? 64 : 32, LB_TY = (d3 && !f64) ? 4 : 8;
   static constexpr int Q_TX = (d3 && f64) ? 16 : 32, Q_TY = 8;
   // planes per block along z in each sweep
-  static constexpr int ZC_LB = f64 ? 16 : 128, ZC_Q = 128;
+  static constexpr int ZC_LB = f64 ? 16 : 32, ZC_Q = 128;
   // waves per SIMD the register allocation is held to (LDS allows 3 blocks
   // of the single-precision 3D stress sweep per CU)
   static constexpr int LB_WPE = (d3 && !f64) ? 3 : 1;
