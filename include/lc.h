@@ -69,8 +69,11 @@ typedef int32_t lc_status;
 #define LC_VARIANT_AUTO 0
 #define LC_VARIANT_STAGED 1 /* one kernel per stage, intermediates in scratch */
 #define LC_VARIANT_SPLIT 2  /* two sweeps: LB update + velocity, then Q update */
-#define LC_VARIANT_FUSED 3  /* single sweep with LDS halo tiles */
+#define LC_VARIANT_FUSED 3  /* reserved (single sweep); returns LC_EUNSUPPORTED */
 
+/* A periodic grid of nx * ny * nz sites (nz == 1 for D2Q9).  Every
+ * dimension >= 1, ny and nz <= 65535, at most 4e9 sites; any other grid is
+ * rejected with LC_EINVAL. */
 typedef struct {
   int32_t lattice;   /* LC_D2Q9 or LC_D3Q19 */
   int32_t precision; /* LC_FP64 or LC_FP32_DEV */

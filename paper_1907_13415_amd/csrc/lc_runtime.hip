@@ -47,8 +47,11 @@ lc_status check_grid(const lc_grid* g) {
     return fail(LC_EINVAL, "unknown precision %d", g->precision);
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(LC_EINVAL, "grid dimensions must be >= 1");
   if (g->lattice == LC_D2Q9 && g->nz != 1) return fail(LC_EINVAL, "D2Q9 requires nz == 1");
+  // site indices are 32-bit unsigned inside the sweeps; ny and nz index
+  // launch grid dimensions, which are limited to 65535 blocks
   const double n = double(g->nx) * g->ny * g->nz;
   if (n > 4.0e9) return fail(LC_EINVAL, "grid too large (%.3g sites)", n);
+  if (g->ny > 65535 || g->nz > 65535) return fail(LC_EINVAL, "ny and nz must not exceed 65535");
   return LC_OK;
 }
 

@@ -101,11 +101,11 @@ template <typename S, int TX, int TY, int NC>
 __device__ __forceinline__ void load_region(S* dst, const S* const* src, int x0, int y0, int gz,
                                             const GridDims& g, int tid) {
   constexpr int W2 = TX + 4, R2 = (TX + 4) * (TY + 4), NT = TX * TY;
-  const int plane = g.nx * g.ny * gz;
+  const uint32_t plane = uint32_t(g.nx) * uint32_t(g.ny) * uint32_t(gz);
   for (int k = tid; k < R2; k += NT) {
     const int i = k % W2, j = k / W2;
     const int gx = wrapi(x0 - 2 + i, g.nx), gy = wrapi(y0 - 2 + j, g.ny);
-    const int s = plane + gx + g.nx * gy;
+    const uint32_t s = plane + uint32_t(gx) + uint32_t(g.nx) * uint32_t(gy);
 #pragma unroll
     for (int q = 0; q < NC; q++) dst[q * R2 + k] = src[q][s];
   }

@@ -63,7 +63,8 @@ def test_init_rejects_bad_params(bad):
 
 
 @pytest.mark.parametrize("grid", [(0, 0, 16, 16, 2), (0, 0, 0, 16, 1), (2, 0, 16, 16, 1), (0, 3, 16, 16, 1),
-                                  (1, 1, 8, -1, 8)])
+                                  (1, 1, 8, -1, 8), (1, 1, 8, 65536, 8), (1, 1, 8, 8, 65536),
+                                  (1, 1, 2000, 2000, 1001)])
 def test_init_rejects_bad_grid(grid):
     from paper_1907_13415_amd import lc
     params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
