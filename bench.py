@@ -219,7 +219,9 @@ def run_batch(torch, lc, stream, dev, steps):
         obs = b.observe()
         physics = batch_velocities(b, ws)
     sites = sum(w.shape[1] * w.shape[2] for w in ws)
-    return dict(grids=len(ws), sites=sites, tile=["32x8", "64x4", "16x16"][tile], ms_per_step=round(ms, 5),
+    shapes_ = ["32x8", "64x4", "16x16", "32x16", "64x8", "64x16", "128x8"]
+    return dict(grids=len(ws), sites=sites, tiles={"lb": shapes_[tile % 7], "q": shapes_[tile // 7]},
+                ms_per_step=round(ms, 5),
                 mlups=round(sites / (ms * 1e-3) / 1e6, 2),
                 roofline_frac=round(alg_bytes_per_site(9, 4) * sites / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 nonfinite=int(sum(o["nonfinite"] for o in obs)), sweep=physics)

@@ -311,14 +311,19 @@ lc_status lc_batch_load_state(lc_batch *b, int32_t k, const double *f_dev, const
  * whole runs of 64 steps, direct launches for the rest). */
 lc_status lc_batch_step(lc_batch *b, int64_t n);
 
-/* Select the tile shape (0: 32x8, 1: 64x4, 2: 16x16 sites per block).
- * Results do not depend on the tile shape. */
+/* Select the tile shape of each sweep: v_lb for the stress / LB sweep, v_q
+ * for the Q sweep (0: 32x8, 1: 64x4, 2: 16x16, 3: 32x16, 4: 64x8, 5: 64x16,
+ * 6: 128x8 sites per block).  Results do not depend on the tile shapes.
+ * LC_EINVAL outside 0..6. */
+lc_status lc_batch_set_tiles(lc_batch *b, int32_t v_lb, int32_t v_q);
+
+/* lc_batch_set_tiles(b, variant, variant). */
 lc_status lc_batch_set_tile(lc_batch *b, int32_t variant);
 
-/* Time every tile shape for trial_steps steps (after one untimed step) with
- * HIP events and keep the fastest.  The state advances by
- * 3 * (trial_steps + 1) steps: tune before loading the real state, or load
- * it again afterwards.  Synchronises the stream. */
+/* Time every pair of tile shapes for trial_steps steps (after one untimed
+ * step) with HIP events and keep the fastest; *chosen = v_lb + 7 * v_q.
+ * The state advances by 49 * (trial_steps + 1) steps: tune before loading
+ * the real state, or load it again afterwards.  Synchronises the stream. */
 lc_status lc_batch_autotune(lc_batch *b, int32_t trial_steps, int32_t *chosen, double *ms_per_step);
 
 /* Observables of every grid: out has ngrids entries.  Synchronises. */

@@ -18,7 +18,7 @@ struct BatchDesc {
   int nx, ny;
   int64_t N;
   int64_t f_off, q_off, u_off;  // element offsets into the arenas
-  int tile0, tiles_x;           // first block of this grid, tiles along x
+  int tile0[2], tiles_x[2];     // per sweep (0: LB, 1: Q): first block of this grid, tiles along x
   Coef<S> c;
 };
 
@@ -29,10 +29,10 @@ __global__ void __launch_bounds__(TX* TY)
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int k = tile_grid[b];
   const BatchDesc<S> d = desc[k];
-  const int t = b - d.tile0;
+  const int t = b - d.tile0[0];
   const GridDims g{d.nx, d.ny, 1, d.N};
   split_lb_body<LAT, S, DEV, TX, TY>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g, d.c, 1,
-                                     t % d.tiles_x, t / d.tiles_x, 0);
+                                     t % d.tiles_x[0], t / d.tiles_x[0], 0);
 }
 
 template <int LAT, typename S, int TX, int TY>
@@ -42,15 +42,21 @@ __global__ void __launch_bounds__(TX* TY)
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int k = tile_grid[b];
   const BatchDesc<S> d = desc[k];
-  const int t = b - d.tile0;
+  const int t = b - d.tile0[1];
   const GridDims g{d.nx, d.ny, 1, d.N};
-  split_q_body<LAT, S, TX, TY>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.c, 1, t % d.tiles_x,
-                               t / d.tiles_x, 0);
+  split_q_body<LAT, S, TX, TY>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.c, 1, t % d.tiles_x[1],
+                               t / d.tiles_x[1], 0);
 }
 
-// Tile shapes the batch can run with (chosen by lc_batch_autotune).
-constexpr int BATCH_NV = 3;
-__host__ __device__ constexpr int batch_tx(int v) { return v == 0 ? 32 : (v == 1 ? 64 : 16); }
-__host__ __device__ constexpr int batch_ty(int v) { return v == 0 ? 8 : (v == 1 ? 4 : 16); }
+// Tile shapes the batch can run with, chosen per sweep by lc_batch_autotune
+// (the stress sweep favours wide tiles, which share HBM lines; the Q sweep
+// tiles with the smaller ring).
+constexpr int BATCH_NV = 7;  // 32x8, 64x4, 16x16, 32x16, 64x8, 64x16, 128x8
+__host__ __device__ constexpr int batch_tx(int v) {
+  return v == 0 || v == 3 ? 32 : (v == 1 || v == 4 || v == 5 ? 64 : (v == 2 ? 16 : 128));
+}
+__host__ __device__ constexpr int batch_ty(int v) {
+  return v == 0 || v == 4 || v == 6 ? 8 : (v == 1 ? 4 : 16);
+}
 
 }  // namespace lc

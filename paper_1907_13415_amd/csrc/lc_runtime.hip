@@ -821,9 +821,9 @@ namespace lc {
 struct BatchLayout {
   std::vector<size_t> f_off, q_off, u_off;  // byte offsets into the arenas / scratch u region
   size_t f_bytes = 0, q_bytes = 0;
-  size_t off_desc = 0, off_map[BATCH_NV] = {0, 0, 0}, off_u = 0, off_view = 0, off_res = 0;
+  size_t off_desc = 0, off_map[BATCH_NV] = {}, off_u = 0, off_view = 0, off_res = 0;
   size_t scratch_bytes = 0;
-  int tiles[BATCH_NV] = {0, 0, 0};
+  int tiles[BATCH_NV] = {};
   std::vector<int> tile0[BATCH_NV], tiles_x[BATCH_NV];
 };
 
@@ -895,7 +895,7 @@ struct lc_batch {
   std::vector<lc_ctx> views;  // single-grid contexts over the arenas
   std::vector<char> host_desc;
   std::vector<int> host_map[BATCH_NV];
-  int variant;
+  int vt[2];  // tile shape of each sweep (0: LB, 1: Q)
   int parity;
   int64_t step;
   bool loaded;
@@ -918,8 +918,10 @@ static void batch_fill_desc(lc_batch* b) {
     d[k].f_off = int64_t(b->B.f_off[k] / es);
     d[k].q_off = int64_t(b->B.q_off[k] / es);
     d[k].u_off = int64_t(b->B.u_off[k] / es);
-    d[k].tile0 = b->B.tile0[b->variant][k];
-    d[k].tiles_x = b->B.tiles_x[b->variant][k];
+    for (int w = 0; w < 2; w++) {
+      d[k].tile0[w] = b->B.tile0[b->vt[w]][k];
+      d[k].tiles_x[w] = b->B.tiles_x[b->vt[w]][k];
+    }
     d[k].c = make_coef<S>(b->params[k]);
   }
 }
@@ -938,7 +940,7 @@ static lc_status batch_upload(lc_batch* b) {
 }
 
 template <typename S, bool DEV, int V>
-static void batch_launch_v(lc_batch* b, hipStream_t st, int parity) {
+static void batch_launch_lb(lc_batch* b, hipStream_t st, int parity) {
   constexpr int TX = batch_tx(V), TY = batch_ty(V);
   char* scr = static_cast<char*>(b->arena.scratch);
   const BatchDesc<S>* desc = reinterpret_cast<const BatchDesc<S>*>(scr + b->B.off_desc);
@@ -947,20 +949,44 @@ static void batch_launch_v(lc_batch* b, hipStream_t st, int parity) {
   const S* f0 = static_cast<const S*>(b->arena.f[parity]);
   S* f1 = static_cast<S*>(b->arena.f[parity ^ 1]);
   const S* q0 = static_cast<const S*>(b->arena.Q[parity]);
+  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map,
+                     q0, f0, f1, u);
+}
+
+template <typename S, int V>
+static void batch_launch_q(lc_batch* b, hipStream_t st, int parity) {
+  constexpr int TX = batch_tx(V), TY = batch_ty(V);
+  char* scr = static_cast<char*>(b->arena.scratch);
+  const BatchDesc<S>* desc = reinterpret_cast<const BatchDesc<S>*>(scr + b->B.off_desc);
+  const int* map = reinterpret_cast<const int*>(scr + b->B.off_map[V]);
+  const S* u = reinterpret_cast<const S*>(scr + b->B.off_u);
+  const S* q0 = static_cast<const S*>(b->arena.Q[parity]);
   S* q1 = static_cast<S*>(b->arena.Q[parity ^ 1]);
-  const unsigned nt = unsigned(b->B.tiles[V]);
-  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY>), dim3(nt), dim3(TX, TY), 0, st, desc, map, q0, f0, f1, u);
-  hipLaunchKernelGGL((batch_q<0, S, TX, TY>), dim3(nt), dim3(TX, TY), 0, st, desc, map, q0, u, q1);
+  hipLaunchKernelGGL((batch_q<0, S, TX, TY>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map, q0, u,
+                     q1);
 }
 
 template <typename S, bool DEV>
 static void batch_launch(lc_batch* b, hipStream_t st, int parity) {
-  if (b->variant == 0)
-    batch_launch_v<S, DEV, 0>(b, st, parity);
-  else if (b->variant == 1)
-    batch_launch_v<S, DEV, 1>(b, st, parity);
-  else
-    batch_launch_v<S, DEV, 2>(b, st, parity);
+  static_assert(BATCH_NV == 7, "one launch branch per tile shape");
+  switch (b->vt[0]) {
+    case 0: batch_launch_lb<S, DEV, 0>(b, st, parity); break;
+    case 1: batch_launch_lb<S, DEV, 1>(b, st, parity); break;
+    case 2: batch_launch_lb<S, DEV, 2>(b, st, parity); break;
+    case 3: batch_launch_lb<S, DEV, 3>(b, st, parity); break;
+    case 4: batch_launch_lb<S, DEV, 4>(b, st, parity); break;
+    case 5: batch_launch_lb<S, DEV, 5>(b, st, parity); break;
+    default: batch_launch_lb<S, DEV, 6>(b, st, parity); break;
+  }
+  switch (b->vt[1]) {
+    case 0: batch_launch_q<S, 0>(b, st, parity); break;
+    case 1: batch_launch_q<S, 1>(b, st, parity); break;
+    case 2: batch_launch_q<S, 2>(b, st, parity); break;
+    case 3: batch_launch_q<S, 3>(b, st, parity); break;
+    case 4: batch_launch_q<S, 4>(b, st, parity); break;
+    case 5: batch_launch_q<S, 5>(b, st, parity); break;
+    default: batch_launch_q<S, 6>(b, st, parity); break;
+  }
 }
 
 static void batch_launch_step(lc_batch* b, hipStream_t st, int parity) {
@@ -1055,7 +1081,7 @@ lc_status lc_batch_init(int32_t ngrids, const lc_grid* grids, const lc_params* p
   b->arena = *arena;
   b->stream = static_cast<hipStream_t>(stream);
   b->B = B;
-  b->variant = 0;
+  b->vt[0] = b->vt[1] = 0;
   b->parity = 0;
   b->step = 0;
   b->loaded = false;
@@ -1171,17 +1197,20 @@ lc_status lc_batch_step(lc_batch* b, int64_t n) {
   return hip_check(hipGetLastError(), "batch step launch");
 }
 
-lc_status lc_batch_set_tile(lc_batch* b, int32_t variant) {
+lc_status lc_batch_set_tiles(lc_batch* b, int32_t v_lb, int32_t v_q) {
   clear_error();
   if (!b) return fail(LC_EINVAL, "batch is NULL");
-  if (variant < 0 || variant >= BATCH_NV) return fail(LC_EINVAL, "tile variant out of range");
-  if (variant == b->variant) return LC_OK;
-  b->variant = variant;
+  if (v_lb < 0 || v_lb >= BATCH_NV || v_q < 0 || v_q >= BATCH_NV) return fail(LC_EINVAL, "tile variant out of range");
+  if (v_lb == b->vt[0] && v_q == b->vt[1]) return LC_OK;
+  b->vt[0] = v_lb;
+  b->vt[1] = v_q;
   batch_drop_graphs(b);
   lc_status st = batch_upload(b);
   if (st) return st;
   return hip_check(hipStreamSynchronize(b->stream), "descriptor upload sync");
 }
+
+lc_status lc_batch_set_tile(lc_batch* b, int32_t variant) { return lc_batch_set_tiles(b, variant, variant); }
 
 lc_status lc_batch_autotune(lc_batch* b, int32_t trial_steps, int32_t* chosen, double* ms_per_step) {
   clear_error();
@@ -1196,10 +1225,11 @@ lc_status lc_batch_autotune(lc_batch* b, int32_t trial_steps, int32_t* chosen, d
     (void)hipEventDestroy(e0);
     return st;
   }
+  // every pair of tile shapes (stress sweep, Q sweep)
   int best = 0;
   float best_ms = 1e30f;
-  for (int v = 0; v < BATCH_NV && st == LC_OK; v++) {
-    st = lc_batch_set_tile(b, v);
+  for (int v = 0; v < BATCH_NV * BATCH_NV && st == LC_OK; v++) {
+    st = lc_batch_set_tiles(b, v % BATCH_NV, v / BATCH_NV);
     if (st) break;
     // one untimed step, then the timed trial
     st = lc_batch_step(b, 1);
@@ -1222,7 +1252,7 @@ lc_status lc_batch_autotune(lc_batch* b, int32_t trial_steps, int32_t* chosen, d
   if (st) return st;
   if (chosen) *chosen = best;
   if (ms_per_step) *ms_per_step = double(best_ms) / trial_steps;
-  return lc_batch_set_tile(b, best);
+  return lc_batch_set_tiles(b, best % BATCH_NV, best / BATCH_NV);
 }
 
 lc_status lc_batch_observe(lc_batch* b, uint32_t mask, int32_t half_axis, lc_observables* out) {

@@ -92,6 +92,7 @@ def _load():
         "lc_batch_load_state": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
         "lc_batch_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
         "lc_batch_set_tile": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+        "lc_batch_set_tiles": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
         "lc_batch_autotune": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)],
                               ctypes.c_int32),
         "lc_batch_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
@@ -363,6 +364,10 @@ def lc_batch_set_tile(b, v):
     _check(_lib.lc_batch_set_tile(b, int(v)))
 
 
+def lc_batch_set_tiles(b, v_lb, v_q):
+    _check(_lib.lc_batch_set_tiles(b, int(v_lb), int(v_q)))
+
+
 def lc_batch_autotune(b, trial_steps):
     ch = ctypes.c_int32()
     ms = ctypes.c_double()
@@ -432,6 +437,9 @@ class BatchSolver:
 
     def set_tile(self, v):
         lc_batch_set_tile(self.b, v)
+
+    def set_tiles(self, v_lb, v_q):
+        lc_batch_set_tiles(self.b, v_lb, v_q)
 
     def autotune(self, trial_steps=20):
         return lc_batch_autotune(self.b, trial_steps)

@@ -70,11 +70,10 @@ def test_batch_equals_single_grid_across_graph_replays(prec):
             assert obs[k]["step"] == done
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6])
 def test_batch_every_tile_shape_matches_oracle_fp64(tile):
-    """Each tile shape (32x8, 64x4, 16x16) agrees with the double-precision
-    oracle; shapes differ from each other only by rounding (the compiler
-    contracts multiply-adds per instantiation)."""
+    """Each tile shape (32x8, 64x4, 16x16, 32x16, 64x8, 64x16, 128x8) agrees
+    with the double-precision oracle."""
     lc = _lc()
     q5s, params = _batch_inputs(2)
     b = lc.BatchSolver("fp64", SHAPES, params)
@@ -99,9 +98,9 @@ def test_batch_autotune_keeps_results():
     for k, q5 in enumerate(q5s):
         b.load(k, q5)
     chosen, ms = b.autotune(5)
-    _say("autotune chose tile %d (%.3f ms/step)" % (chosen, ms))
-    assert chosen in (0, 1, 2) and ms > 0
-    ref.set_tile(chosen)
+    _say("autotune chose tiles %d, %d (%.3f ms/step)" % (chosen % 7, chosen // 7, ms))
+    assert 0 <= chosen < 49 and ms > 0
+    ref.set_tiles(chosen % 7, chosen // 7)
     for k, q5 in enumerate(q5s):
         b.load(k, q5)
         ref.load(k, q5)
@@ -148,18 +147,20 @@ def test_temperature_sweep_workload_full_size():
 
 
 def test_batch_tile_shapes_agree_bitwise():
-    """Every site runs the same code wherever it falls in a tile, so the three
-    tile shapes give identical results."""
+    """Every site runs the same code wherever it falls in a tile, so every
+    tile shape of either sweep gives identical results (seven pairings that
+    use each shape once in each sweep)."""
     lc = _lc()
     q5s, params = _batch_inputs(4)
     res = []
-    for v in range(3):
+    for v in range(7):
         b = lc.BatchSolver("fp32dev", SHAPES, params)
-        b.set_tile(v)
+        b.set_tiles(v, (3 * v + 1) % 7)
         for k, q5 in enumerate(q5s):
             b.load(k, q5)
         b.step(70)
-        res.append([b.export(k, lc.LC_FIELD_Q) for k in range(len(SHAPES))])
-    for v in (1, 2):
+        res.append([(b.export(k, lc.LC_FIELD_Q), b.export(k, lc.LC_FIELD_F)) for k in range(len(SHAPES))])
+    for v in range(1, 7):
         for k in range(len(SHAPES)):
-            assert np.array_equal(res[0][k], res[v][k]), (v, k)
+            assert np.array_equal(res[0][k][0], res[v][k][0]), (v, k)
+            assert np.array_equal(res[0][k][1], res[v][k][1]), (v, k)
