@@ -723,12 +723,21 @@ lc_status lc_vjp_backward(lc_ctx* c, int32_t nseg, const double* const* f_cks, c
     nmax = ns[k] > nmax ? ns[k] : nmax;
   }
   if (!c->aux) {
-    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
-      c->aux = nullptr;
-      return fail(LC_EDEVICE, "cannot create the replay stream");
+    // events first, then the stream: the context keeps them only once all
+    // exist, so a failed call leaves nothing half made
+    hipEvent_t ev[5] = {};
+    hipStream_t aux = nullptr;
+    bool ok = true;
+    for (hipEvent_t& e : ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+      for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+      if (aux) (void)hipStreamDestroy(aux);
+      return fail(LC_EDEVICE, "cannot create the replay stream and its events");
     }
-    for (hipEvent_t& e : c->vev)
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(LC_EDEVICE, "event create");
+    for (int i = 0; i < 5; i++) c->vev[i] = ev[i];
+    c->aux = aux;
   }
   const size_t half = up256(lc_vjp_history_bytes(&c->g, nmax));
   const VjpHist H[2] = {{static_cast<double*>(hist), c->L.N},

@@ -276,6 +276,10 @@ class Solver:
                                (ctypes.c_void_p * 2)(self._Q[0].data_ptr(), self._Q[1].data_ptr()),
                                self._scratch.data_ptr())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the library works on self.stream: keep torch from reusing these
+        # blocks before that stream's work on them is done
+        for t in self._f + self._Q + [self._scratch]:
+            t.record_stream(self.stream)
         self.ctx = lc_init(self.grid, self.params, self.bufs, self.stream.cuda_stream)
         if variant != LC_VARIANT_AUTO:
             lc_set_variant(self.ctx, variant)
@@ -413,6 +417,8 @@ class BatchSolver:
                                 (ctypes.c_void_p * 2)(self._Q[0].data_ptr(), self._Q[1].data_ptr()),
                                 self._scratch.data_ptr())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        for t in self._f + self._Q + [self._scratch]:
+            t.record_stream(self.stream)
         self.b = lc_batch_init(self.grids, self.params, self.arena, self.stream.cuda_stream)
 
     def __del__(self):
