@@ -183,12 +183,12 @@ def test_fp32_errors_on_interface_and_spurious_velocity():
     """The FP32 deviation form against double precision (which matches the
     oracle to 1e-12) on the observables of Sec. 2: S(x) and the front speed
     of the flat interface at gamma = 2.701, and the spurious currents of the
-    circle near its static temperature.  These runs are long and slow: a
-    step changes Q near the front by ~3e-6, about 100 FP32 ulps of Q, so
-    rounding of Q itself biases the front by ~1% over 3e5 steps.  The 1e-5
-    bound on S holds for the short workloads (the 1000-step flat interface,
-    the 256^3 slab); here the measured errors are bounded at about twice
-    their observed size."""
+    circle near its static temperature.  These runs are long and slow: the
+    rates near a slow front are small differences of much larger float
+    terms (molecular field, Laplacian), and their rounding biases the front
+    by ~1% over 3e5 steps.  The 1e-5 bound on S holds for the short
+    workloads (the 1000-step flat interface, the 256^3 slab); here the
+    measured errors are bounded at about twice their observed size."""
     require_gpu()
     from paper_1907_13415_amd import lc
     nx, ny, g = 256, 4, 2.701
