@@ -196,7 +196,7 @@ def batch_velocities(b, ws, t0=1000, t1=5000):
                                    for w, v in zip(ws, vel)])
 
 
-def run_batch(torch, lc, stream, dev, steps):
+def run_batch(torch, lc, stream, dev, steps, tiles=None, physics=True):
     from paper_1907_13415_amd import inputs
     ws = inputs.config3()
     shapes = [w.shape[1:] for w in ws]
@@ -204,7 +204,11 @@ def run_batch(torch, lc, stream, dev, steps):
         b = lc.BatchSolver("fp32dev", shapes, [w.params for w in ws], device=dev, stream=stream)
         for k, w in enumerate(ws):
             b.load(k, w.q5)
-        tile, _ = b.autotune(10)
+        if tiles is None:
+            tile, _ = b.autotune(10)
+        else:
+            b.set_tiles(*tiles)
+            tile = tiles[0] + 7 * tiles[1]
         for k, w in enumerate(ws):
             b.load(k, w.q5)
         b.step(64)
@@ -217,14 +221,14 @@ def run_batch(torch, lc, stream, dev, steps):
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1) / steps
         obs = b.observe()
-        physics = batch_velocities(b, ws)
+        sweep = batch_velocities(b, ws) if physics else None
     sites = sum(w.shape[1] * w.shape[2] for w in ws)
     shapes_ = ["32x8", "64x4", "16x16", "32x16", "64x8", "64x16", "128x8"]
     return dict(grids=len(ws), sites=sites, tiles={"lb": shapes_[tile % 7], "q": shapes_[tile // 7]},
                 ms_per_step=round(ms, 5),
                 mlups=round(sites / (ms * 1e-3) / 1e6, 2),
                 roofline_frac=round(alg_bytes_per_site(9, 4) * sites / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                nonfinite=int(sum(o["nonfinite"] for o in obs)), sweep=physics)
+                nonfinite=int(sum(o["nonfinite"] for o in obs)), sweep=sweep)
 
 
 def run_adjoint(torch):
@@ -271,6 +275,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--batch-tiles", help="LB,Q tile shapes of the batched leg instead of tuning (0..6)")
+    ap.add_argument("--no-physics", action="store_true",
+                    help="with --only batch: skip the 5000-step front-speed window (for counter runs)")
     ap.add_argument("--only", choices=["batch", "adjoint", "mrt"],
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
@@ -294,7 +301,9 @@ def main():
         return
 
     if args.only == "batch":
-        print(json.dumps({"batch_sweep": run_batch(torch, lc, stream, dev, args.steps)}), flush=True)
+        tiles = tuple(int(v) for v in args.batch_tiles.split(",")) if args.batch_tiles else None
+        print(json.dumps({"batch_sweep": run_batch(torch, lc, stream, dev, args.steps, tiles,
+                                                   physics=not args.no_physics)}), flush=True)
         return
     if args.only == "adjoint":
         print(json.dumps({"adjoint": run_adjoint(torch)}), flush=True)
