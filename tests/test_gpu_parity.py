@@ -75,6 +75,34 @@ def test_parity_flat_interface_128x16_fp64(variant):
         _compare_state(lc, s, f_ref, q_ref, TOL64, "flat step %d" % target)
 
 
+_SLAB_REF = {}
+
+
+def _slab_reference(n, steps):
+    """Oracle run of the D3Q19 slab recipe at n^3 (cached per size and step)."""
+    key = (n, steps)
+    if key not in _SLAB_REF:
+        w = inputs.config2(n)
+        _SLAB_REF[key] = oracle.run(oracle.D3Q19, oracle.rest_populations(oracle.D3Q19, w.shape), w.q5, w.params,
+                                    steps)
+    return _SLAB_REF[key]
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_parity_slab_32cubed_d3q19_1000_steps(variant):
+    """The slab recipe on a 32^3 D3Q19 grid in double precision for 1000
+    steps (several z-chunks and tiles, periodic wrap in every direction)."""
+    lc = _lc()
+    w = inputs.config2(32)
+    _announce("parity slab 32^3 d3q19 1000 steps variant %d" % variant)
+    s = _solver(lc, 1, "fp64", w.shape, w.params, variant)
+    s.set_chunk(8)  # four z-chunks, so chunk boundaries are crossed
+    s.load(w.q5)
+    s.step(1000)
+    f_ref, q_ref = _slab_reference(32, 1000)
+    _compare_state(lc, s, f_ref, q_ref, TOL64, "slab 32^3 step 1000")
+
+
 @pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("lat,shape", [(0, (1, 23, 37)), (0, (1, 70, 130)), (1, (9, 11, 13)), (1, (17, 6, 67))])
 def test_parity_random_state_ragged(variant, lat, shape):
