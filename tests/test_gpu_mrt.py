@@ -90,12 +90,13 @@ def test_mrt_flat_interface_1000_steps_fp64_and_fp32():
 
 def test_mrt_slab_32cubed_d3q19_1000_steps():
     """The slab recipe on a 32^3 D3Q19 grid with MRT in double precision
-    against the oracle's moment-space MRT at 500 and 1000 steps.  With these
-    ghost rates the rounding differences of the two formulations grow by
-    e every ~170 steps (7.5e-15 at step 100, 2.4e-13 at 500, 1.5e-12 at
-    1000; the same with s_m = 1.5 instead of 1.98, and absent with BGK),
-    a sensitivity of the MRT trajectory, not a disagreement of the step:
-    1e-12 is required at step 500 and 1e-11 at step 1000."""
+    against the oracle's moment-space MRT at 500 and 1000 steps.  The two
+    formulations (projections on the ghost moments here, a generic inverse
+    of the moment matrix in the oracle) round differently, and on this
+    trajectory the difference grows with time, roughly as t^2.3 (7.5e-15
+    at step 100, 2.4e-13 at 500, 1.5e-12 at 1000; the same with s_m = 1.5
+    instead of 1.98; BGK stays at 5e-15): 1e-12 is required at step 500
+    and 1e-11 at step 1000."""
     lc = _lc()
     w = inputs.config2(32)
     s = lc.Solver("D3Q19", "fp64", w.shape, w.params)
