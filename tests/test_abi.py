@@ -96,3 +96,61 @@ def test_buffer_bytes():
     assert fb == 19 * 512 * 4 and qb == 5 * 512 * 4 and sb > 0
     fb, qb, sb = lc.lc_buffer_bytes(lc.make_grid(lc.LC_D2Q9, lc.LC_FP64, 16, 8, 1))
     assert fb == 9 * 128 * 8 and qb == 5 * 128 * 8
+
+
+def test_host_side_validation_of_settings_and_reverse_calls():
+    """Collision, variant and chunk settings and the reverse-sweep entry
+    points reject bad arguments on the host, before any device work."""
+    from paper_1907_13415_amd import lc
+    params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
+    ctx3 = lc.lc_init(lc.make_grid(lc.LC_D3Q19, lc.LC_FP32_DEV, 8, 8, 8), params, _fake_bufs(lc), 0)
+    ctx2 = lc.lc_init(lc.make_grid(lc.LC_D2Q9, lc.LC_FP64, 16, 16, 1), params, _fake_bufs(lc), 0)
+    try:
+        for ctx, rates in ((ctx3, (1.1, 1.2, 1.3)), (ctx3, (1.0, 1.0, 1.0, 1.0, 2.0)), (ctx2, (1.0, 0.0, 1.0)),
+                           (ctx2, (1.0, 1.0, 1.0, 1.0, 1.0))):
+            with pytest.raises(lc.LCError) as e:
+                lc.lc_set_collision(ctx, lc.LC_COLL_MRT, rates)
+            assert e.value.code == lc.LC_EINVAL
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_set_collision(ctx3, 5)
+        assert e.value.code == lc.LC_EINVAL
+        lc.lc_set_collision(ctx3, lc.LC_COLL_MRT, (1.2, 1.3, 1.4, 1.5, 1.6))
+        lc.lc_set_collision(ctx2, lc.LC_COLL_MRT, (1.2, 1.3, 1.4))
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_set_variant(ctx3, lc.LC_VARIANT_FUSED)
+        assert e.value.code == lc.LC_EUNSUPPORTED
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_set_variant(ctx3, 9)
+        assert e.value.code == lc.LC_EINVAL
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_set_chunk(ctx3, -1)
+        assert e.value.code == lc.LC_EINVAL
+        # the reverse step: D2Q9 double with BGK only, arguments checked first
+        dummy = 1 << 40
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_step(ctx3, dummy, dummy, dummy, dummy, dummy)
+        assert e.value.code == lc.LC_EUNSUPPORTED
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_step(ctx2, dummy, dummy, dummy, dummy, dummy)  # MRT selected above
+        assert e.value.code == lc.LC_EUNSUPPORTED
+        lc.lc_set_collision(ctx2, lc.LC_COLL_BGK)
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_segment(ctx2, dummy, dummy, 0, dummy, dummy, dummy, dummy)
+        assert e.value.code == lc.LC_EINVAL
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_segment(ctx2, dummy, dummy, 4, dummy + 8, dummy, dummy, dummy)  # misaligned history
+        assert e.value.code == lc.LC_EINVAL
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_backward(ctx2, [dummy, dummy], [dummy, dummy], [10, 0], dummy, dummy, dummy, dummy)
+        assert e.value.code == lc.LC_EINVAL
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_backward(ctx2, [], [], [], dummy, dummy, dummy, dummy)
+        assert e.value.code == lc.LC_EINVAL
+        g2 = lc.make_grid(lc.LC_D2Q9, lc.LC_FP64, 16, 16, 1)
+        h = lc.lc_vjp_history_bytes(g2, 10)
+        assert h == 11 * (9 + 5 + 10) * 256 * 8
+        assert lc.lc_vjp_backward_bytes(g2, 10) == 2 * ((h + 255) // 256 * 256)
+        assert lc.lc_vjp_backward_bytes(g2, 0) == 0
+    finally:
+        lc.lc_free(ctx3)
+        lc.lc_free(ctx2)
