@@ -157,6 +157,48 @@ def test_observables_match_oracle():
         assert o["step"] == 5 and o["nonfinite"] == 0
 
 
+def test_observables_3d_half_axis_z_match_oracle():
+    lc = _lc()
+    rng = np.random.default_rng(8)
+    shape = (12, 10, 14)
+    q5 = inputs.random_q5(shape, rng, amp=0.1)
+    rel = inputs.random_rel(19, shape, rng, amp=1e-3)
+    p = (1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
+    _, w = lc.lc_lattice_info(1)
+    s = lc.Solver("D3Q19", "fp64", shape, p)
+    s.load(q5, w.reshape(19, 1, 1, 1) * (1 + rel))
+    s.step(4)
+    f_ref, q_ref = oracle.run(1, oracle.rest_populations(1, shape, rel=rel), q5, p, 4)
+    for ax in (0, 1, 2):
+        o = s.observe(half_axis=ax)
+        r = oracle.observe(1, f_ref, q_ref, p, half_axis=ax)
+        assert abs(o["mass"] - r["mass"]) < 1e-12 * r["mass"]
+        np.testing.assert_allclose(o["mom"], r["mom"], rtol=0, atol=1e-13)
+        assert abs(o["umax"] - r["umax"]) < 1e-12 * SCALES["u"]
+        assert abs(o["ssum"] - r["ssum"]) < 1e-12 * r["ssum"]
+        assert abs(o["ssum_half"] - r["ssum_half"]) < 1e-12 * r["ssum"]
+
+
+def test_set_params_between_steps_equals_a_restart():
+    """Changing the parameters between steps (a temperature quench) gives the
+    same state, bit for bit, as exporting, loading into a fresh context with
+    the new parameters and stepping there."""
+    lc = _lc()
+    w = inputs.config0()
+    p2 = inputs.with_gamma(w.params, 2.705)
+    a = lc.Solver("D2Q9", "fp64", w.shape, w.params)
+    a.load(w.q5)
+    a.step(30)
+    f_mid, q_mid = a.export(lc.LC_FIELD_F), a.export(lc.LC_FIELD_Q)
+    a.set_params(p2)
+    a.step(30)
+    b = lc.Solver("D2Q9", "fp64", w.shape, p2)
+    b.load(q_mid, f_mid)
+    b.step(30)
+    assert np.array_equal(a.export(lc.LC_FIELD_Q), b.export(lc.LC_FIELD_Q))
+    assert np.array_equal(a.export(lc.LC_FIELD_F), b.export(lc.LC_FIELD_F))
+
+
 def test_nonfinite_state_is_reported():
     lc = _lc()
     shape = (1, 16, 16)
