@@ -337,18 +337,18 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
   constexpr int DIM = L::dim;
-  // In single precision a four-plane ring: the plane stored at iteration
-  // p+1 is never one the predictor of iteration p reads, so one barrier per
-  // plane suffices.  Double precision keeps three planes (LDS) and a second
-  // barrier.
-  constexpr bool RING4 = DIM == 3 && sizeof(S) == 4;
-  constexpr int NP = DIM == 3 ? (RING4 ? 4 : 3) : 1;
+  // Three LDS planes of Q and u (z-1, z, z+1 of the predictor).  Q^P on
+  // the tile and its ring: in single precision one LDS plane for the
+  // corrector's in-plane neighbours, its centre and z neighbours being the
+  // owner's own predictor values kept in registers; in double precision
+  // (one wave per SIMD, where registers are the scarcer resource) three LDS
+  // planes, z-1, z and z+1 of the corrector.
+  constexpr bool ZREG = DIM == 3 && sizeof(S) == 4;
+  constexpr int NP = DIM == 3 ? 3 : 1;
+  constexpr int NPS = (DIM == 3 && !ZREG) ? 3 : 1;
   constexpr int NC = 5 + DIM;  // Q components then u components
-  // predictor planes: the corrector of plane p reads Q^P of planes p-1,
-  // p and p+1
-  constexpr int NPP = DIM == 3 ? 3 : 1;
   __shared__ S sQ[NP][NC][T::R2];
-  __shared__ S sP[NPP][5][T::R1];
+  __shared__ S sP[NPS][5][T::R1];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   const int x0 = bx * TX, y0 = by * TY;
@@ -362,15 +362,17 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   for (int a = 0; a < DIM; a++) src[5 + a] = uin + a * N;
   const S* const* csrc = src;
 
-  // What the owner keeps from its predictor for its corrector: R(Q) and the
-  // flow terms (from u/2 and the undivided velocity differences; RAW form).
-  // With the four-plane ring Q itself is read back from LDS (plane p-1 stays
-  // there until the barrier of iteration p+1); with three planes the next
-  // iteration overwrites it without a barrier, so the owner keeps it.
+  // What the owner keeps from its predictor for its corrector: Q, R(Q) and
+  // the flow terms (from u/2 and the undivided velocity differences; RAW
+  // form).  Q^P = Q + R(Q) is formed from them again where needed (the same
+  // expression, so the same rounding as the value shared through LDS).
   struct Stash {
     Sym<S> r;
     Flow<S> fl;
-    Sym<S> q;  // used without the four-plane ring only
+    Sym<S> q;
+  };
+  auto qp_of = [](const Stash& st) {
+    return Sym<S>{st.q.xx + st.r.xx, st.q.xy + st.r.xy, st.q.xz + st.r.xz, st.q.yy + st.r.yy, st.q.yz + st.r.yz};
   };
 
   // rate and predictor at R1 point (i, j) of plane slot m; returns Q^P
@@ -392,65 +394,52 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     }
     st.fl = flow_terms<S, true>(u, G, c);
     st.r = be_rate_flow<S, true>(q, H, d, st.fl, c);
-    if constexpr (!RING4) st.q = q;
-    return Sym<S>{q.xx + st.r.xx, q.xy + st.r.xy, q.xz + st.r.xz, q.yy + st.r.yy, q.yz + st.r.yz};
+    st.q = q;
+    return qp_of(st);
   };
-  auto store_pred = [&](int ps, int i, int j, const Sym<S>& qp) {
+  auto store_pred = [&](int b, int i, int j, const Sym<S>& qp) {
     const int k1 = i + T::W1 * j;
-    sP[ps][0][k1] = qp.xx;
-    sP[ps][1][k1] = qp.xy;
-    sP[ps][2][k1] = qp.xz;
-    sP[ps][3][k1] = qp.yy;
-    sP[ps][4][k1] = qp.yz;
+    sP[b][0][k1] = qp.xx;
+    sP[b][1][k1] = qp.xy;
+    sP[b][2][k1] = qp.xz;
+    sP[b][3][k1] = qp.yy;
+    sP[b][4][k1] = qp.yz;
   };
-  // predictor over the region into sP[ps]: the owner's site (kept in st),
-  // then a ring site for threads tid < RING.  The two calls inline the same
-  // expressions, and contraction into FMAs happens only within a source
-  // expression, so a site's predictor rounds the same as owner or ring.
-  auto pred_plane = [&](int m, int zp, int zm, int ps, Stash& st) {
-    store_pred(ps, tx + 1, ty + 1, pred_point(m, zp, zm, tx + 1, ty + 1, st));
-    if (tid < T::RING) {
-      int i, j;
-      T::ring(tid, i, j);
-      Stash tmp;
-      store_pred(ps, i, j, pred_point(m, zp, zm, i, j, tmp));
-    }
-  };
-  // corrector at the owner's site of plane z from the predictor planes
-  // ps (plane z) and pzp / pzm (planes z+1 / z-1)
-  auto corr_site = [&](int z, int m, int ps, int pzp, int pzm, const Stash& st) {
+  const int k1 = (tx + 1) + T::W1 * (ty + 1);
+  auto pred_at = [&](int b) { return Sym<S>{sP[b][0][k1], sP[b][1][k1], sP[b][2][k1], sP[b][3][k1], sP[b][4][k1]}; };
+  // corrector at the owner's site of plane z: in-plane neighbours of Q^P
+  // from sP[b], the centre pc and the z neighbours pzp / pzm (3D)
+  auto corr_site = [&](int z, int b, const Stash& st, const Sym<S>& pc, const Sym<S>& pzp, const Sym<S>& pzm) {
     if (!own) return;
-    const int kq = T::r2(tx + 1, ty + 1);
-    const Sym<S> q = RING4 ? Sym<S>{sQ[m][0][kq], sQ[m][1][kq], sQ[m][2][kq], sQ[m][3][kq], sQ[m][4][kq]} : st.q;
-    const int k1 = (tx + 1) + T::W1 * (ty + 1);
-    S v[5], lap[5], dx[5], dy[5], dz[5];
+    const S vc[5] = {pc.xx, pc.xy, pc.xz, pc.yy, pc.yz};
+    const S vzp[5] = {pzp.xx, pzp.xy, pzp.xz, pzp.yy, pzp.yz};
+    const S vzm[5] = {pzm.xx, pzm.xy, pzm.xz, pzm.yy, pzm.yz};
+    S lap[5], dx[5], dy[5], dz[5];
 #pragma unroll
     for (int q = 0; q < 5; q++) {
-      const S cc = sP[ps][q][k1];
-      const S xp = sP[ps][q][k1 + 1], xm = sP[ps][q][k1 - 1];
-      const S yp = sP[ps][q][k1 + T::W1], ym = sP[ps][q][k1 - T::W1];
-      v[q] = cc;
+      const S cc = vc[q];
+      const S xp = sP[b][q][k1 + 1], xm = sP[b][q][k1 - 1];
+      const S yp = sP[b][q][k1 + T::W1], ym = sP[b][q][k1 - T::W1];
       dx[q] = xp - xm;
       dy[q] = yp - ym;
       S l = (xp + xm) + (yp + ym);
       if constexpr (DIM == 3) {
-        const S zpv = sP[pzp][q][k1], zmv = sP[pzm][q][k1];
-        dz[q] = zpv - zmv;
-        l += zpv + zmv;
+        dz[q] = vzp[q] - vzm[q];
+        l += vzp[q] + vzm[q];
         lap[q] = l - S(6) * cc;
       } else {
         dz[q] = S(0);
         lap[q] = l - S(4) * cc;
       }
     }
-    const Sym<S> p{v[0], v[1], v[2], v[3], v[4]};
     const Sym<S> d[3] = {Sym<S>{dx[0], dx[1], dx[2], dx[3], dx[4]}, Sym<S>{dy[0], dy[1], dy[2], dy[3], dy[4]},
                          Sym<S>{dz[0], dz[1], dz[2], dz[3], dz[4]}};
     const Sym<S> Lp{lap[0], lap[1], lap[2], lap[3], lap[4]};
-    const Sym<S> H = molecular_field(p, Lp, c);
-    const Sym<S> Rp = be_rate_flow<S, true>(p, H, d, st.fl, c);
+    const Sym<S> H = molecular_field(pc, Lp, c);
+    const Sym<S> Rp = be_rate_flow<S, true>(pc, H, d, st.fl, c);
     const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-    if (rec) store_sym(rec, N, s, p);  // record the predictor (reverse-mode replay)
+    if (rec) store_sym(rec, N, s, pc);  // record the predictor (reverse-mode replay)
+    const Sym<S>& q = st.q;
     Qout[s] = q.xx + S(0.5) * (st.r.xx + Rp.xx);
     Qout[N + s] = q.xy + S(0.5) * (st.r.xy + Rp.xy);
     Qout[2 * N + s] = q.xz + S(0.5) * (st.r.xz + Rp.xz);
@@ -462,36 +451,68 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     load_region<S, TX, TY, NC>(&sQ[0][0][0], csrc, x0, y0, 0, g, tid);
     __syncthreads();
     Stash st;
-    pred_plane(0, 0, 0, 0, st);
+    const Sym<S> pc = pred_point(0, 0, 0, tx + 1, ty + 1, st);
+    store_pred(0, tx + 1, ty + 1, pc);
+    if (tid < T::RING) {
+      int i, j;
+      T::ring(tid, i, j);
+      Stash tmp;
+      store_pred(0, i, j, pred_point(0, 0, 0, i, j, tmp));
+    }
     __syncthreads();
-    corr_site(0, 0, 0, 0, 0, st);
+    corr_site(0, 0, st, pc, pc, pc);
   } else {
     const int zb = bz * zc;
     const int ze = min(zb + zc, g.nz);
-    auto slot = [](int p) { return (p + NP) % NP; };   // p >= -NP
-    auto pslot = [](int p) { return (p + 3) % 3; };    // p >= -3
+    auto slot = [](int p) { return (p + 3) % 3; };  // p >= -3
     RegionRegs<S, TX, TY, NC> rq;
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 2)][0][0], csrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
     load_region<S, TX, TY, NC>(&sQ[slot(zb - 1)][0][0], csrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
     fetch_region<S, TX, TY, NC>(rq, csrc, x0, y0, wrapi(zb, g.nz), g, tid);
+    auto pslot = [](int p) { return (p + 3) % 3; };  // p >= -3
+    Sym<S> pm = sym_zero<S>();  // Q^P of plane p-2 at the owner's site (ZREG)
     // one plane of the pipeline: predictor of plane p, corrector of p-1;
     // `prev` holds the stash of plane p-1, `cur` receives that of plane p
     auto iteration = [&](int p, const Stash& prev, Stash& cur) {
-      // with four slots, slot(p+1) was last read by the predictor of
-      // iteration p-2, which every thread finished before the barrier of
-      // iteration p-1 (with three, the second barrier below protects it)
+      // slot(p+1) = slot(p-2) was last read by the predictor of iteration
+      // p-1, before that iteration's second barrier
       store_region<S, TX, TY, NC>(rq, &sQ[slot(p + 1)][0][0], tid);
       if (p + 2 <= ze + 1) fetch_region<S, TX, TY, NC>(rq, csrc, x0, y0, wrapi(p + 2, g.nz), g, tid);
+      // plane p+1 of Q and u, and the Q^P written in iteration p-1, are
+      // visible after this barrier
       __syncthreads();
-      // the predictor writes sP[pslot(p)], last read by the corrector of
-      // iteration p-1, which precedes the barrier above; the corrector reads
-      // the owner's own Q^P of plane p, written by the same thread
-      pred_plane(slot(p), slot(p + 1), slot(p - 1), pslot(p), cur);
-      if constexpr (!RING4) __syncthreads();
-      if (p - 1 >= zb) corr_site(p - 1, slot(p - 1), pslot(p - 1), pslot(p), pslot(p - 2), prev);
+      // without ZREG, sP[pslot(p)] was last read by the corrector of
+      // iteration p-1, and the predictor values go there at once
+      const Sym<S> own_p = pred_point(slot(p), slot(p + 1), slot(p - 1), tx + 1, ty + 1, cur);
+      if constexpr (!ZREG) store_pred(pslot(p), tx + 1, ty + 1, own_p);
+      const bool ring = tid < T::RING;
+      int ri = 0, rj = 0;
+      Sym<S> ring_p = sym_zero<S>();
+      if (ring) {
+        T::ring(tid, ri, rj);
+        Stash tmp;
+        ring_p = pred_point(slot(p), slot(p + 1), slot(p - 1), ri, rj, tmp);
+        if constexpr (!ZREG) store_pred(pslot(p), ri, rj, ring_p);
+      }
+      if constexpr (ZREG) {
+        const Sym<S> pc = qp_of(prev);  // Q^P of plane p-1
+        if (p - 1 >= zb) corr_site(p - 1, 0, prev, pc, own_p, pm);
+        // every corrector has read plane p-1 of Q^P, every predictor plane
+        // p-1 of Q and u: both may be overwritten
+        __syncthreads();
+        store_pred(0, tx + 1, ty + 1, own_p);
+        if (ring) store_pred(0, ri, rj, ring_p);
+        pm = pc;
+      } else {
+        // Q^P of plane p visible; every predictor has read plane p-1 of Q
+        // and u, which may be overwritten
+        __syncthreads();
+        if (p - 1 >= zb)
+          corr_site(p - 1, pslot(p - 1), prev, pred_at(pslot(p - 1)), pred_at(pslot(p)), pred_at(pslot(p - 2)));
+      }
     };
     // two planes per trip, so the two stashes swap roles without copies
-    Stash stA, stB;
+    Stash stA{}, stB{};
     int p = zb - 1;
     for (; p + 1 <= ze; p += 2) {
       iteration(p, stA, stB);
