@@ -31,8 +31,10 @@ __global__ void __launch_bounds__(TX* TY)
   const BatchDesc<S> d = desc[k];
   const int t = b - d.tile0[0];
   const GridDims g{d.nx, d.ny, 1, d.N};
-  split_lb_body<LAT, S, DEV, TX, TY>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g, d.c, 1,
-                                     t % d.tiles_x[0], t / d.tiles_x[0], 0);
+  // many grids stream through the caches together: populations read with
+  // nontemporal loads
+  split_lb_body<LAT, S, DEV, TX, TY, false, true>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g, d.c,
+                                                  1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
 }
 
 template <int LAT, typename S, int TX, int TY>

@@ -165,7 +165,10 @@ __device__ __forceinline__ void store_out(S* p, S v) {
   __builtin_nontemporal_store(v, p);
 }
 
-template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false>
+// STREAM_F: read the populations with nontemporal loads (each is pulled by
+// one site only; measured to help where many grids share the caches, and to
+// hurt a single small grid that stays resident in them).
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false, bool STREAM_F = false>
 __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S* __restrict__ fin,
                                               S* __restrict__ fout, S* __restrict__ uout, const GridDims& g,
                                               const Coef<S>& c, int zc, int bx, int by, int bz,
@@ -258,7 +261,11 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
       if (L::cy(i) == -1) d += o.yp;
       if (L::cz(i) == 1) d += o.zm;
       if (L::cz(i) == -1) d += o.zp;
-      f[i] = (fin + size_t(i) * size_t(N))[d];
+      const S* a = &(fin + size_t(i) * size_t(N))[d];
+      if constexpr (STREAM_F)
+        f[i] = __builtin_nontemporal_load(a);
+      else
+        f[i] = *a;
     }
   };
   // lattice-Boltzmann update of the owner's site in plane z; writes the
