@@ -19,8 +19,10 @@ with what the paper prints and with the mean-field bulk phase diagram.
    temperature of zero velocity found by bisection, and D3Q19 on one plane
    (the paper's lattice) against D2Q9.
 
-The paper ran an MRT collision with unstated rates; this library runs BGK,
-so spurious-current amplitudes are compared in order of magnitude only.
+The paper ran an MRT collision with unstated rates.  The circle runs both
+with BGK and with MRT on the standard basis at the ghost rates of Lallemand
+and Luo; spurious-current amplitudes are compared in order of magnitude
+only.
 """
 import math
 import sys
@@ -46,9 +48,11 @@ def s_nematic(g):
     return 0.25 + 0.75 * math.sqrt(1.0 - 8.0 / (3.0 * g))
 
 
-def _solver(q5, gamma, lattice="D2Q9", prec="fp64"):
+def _solver(q5, gamma, lattice="D2Q9", prec="fp64", mrt=None):
     from paper_1907_13415_amd import lc
     s = lc.Solver(lattice, prec, q5.shape[1:], inputs.with_gamma(PAPER, gamma))
+    if mrt is not None:
+        s.set_collision(lc.LC_COLL_MRT, mrt)
     s.load(q5)
     return s
 
@@ -131,14 +135,22 @@ def test_bulk_limits(gamma, start, expect):
         assert abs(S.min() - s_nematic(gamma)) < 1e-6 and abs(S.max() - s_nematic(gamma)) < 1e-6
 
 
-def _circle(gamma, t=35000, dt=1000, angle=0.0, lattice="D2Q9", prec="fp64"):
-    s = _solver(inputs.paper_circle(100, 25.0, angle), gamma, lattice, prec)
+def _circle(gamma, t=35000, dt=1000, angle=0.0, lattice="D2Q9", prec="fp64", mrt=None):
+    s = _solver(inputs.paper_circle(100, 25.0, angle), gamma, lattice, prec, mrt)
     sn = s_nematic(gamma)
     o0 = _run_to(s, t - dt)
     o1 = _run_to(s, t)
     r0 = math.sqrt(o0["ssum"] / (math.pi * sn))
     r1 = math.sqrt(o1["ssum"] / (math.pi * sn))
     return (r1 - r0) / dt, r1, o1["umax"], s
+
+
+def _grows(gamma, **kw):
+    """Whether the nucleus grows at t = 35000: its radius increases.  Below
+    the static temperature it shrinks, and far below it has melted by then
+    (radius near 0, a residual rate at the level of rounding, either sign)."""
+    v, r, _, _ = _circle(gamma, **kw)
+    return v > 0 and r > 20.0
 
 
 def test_circle_static_temperature_and_spurious_currents():
@@ -150,16 +162,17 @@ def test_circle_static_temperature_and_spurious_currents():
     require_gpu()
     from paper_1907_13415_amd import lc
     lo, hi = 2.700, 2.715
-    vlo = _circle(lo)[0]
-    vhi = _circle(hi)[0]
-    _say("circle: interface velocity at t=35000 %.3e at gamma %.3f, %.3e at %.3f" % (vlo, lo, vhi, hi))
-    assert vlo < 0 < vhi  # shrinks below the static temperature, grows above
+    vlo, rlo = _circle(lo)[:2]
+    vhi, rhi = _circle(hi)[:2]
+    _say("circle: at t=35000 R %.3f, interface velocity %.3e at gamma %.3f; R %.3f, %.3e at %.3f"
+         % (rlo, vlo, lo, rhi, vhi, hi))
+    assert not _grows(lo) and _grows(hi)  # shrinks below the static temperature, grows above
     for _ in range(11):
         mid = 0.5 * (lo + hi)
-        if _circle(mid)[0] < 0:
-            lo = mid
-        else:
+        if _grows(mid):
             hi = mid
+        else:
+            lo = mid
     g = 0.5 * (lo + hi)
     vi, r, umax, _ = _circle(g)
     _say("circle: static temperature %.6f (paper 2.707681); there R %.4f, interface velocity %.2e, "
@@ -177,6 +190,38 @@ def test_circle_static_temperature_and_spurious_currents():
     d = float(np.abs(s2.export(lc.LC_FIELD_S) - s3.export(lc.LC_FIELD_S)).max())
     _say("  D3Q19 on one plane: max|S(D3Q19) - S(D2Q9)| %.2e, max|u| %.3e" % (d, umax3))
     assert d < 1e-10 and abs(umax3 - up) < 1e-3 * up
+
+
+# D2Q9 ghost rates (s_e, s_eps, s_q) of Lallemand and Luo (2000); the paper
+# names MRT but not its rates
+LL_RATES = (1.64, 1.54, 1.9)
+
+
+def test_circle_with_mrt():
+    """The circle of Sec. 2 with the MRT collision the paper ran (standard
+    D2Q9 basis, ghost rates of Lallemand and Luo): the static temperature
+    moves by less than the bisection width from the BGK one (the ghost
+    moments do not enter the Chapman-Enskog hydrodynamics), and the spurious
+    currents stay of order 1e-6 (paper: 8.97e-7 and 1.13e-6 at 20 degrees)."""
+    require_gpu()
+    lo, hi = 2.700, 2.715
+    assert not _grows(lo, mrt=LL_RATES) and _grows(hi, mrt=LL_RATES)
+    for _ in range(11):
+        mid = 0.5 * (lo + hi)
+        if _grows(mid, mrt=LL_RATES):
+            hi = mid
+        else:
+            lo = mid
+    g = 0.5 * (lo + hi)
+    vi, r, umax, _ = _circle(g, mrt=LL_RATES)
+    vb, rb, ub, _ = _circle(g)
+    _say("circle, MRT %s: static temperature %.6f (paper 2.707681); there R %.4f, max|u| %.3e "
+         "(BGK at the same temperature: R %.4f, max|u| %.3e)" % (LL_RATES, g, r, umax, rb, ub))
+    assert abs(g - 2.707681) < 5e-4
+    assert 1e-7 < umax < 1e-5
+    _, _, umax20, _ = _circle(g, angle=20.0, mrt=LL_RATES)
+    _say("  director turned by 20 deg: max|u| %.3e (paper 1.13e-6)" % umax20)
+    assert 1e-7 < umax20 < 1e-5
 
 
 def test_fp32_errors_on_interface_and_spurious_velocity():
