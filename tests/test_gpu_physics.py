@@ -36,6 +36,9 @@ from gpu_util import require_gpu
 pytestmark = pytest.mark.gpu
 
 PAPER = inputs.PAPER_PARAMS
+# D2Q9 ghost rates (s_e, s_eps, s_q) of Lallemand and Luo (2000); the paper
+# names MRT but not its rates
+LL_RATES = (1.64, 1.54, 1.9)
 
 
 def _say(m):
@@ -67,11 +70,12 @@ def _run_to(s, t):
     return s.observe(half_axis=0)
 
 
-def test_flat_interface_static_at_coexistence():
+@pytest.mark.parametrize("mrt", [None, LL_RATES], ids=["bgk", "mrt"])
+def test_flat_interface_static_at_coexistence(mrt):
     require_gpu()
     from paper_1907_13415_amd import lc
     nx, ny = 128, 4
-    s = _solver(inputs.paper_flat(nx, ny), 2.7)
+    s = _solver(inputs.paper_flat(nx, ny), 2.7, mrt=mrt)
     o0 = _run_to(s, 250000)
     o1 = _run_to(s, 350000)
     S = s.export(lc.LC_FIELD_S)[0, 0].mean(axis=0)
@@ -81,8 +85,9 @@ def test_flat_interface_static_at_coexistence():
     fun = lambda xx, xi, lam: (1 / 6) * (1 - np.tanh((xx - xi) / (2 * lam)))
     (xi, lam), _ = curve_fit(fun, x[sel], S[sel], p0=(96.0, 2.0))
     disp = (o1["ssum_half"] - o0["ssum_half"]) / (ny / 3.0)
-    _say("flat, gamma 2.7, t=350000: lambda %.5f  x_i %.4f  S(centre) %.9f  S(far) %.2e  "
-         "drift over 1e5 steps %.2e  max|u| %.2e" % (lam, xi, S[nx // 2], S[0], disp, o1["umax"]))
+    _say("flat (%s), gamma 2.7, t=350000: lambda %.5f  x_i %.4f  S(centre) %.9f  S(far) %.2e  "
+         "drift over 1e5 steps %.2e  max|u| %.2e" % ("MRT" if mrt else "BGK", lam, xi, S[nx // 2], S[0], disp,
+                                                     o1["umax"]))
     assert abs(lam - 2.0) < 0.05
     # the tails of the two interfaces, 32 sites = 16 widths apart, overlap by
     # (1/3) exp(-16) ~ 4e-8 at the centre and at the far point
@@ -92,19 +97,21 @@ def test_flat_interface_static_at_coexistence():
     assert o1["umax"] < 1e-12  # the paper: below machine precision
 
 
-def test_flat_interface_velocity_near_coexistence():
+@pytest.mark.parametrize("mrt", [None, LL_RATES], ids=["bgk", "mrt"])
+def test_flat_interface_velocity_near_coexistence(mrt):
     require_gpu()
     nx, ny = 256, 4
     res = {}
     for g in (2.699, 2.701):
-        s = _solver(inputs.paper_flat(nx, ny), g)
+        s = _solver(inputs.paper_flat(nx, ny), g, mrt=mrt)
         o0 = _run_to(s, 100000)
         o1 = _run_to(s, 300000)
         v = (o1["ssum_half"] - o0["ssum_half"]) / (s_nematic(g) * ny) / 200000
         lam = math.sqrt(27 * PAPER[2] / (PAPER[0] * g))
         est = 10.0 / 9.0 * PAPER[3] * PAPER[0] * lam * (g - 2.7)
         res[g] = (v, est)
-        _say("flat, gamma %.3f: interface velocity %.4e (travelling-wave estimate %.4e)" % (g, v, est))
+        _say("flat (%s), gamma %.3f: interface velocity %.4e (travelling-wave estimate %.4e)"
+             % ("MRT" if mrt else "BGK", g, v, est))
     (vm, em), (vp, ep) = res[2.699], res[2.701]
     assert vm < 0 < vp  # nematic shrinks below coexistence, grows above
     assert abs(vp + vm) < 0.05 * abs(vp)  # linear in the shift this close
@@ -190,11 +197,6 @@ def test_circle_static_temperature_and_spurious_currents():
     d = float(np.abs(s2.export(lc.LC_FIELD_S) - s3.export(lc.LC_FIELD_S)).max())
     _say("  D3Q19 on one plane: max|S(D3Q19) - S(D2Q9)| %.2e, max|u| %.3e" % (d, umax3))
     assert d < 1e-10 and abs(umax3 - up) < 1e-3 * up
-
-
-# D2Q9 ghost rates (s_e, s_eps, s_q) of Lallemand and Luo (2000); the paper
-# names MRT but not its rates
-LL_RATES = (1.64, 1.54, 1.9)
 
 
 def test_circle_with_mrt():
