@@ -50,14 +50,15 @@ def kernel_hash():
     return h.hexdigest()[:12]
 
 
-def measured_traffic():
-    """HBM bytes per step from the committed counter summary, if it was
-    taken on the current kernel sources (else None)."""
+def measured_traffic(key="hbm_bytes_per_step"):
+    """HBM bytes (per step, or per launch of one sweep) from the committed
+    counter summary, if it was taken on the current kernel sources (else
+    None)."""
     if not os.path.exists(COUNTERS):
         return None
     txt = open(COUNTERS).read()
     m = re.search(r"kernel_sources_sha1:\s*([0-9a-f]+)", txt)
-    t = re.search(r"hbm_bytes_per_step:\s*([0-9.eE+]+)", txt)
+    t = re.search(r"^" + key + r":\s*([0-9.eE+]+)", txt, re.M)
     if not m or not t or m.group(1) != kernel_hash():
         return None
     return float(t.group(1))
@@ -327,6 +328,11 @@ def main():
     kernel_ms = sum(r32["kernel_ms"])  # the two sweeps of one step
     achieved = bytes_site * N / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic()
+    # measured HBM rate of each sweep: counter bytes per launch over its
+    # event-timed duration
+    per_launch = [measured_traffic("hbm_bytes_per_launch_split_lb"), measured_traffic("hbm_bytes_per_launch_split_q")]
+    measured_gbs = [None if b is None else round(b / (ms * 1e-3) / 1e9, 1)
+                    for b, ms in zip(per_launch, r32["kernel_ms"])]
     out = {
         "metric": METRIC,
         "value": round(mlups32, 2),
@@ -344,6 +350,7 @@ def main():
                    "storage": "fp32 deviation", "gamma": 2.7, "steps_in_config": 500},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "measured_gbs_per_sweep": measured_gbs,
                      "kernel": "split_lb + split_q (the two launches of one step)",
                      "bytes_per_site": bytes_site, "sites_per_launch": N,
                      "kernel_ms": [round(v, 5) for v in r32["kernel_ms"]]},
