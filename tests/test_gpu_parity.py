@@ -244,6 +244,27 @@ def test_fp32dev_within_tolerance_on_S(variant):
     assert err < 1e-5
 
 
+def test_fp32dev_slab_256cubed_500_steps_within_tolerance_on_S():
+    """The 256^3 D3Q19 slab over its 500 steps in the FP32 deviation form
+    against double precision on the GPU (which matches the oracle to
+    1e-12): |S32 - S64| <= 1e-5 at every site."""
+    import torch
+    lc = _lc()
+    w = inputs.config2(256)
+    _announce("fp32dev vs fp64, 256^3 slab, 500 steps")
+    S = []
+    for prec in ("fp64", "fp32dev"):
+        s = lc.Solver("D3Q19", prec, w.shape, w.params)
+        s.load(w.q5)
+        s.step(500)
+        S.append(_export_dev(lc, s, lc.LC_FIELD_S, 1))
+        del s
+        torch.cuda.empty_cache()
+    err = float((S[1] - S[0]).abs().max().item())
+    _announce("  max |S32 - S64| = %.3e" % err)
+    assert err < 1e-5
+
+
 def _export_dev(lc, s, field, ncomp):
     import torch
     out = torch.empty((ncomp,) + s.shape, dtype=torch.float64, device=s.device)
