@@ -25,6 +25,13 @@
  *  - Storage precision.  LC_FP64 stores f and Q as double.  LC_FP32_DEV
  *    stores the deviation f_i - w_i*rho0 (rho0 = 1) and Q as float and does
  *    all per-site arithmetic in float; reductions accumulate in double.
+ *    LC_MIXED stores f as LC_FP32_DEV does (float deviations, float moments
+ *    and collision, float velocity) and Q as double, with the molecular
+ *    field, stress, body force and Q update in double: the float rounding
+ *    of the Q right-hand side, which moves slow interfaces in LC_FP32_DEV,
+ *    is gone, at 2(q*4 + 5*8) bytes per site update.  LC_MIXED runs the
+ *    split variant only (LC_VARIANT_STAGED: LC_EUNSUPPORTED) and single
+ *    grids only (the batched form rejects it).
  *    Every load/export entry point speaks double "logical" values (full f)
  *    whatever the storage precision.
  *  - Memory ownership.  The caller allocates and owns every device buffer
@@ -60,6 +67,7 @@ typedef int32_t lc_status;
 
 #define LC_FP64 0
 #define LC_FP32_DEV 1
+#define LC_MIXED 2
 
 /* Collision operators for lc_set_collision. */
 #define LC_COLL_BGK 0 /* single relaxation time (default) */
@@ -76,7 +84,7 @@ typedef int32_t lc_status;
  * rejected with LC_EINVAL. */
 typedef struct {
   int32_t lattice;   /* LC_D2Q9 or LC_D3Q19 */
-  int32_t precision; /* LC_FP64 or LC_FP32_DEV */
+  int32_t precision; /* LC_FP64, LC_FP32_DEV or LC_MIXED */
   int32_t nx, ny, nz;
 } lc_grid;
 
@@ -94,7 +102,8 @@ typedef struct {
 } lc_params;
 
 /* Caller-owned device buffers.  f[0], f[1]: q*N values each; Q[0], Q[1]:
- * 5*N values each (element size 8 for LC_FP64, 4 for LC_FP32_DEV);
+ * 5*N values each (element size 8 for LC_FP64, 4 for LC_FP32_DEV; for
+ * LC_MIXED 4 for f and 8 for Q);
  * scratch: the scratch_bytes reported by lc_buffer_bytes.  All 256-byte aligned, disjoint, and
  * valid for the lifetime of the context. */
 typedef struct {
@@ -164,7 +173,8 @@ lc_status lc_init(const lc_grid *grid, const lc_params *params, const lc_buffers
 lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 
 /* Choose the kernel variant (LC_VARIANT_*); AUTO picks the fastest the
- * build provides for this grid.  LC_EUNSUPPORTED if not available. */
+ * build provides for this grid.  LC_EUNSUPPORTED if not available (the
+ * fused variant; the staged variant for LC_MIXED). */
 lc_status lc_set_variant(lc_ctx *ctx, int32_t variant);
 
 /* Collision operator of the lattice-Boltzmann update.  LC_COLL_BGK (the
@@ -282,7 +292,9 @@ lc_status lc_free(lc_ctx *ctx);
  * Batched form: many independent two-dimensional D2Q9 grids of their own
  * sizes and parameters (for example a temperature sweep in gamma around the
  * coexistence value of Sec. 2.1) advanced together.  All grids share one
- * storage precision.  The grids' fields live in caller-owned arenas: grid k
+ * storage precision, LC_FP64 or LC_FP32_DEV (LC_MIXED: LC_EUNSUPPORTED from
+ * lc_batch_layout and lc_batch_init).  The grids' fields live in
+ * caller-owned arenas: grid k
  * occupies f_offsets[k] bytes into each f arena (9*N_k values) and
  * q_offsets[k] bytes into each Q arena (5*N_k values), in the single-grid
  * layout.  A step of the batch is two kernel launches covering the tiles of

@@ -5,12 +5,15 @@
 
 namespace lc {
 
+// Every kernel here takes the population type S (with DEV for the deviation
+// form) and the order-tensor type QT (S, or double in the mixed form).
+
 // Logical double state -> storage form.  f_dev == nullptr: fluid at rest.
 // The population buffer is in pull form: buf_i(y) = f_i(y + c_i).
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 __global__ void __launch_bounds__(256) load_state(const double* __restrict__ f_dev,
                                                   const double* __restrict__ q_dev, S* __restrict__ f,
-                                                  S* __restrict__ Q, GridDims g) {
+                                                  QT* __restrict__ Q, GridDims g) {
   using L = Lattice<LAT>;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -33,11 +36,11 @@ __global__ void __launch_bounds__(256) load_state(const double* __restrict__ f_d
     f[i * N + s] = DEV ? S(v - w) : S(v);
   }
 #pragma unroll
-  for (int k = 0; k < 5; k++) Q[k * N + s] = S(q_dev[k * N + s]);
+  for (int k = 0; k < 5; k++) Q[k * N + s] = QT(q_dev[k * N + s]);
 }
 
-template <int LAT, typename S, bool DEV>
-__global__ void __launch_bounds__(256) export_fq(const S* __restrict__ fb, const S* __restrict__ Q,
+template <int LAT, typename S, bool DEV, typename QT = S>
+__global__ void __launch_bounds__(256) export_fq(const S* __restrict__ fb, const QT* __restrict__ Q,
                                                  double* __restrict__ fo, double* __restrict__ qo, GridDims g) {
   using L = Lattice<LAT>;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -59,10 +62,11 @@ __global__ void __launch_bounds__(256) export_fq(const S* __restrict__ fb, const
   }
 }
 
-// Derived fields: 0 rho, 1 u (3), 2 force (3), 3 S.  Needs tau in scratch.
-template <int LAT, typename S, bool DEV>
-__global__ void __launch_bounds__(256) export_derived(const S* __restrict__ fin, const S* __restrict__ Q,
-                                                      const S* __restrict__ tau, double* __restrict__ out,
+// Derived fields: 0 rho, 1 u (3), 2 force (3), 3 S.  Needs tau (QT) in
+// scratch.
+template <int LAT, typename S, bool DEV, typename QT = S>
+__global__ void __launch_bounds__(256) export_derived(const S* __restrict__ fin, const QT* __restrict__ Q,
+                                                      const QT* __restrict__ tau, double* __restrict__ out,
                                                       int which, GridDims g) {
   using L = Lattice<LAT>;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -72,23 +76,26 @@ __global__ void __launch_bounds__(256) export_derived(const S* __restrict__ fin,
   const int64_t N = g.N;
   const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
   if (which == 3) {
-    const Sym<S> q = load_sym(Q, N, s);
+    const Sym<QT> q = load_sym(Q, N, s);
     out[s] = sqrt(1.5 * double(ddot(q, q)));
     return;
   }
   const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
-  S F[3];
-  body_force<LAT, S>(tau, N, s, nb, F);
+  QT FQ[3];
+  body_force<LAT, QT>(tau, N, s, nb, FQ);
+  const S F[3] = {S(FQ[0]), S(FQ[1]), S(FQ[2])};
   S f[L::q];
   gather_f<LAT, S>(fin, N, s, nb, f);
-  S rho, u[3];
-  moments<LAT, S, DEV>(f, F, rho, u);
+  S rho, mass, u[3];
+  moments<LAT, S, DEV>(f, F, rho, u, mass);
   if (which == 0) {
-    out[s] = double(rho);
-  } else {
-    const S* v = which == 1 ? u : F;
+    out[s] = DEV ? 1.0 + double(mass) : double(rho);
+  } else if (which == 1) {
 #pragma unroll
-    for (int a = 0; a < 3; a++) out[a * N + s] = double(v[a]);
+    for (int a = 0; a < 3; a++) out[a * N + s] = double(u[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; a++) out[a * N + s] = double(FQ[a]);
   }
 }
 
@@ -131,9 +138,9 @@ __device__ __forceinline__ void block_reduce_obs(double (&v)[OBS_W], double* __r
   }
 }
 
-template <int LAT, typename S, bool DEV>
-__global__ void __launch_bounds__(256) observe_partial(const S* __restrict__ fin, const S* __restrict__ Q,
-                                                       const S* __restrict__ tau, double* __restrict__ partial,
+template <int LAT, typename S, bool DEV, typename QT = S>
+__global__ void __launch_bounds__(256) observe_partial(const S* __restrict__ fin, const QT* __restrict__ Q,
+                                                       const QT* __restrict__ tau, double* __restrict__ partial,
                                                        GridDims g, int half_axis, int want_u) {
   using L = Lattice<LAT>;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,13 +169,15 @@ __global__ void __launch_bounds__(256) observe_partial(const S* __restrict__ fin
     v[2] = jy;
     v[3] = jz;
     if (want_u) {
-      S F[3], rho, u[3];
-      body_force<LAT, S>(tau, N, s, nb, F);
+      QT FQ[3];
+      body_force<LAT, QT>(tau, N, s, nb, FQ);
+      const S F[3] = {S(FQ[0]), S(FQ[1]), S(FQ[2])};
+      S rho, u[3];
       moments<LAT, S, DEV>(f, F, rho, u);
       const double uu = double(u[0]) * u[0] + double(u[1]) * u[1] + double(u[2]) * u[2];
       v[4] = sqrt(uu);
     }
-    const Sym<S> q = load_sym(Q, N, s);
+    const Sym<QT> q = load_sym(Q, N, s);
     const double qq = double(q.xx) * q.xx + double(q.yy) * q.yy + (double(q.xx) + q.yy) * (double(q.xx) + q.yy) +
                       2.0 * (double(q.xy) * q.xy + double(q.xz) * q.xz + double(q.yz) * q.yz);
     bad |= !isfinite(qq);

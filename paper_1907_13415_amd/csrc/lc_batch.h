@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(TX* TY)
   // many grids stream through the caches together: populations read with
   // nontemporal loads
   split_lb_body<LAT, S, DEV, TX, TY, false, true>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g, d.c,
-                                                  1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
+                                                  d.c, 1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
 }
 
 template <int LAT, typename S, int TX, int TY>

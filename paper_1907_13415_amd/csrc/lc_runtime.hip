@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 
 #include "../../include/lc.h"
 #include "lc_aux.h"
@@ -43,7 +44,7 @@ int lattice_q(int lattice) { return lattice == LC_D2Q9 ? 9 : 19; }
 lc_status check_grid(const lc_grid* g) {
   if (!g) return fail(LC_EINVAL, "grid is NULL");
   if (g->lattice != LC_D2Q9 && g->lattice != LC_D3Q19) return fail(LC_EINVAL, "unknown lattice %d", g->lattice);
-  if (g->precision != LC_FP64 && g->precision != LC_FP32_DEV)
+  if (g->precision != LC_FP64 && g->precision != LC_FP32_DEV && g->precision != LC_MIXED)
     return fail(LC_EINVAL, "unknown precision %d", g->precision);
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(LC_EINVAL, "grid dimensions must be >= 1");
   if (g->lattice == LC_D2Q9 && g->nz != 1) return fail(LC_EINVAL, "D2Q9 requires nz == 1");
@@ -91,23 +92,25 @@ Layout layout_of(const lc_grid& g) {
   Layout L;
   const int64_t N = int64_t(g.nx) * g.ny * g.nz;
   const size_t es = g.precision == LC_FP64 ? 8 : 4;
+  const size_t es_q = g.precision == LC_FP32_DEV ? 4 : 8;
   const int dim = g.lattice == LC_D2Q9 ? 2 : 3;
   const int ntau = dim == 2 ? 4 : 9;
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
   L.N = N;
   L.q = lattice_q(g.lattice);
   L.es = es;
+  L.es_q = es_q;
   L.f_bytes = size_t(L.q) * N * es;
-  L.q_bytes = size_t(5) * N * es;
+  L.q_bytes = size_t(5) * N * es_q;
   size_t off = 0;
   L.off_tau = off;
-  off = up(off + size_t(ntau) * N * es);
+  off = up(off + size_t(ntau) * N * es_q);
   L.off_u = off;
   off = up(off + size_t(dim) * N * es);
   L.off_qp = off;
-  off = up(off + size_t(5) * N * es);
+  off = up(off + size_t(5) * N * es_q);
   L.off_r = off;
-  off = up(off + size_t(5) * N * es);
+  off = up(off + size_t(5) * N * es_q);
   const dim3 grid = site_grid(g);
   L.nblocks = int64_t(grid.x) * grid.y * grid.z;
   L.off_partial = off;
@@ -189,9 +192,13 @@ static void ctx_mark(lc_ctx* c) {
 }  // namespace lc
 
 // ---------------------------------------------------------------------------
-// Dispatch helpers.
-template <int LAT, typename S, bool DEV>
+// Dispatch helpers.  Each is instantiated for (lattice, S = population and
+// collision type, DEV = deviation storage, QT = order-tensor type).
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
+  if constexpr (!std::is_same<S, QT>::value) {
+    return fail(LC_EUNSUPPORTED, "the staged variant has no mixed-precision form");
+  } else {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = ctx_coef<S>(c);
   char* scr = static_cast<char*>(c->b.scratch);
@@ -216,6 +223,7 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
     c->step++;
   }
   return hip_check(hipGetLastError(), "step launch");
+  }
 }
 
 
@@ -223,12 +231,14 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
 // populations) on stream st; u receives the force-corrected velocity.
 // rec_lb / rec_q, when not null, record rho and F / the predictor for
 // reverse-mode replay.  With mark, timing events bracket the two sweeps.
-template <int LAT, typename S, bool DEV>
-static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const S* q0, S* f1, S* q1, S* u,
-                            S* rec_lb, S* rec_q) {
-  using C = SplitCfg<LAT, S>;
+template <int LAT, typename S, bool DEV, typename QT = S>
+static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const QT* q0, S* f1, QT* q1, S* u,
+                            S* rec_lb, QT* rec_q) {
+  // tile shapes of the order-tensor type, whose LDS regions dominate
+  using C = SplitCfg<LAT, QT>;
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = ctx_coef<S>(c);
+  const Coef<QT> kq = ctx_coef<QT>(c);
   const int zc1 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_LB) : 1;
   const int zc2 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_Q) : 1;
   const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY,
@@ -237,101 +247,102 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
                 unsigned((c->g.nz + zc2 - 1) / zc2));
   if (mark) ctx_mark(c);
   if (c->coll == LC_COLL_MRT)
-    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, true>), g1, dim3(C::LB_TX, C::LB_TY), 0,
-                       st, q0, f0, f1, u, gd, k, zc1, rec_lb);
+    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, true, QT>), g1,
+                       dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
   else
-    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE>), g1, dim3(C::LB_TX, C::LB_TY), 0, st,
-                       q0, f0, f1, u, gd, k, zc1, rec_lb);
+    hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, false, QT>), g1,
+                       dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
   if (mark) ctx_mark(c);
-  hipLaunchKernelGGL((split_q<LAT, S, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1, gd,
-                     k, zc2, rec_q);
+  hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE, S>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1,
+                     gd, kq, zc2, rec_q);
   if (mark) ctx_mark(c);
 }
 
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps_split(lc_ctx* c, int64_t n) {
   S* u = reinterpret_cast<S*>(static_cast<char*>(c->b.scratch) + c->L.off_u);
   for (int64_t it = 0; it < n; it++) {
-    step_split_ptrs<LAT, S, DEV>(c, c->stream, true, static_cast<const S*>(c->b.f[c->parity]),
-                                 static_cast<const S*>(c->b.Q[c->parity]), static_cast<S*>(c->b.f[c->parity ^ 1]),
-                                 static_cast<S*>(c->b.Q[c->parity ^ 1]), u, nullptr, nullptr);
+    step_split_ptrs<LAT, S, DEV, QT>(c, c->stream, true, static_cast<const S*>(c->b.f[c->parity]),
+                                     static_cast<const QT*>(c->b.Q[c->parity]),
+                                     static_cast<S*>(c->b.f[c->parity ^ 1]), static_cast<QT*>(c->b.Q[c->parity ^ 1]),
+                                     u, nullptr, nullptr);
     c->parity ^= 1;
     c->step++;
   }
   return hip_check(hipGetLastError(), "step launch");
 }
 
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps(lc_ctx* c, int64_t n) {
-  if (c->variant == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV>(c, n);
-  return run_steps_staged<LAT, S, DEV>(c, n);
+  if (c->variant == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV, QT>(c, n);
+  return run_steps_staged<LAT, S, DEV, QT>(c, n);
 }
 
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status compute_tau(lc_ctx* c) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
-  const Coef<S> k = make_coef<S>(c->p);
-  S* tau = reinterpret_cast<S*>(static_cast<char*>(c->b.scratch) + c->L.off_tau);
-  hipLaunchKernelGGL((stage_tau<LAT, S>), site_grid(c->g), site_block(), 0, c->stream,
-                     static_cast<const S*>(c->b.Q[c->parity]), tau, gd, k);
+  const Coef<QT> k = make_coef<QT>(c->p);
+  QT* tau = reinterpret_cast<QT*>(static_cast<char*>(c->b.scratch) + c->L.off_tau);
+  hipLaunchKernelGGL((stage_tau<LAT, QT>), site_grid(c->g), site_block(), 0, c->stream,
+                     static_cast<const QT*>(c->b.Q[c->parity]), tau, gd, k);
   return hip_check(hipGetLastError(), "stress launch");
 }
 
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status do_load(lc_ctx* c, const double* f, const double* q) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
-  hipLaunchKernelGGL((load_state<LAT, S, DEV>), site_grid(c->g), site_block(), 0, c->stream, f, q,
-                     static_cast<S*>(c->b.f[0]), static_cast<S*>(c->b.Q[0]), gd);
+  hipLaunchKernelGGL((load_state<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream, f, q,
+                     static_cast<S*>(c->b.f[0]), static_cast<QT*>(c->b.Q[0]), gd);
   return hip_check(hipGetLastError(), "load launch");
 }
 
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status do_export(lc_ctx* c, int field, double* dst) {
   const int64_t N = c->L.N;
   const S* f = static_cast<const S*>(c->b.f[c->parity]);
-  const S* q = static_cast<const S*>(c->b.Q[c->parity]);
+  const QT* q = static_cast<const QT*>(c->b.Q[c->parity]);
   if (field == LC_FIELD_F || field == LC_FIELD_Q) {
     const GridDims gd{c->g.nx, c->g.ny, c->g.nz, N};
-    hipLaunchKernelGGL((export_fq<LAT, S, DEV>), site_grid(c->g), site_block(), 0, c->stream, f, q,
+    hipLaunchKernelGGL((export_fq<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream, f, q,
                        field == LC_FIELD_F ? dst : nullptr, field == LC_FIELD_Q ? dst : nullptr, gd);
     return hip_check(hipGetLastError(), "export launch");
   }
   int which = field == LC_FIELD_RHO ? 0 : field == LC_FIELD_U ? 1 : field == LC_FIELD_FORCE ? 2 : 3;
   if (which != 3) {
-    lc_status st = compute_tau<LAT, S, DEV>(c);
+    lc_status st = compute_tau<LAT, S, DEV, QT>(c);
     if (st) return st;
   }
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, N};
-  const S* tau = reinterpret_cast<const S*>(static_cast<char*>(c->b.scratch) + c->L.off_tau);
-  hipLaunchKernelGGL((export_derived<LAT, S, DEV>), site_grid(c->g), site_block(), 0, c->stream, f, q, tau, dst,
-                     which, gd);
+  const QT* tau = reinterpret_cast<const QT*>(static_cast<char*>(c->b.scratch) + c->L.off_tau);
+  hipLaunchKernelGGL((export_derived<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream, f, q, tau,
+                     dst, which, gd);
   return hip_check(hipGetLastError(), "export launch");
 }
 
 // Reductions of the current state into OBS_W doubles at res (device),
 // enqueued on the context stream.
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status do_observe_async(lc_ctx* c, uint32_t mask, int half_axis, double* res) {
   const int want_u = (mask & LC_OBS_UMAX) ? 1 : 0;
   if (want_u) {
-    lc_status st = compute_tau<LAT, S, DEV>(c);
+    lc_status st = compute_tau<LAT, S, DEV, QT>(c);
     if (st) return st;
   }
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   char* scr = static_cast<char*>(c->b.scratch);
-  const S* tau = reinterpret_cast<const S*>(scr + c->L.off_tau);
+  const QT* tau = reinterpret_cast<const QT*>(scr + c->L.off_tau);
   double* partial = reinterpret_cast<double*>(scr + c->L.off_partial);
-  hipLaunchKernelGGL((observe_partial<LAT, S, DEV>), site_grid(c->g), site_block(), 0, c->stream,
-                     static_cast<const S*>(c->b.f[c->parity]), static_cast<const S*>(c->b.Q[c->parity]), tau,
+  hipLaunchKernelGGL((observe_partial<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream,
+                     static_cast<const S*>(c->b.f[c->parity]), static_cast<const QT*>(c->b.Q[c->parity]), tau,
                      partial, gd, half_axis, want_u);
   hipLaunchKernelGGL(observe_final, dim3(1), dim3(256), 0, c->stream, partial, c->L.nblocks, res);
   return hip_check(hipGetLastError(), "observe launch");
 }
 
-template <int LAT, typename S, bool DEV>
+template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status do_observe(lc_ctx* c, uint32_t mask, int half_axis, double* host8) {
   double* res = reinterpret_cast<double*>(static_cast<char*>(c->b.scratch) + c->L.off_obs);
-  lc_status st = do_observe_async<LAT, S, DEV>(c, mask, half_axis, res);
+  lc_status st = do_observe_async<LAT, S, DEV, QT>(c, mask, half_axis, res);
   if (st) return st;
   st = hip_check(hipMemcpyAsync(host8, res, OBS_W * sizeof(double), hipMemcpyDeviceToHost, c->stream),
                  "observe copy");
@@ -357,12 +368,13 @@ static void fill_observables(const double* h, uint32_t mask, int half_axis, int6
   out->nonfinite = h[7] != 0.0 ? 1 : 0;
 }
 
-#define LC_DISPATCH(ctx, FN, ...)                                                   \
-  ((ctx)->g.lattice == LC_D2Q9                                                      \
-       ? ((ctx)->g.precision == LC_FP64 ? FN<0, double, false>(ctx, ##__VA_ARGS__)  \
-                                        : FN<0, float, true>(ctx, ##__VA_ARGS__))   \
-       : ((ctx)->g.precision == LC_FP64 ? FN<1, double, false>(ctx, ##__VA_ARGS__)  \
-                                        : FN<1, float, true>(ctx, ##__VA_ARGS__)))
+#define LC_DISPATCH_LAT(ctx, LAT, FN, ...)                                              \
+  ((ctx)->g.precision == LC_FP64    ? FN<LAT, double, false, double>(ctx, ##__VA_ARGS__) \
+   : (ctx)->g.precision == LC_MIXED ? FN<LAT, float, true, double>(ctx, ##__VA_ARGS__)   \
+                                    : FN<LAT, float, true, float>(ctx, ##__VA_ARGS__))
+#define LC_DISPATCH(ctx, FN, ...)                                                 \
+  ((ctx)->g.lattice == LC_D2Q9 ? LC_DISPATCH_LAT(ctx, 0, FN, ##__VA_ARGS__)       \
+                               : LC_DISPATCH_LAT(ctx, 1, FN, ##__VA_ARGS__))
 
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -461,6 +473,7 @@ lc_status lc_set_variant(lc_ctx* c, int32_t variant) {
     return LC_OK;
   }
   if (variant == LC_VARIANT_STAGED) {
+    if (c->g.precision == LC_MIXED) return fail(LC_EUNSUPPORTED, "the staged variant has no mixed-precision form");
     c->variant = LC_VARIANT_STAGED;
     return LC_OK;
   }
@@ -842,6 +855,7 @@ static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B
     lc_status st = check_grid(&grids[k]);
     if (st) return st;
     if (grids[k].lattice != LC_D2Q9) return fail(LC_EUNSUPPORTED, "the batched form runs D2Q9 grids");
+    if (grids[k].precision == LC_MIXED) return fail(LC_EUNSUPPORTED, "the batched form has no mixed-precision form");
     if (grids[k].precision != grids[0].precision) return fail(LC_EINVAL, "all grids must share one precision");
   }
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };

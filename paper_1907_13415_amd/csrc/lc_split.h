@@ -94,12 +94,22 @@ __device__ __forceinline__ void stencil_lds(const S (*m)[R2], const S (*zp)[R2],
   L = Sym<S>{lap[0], lap[1], lap[2], lap[3], lap[4]};
 }
 
+// The NC component arrays of an LDS region: the first NA of type A, the
+// rest of type B, read as A (the velocity of the mixed-precision form is
+// stored in single precision next to a double-precision Q).
+template <typename A, typename B, int NC, int NA>
+struct RegionSrc {
+  const A* a[NA];
+  const B* b[NC > NA ? NC - NA : 1];
+  __device__ __forceinline__ A operator()(int q, uint32_t s) const { return q < NA ? a[q][s] : A(b[q - NA][s]); }
+};
+
 // Load plane gz of NC component arrays (component stride N) into an LDS
 // plane over the R2 region of the block, with periodic wrap.
 // dst points at an LDS plane laid out [NC][R2].
-template <typename S, int TX, int TY, int NC>
-__device__ __forceinline__ void load_region(S* dst, const S* const* src, int x0, int y0, int gz,
-                                            const GridDims& g, int tid) {
+template <typename S, int TX, int TY, int NC, typename SRC>
+__device__ __forceinline__ void load_region(S* dst, const SRC& src, int x0, int y0, int gz, const GridDims& g,
+                                            int tid) {
   constexpr int W2 = TX + 4, R2 = (TX + 4) * (TY + 4), NT = TX * TY;
   const uint32_t plane = uint32_t(g.nx) * uint32_t(g.ny) * uint32_t(gz);
   for (int k = tid; k < R2; k += NT) {
@@ -107,7 +117,7 @@ __device__ __forceinline__ void load_region(S* dst, const S* const* src, int x0,
     const int gx = wrapi(x0 - 2 + i, g.nx), gy = wrapi(y0 - 2 + j, g.ny);
     const uint32_t s = plane + uint32_t(gx) + uint32_t(g.nx) * uint32_t(gy);
 #pragma unroll
-    for (int q = 0; q < NC; q++) dst[q * R2 + k] = src[q][s];
+    for (int q = 0; q < NC; q++) dst[q * R2 + k] = src(q, s);
   }
 }
 
@@ -121,9 +131,9 @@ struct RegionRegs {
   S v[P][NC];
 };
 
-template <typename S, int TX, int TY, int NC>
-__device__ __forceinline__ void fetch_region(RegionRegs<S, TX, TY, NC>& r, const S* const* src, int x0, int y0,
-                                             int gz, const GridDims& g, int tid) {
+template <typename S, int TX, int TY, int NC, typename SRC>
+__device__ __forceinline__ void fetch_region(RegionRegs<S, TX, TY, NC>& r, const SRC& src, int x0, int y0, int gz,
+                                             const GridDims& g, int tid) {
   using RR = RegionRegs<S, TX, TY, NC>;
   constexpr int W2 = TX + 4;
   const uint32_t plane = uint32_t(g.nx) * uint32_t(g.ny) * uint32_t(gz);
@@ -135,7 +145,7 @@ __device__ __forceinline__ void fetch_region(RegionRegs<S, TX, TY, NC>& r, const
       const int gx = wrapi(x0 - 2 + i, g.nx), gy = wrapi(y0 - 2 + j, g.ny);
       const uint32_t s = plane + uint32_t(gx) + uint32_t(g.nx) * uint32_t(gy);
 #pragma unroll
-      for (int q = 0; q < NC; q++) r.v[p][q] = src[q][s];
+      for (int q = 0; q < NC; q++) r.v[p][q] = src(q, s);
     }
   }
 }
@@ -167,11 +177,14 @@ __device__ __forceinline__ void store_out(S* p, S v) {
 
 // STREAM_F: read the populations with nontemporal loads (each is pulled by
 // one site only; measured to help where many grids share the caches, and to
-// hurt a single small grid that stays resident in them).
-template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false, bool STREAM_F = false>
-__device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S* __restrict__ fin,
+// hurt a single small grid that stays resident in them).  QT: the type of Q
+// and of the molecular field, stress and body force (S, or double in the
+// mixed-precision form, whose populations and collision stay in S); cq
+// holds the constants in that type.
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false, bool STREAM_F = false, typename QT = S>
+__device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const S* __restrict__ fin,
                                               S* __restrict__ fout, S* __restrict__ uout, const GridDims& g,
-                                              const Coef<S>& c, int zc, int bx, int by, int bz,
+                                              const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz,
                                               S* __restrict__ rec = nullptr) {
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
@@ -181,27 +194,27 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
   // tau_{a x} is needed at x +- 1 (rows 1..TY of the R1 region, all
   // columns) and tau_{a y} at y +- 1 (columns 1..TX, all rows)
   constexpr int NXA = T::W1 * TY, NYA = TX * T::H1;
-  __shared__ S sQ[NQP][5][T::R2];
-  __shared__ S sTx[NTP][DIM][NXA];
-  __shared__ S sTy[NTP][DIM][NYA];
+  __shared__ QT sQ[NQP][5][T::R2];
+  __shared__ QT sTx[NTP][DIM][NXA];
+  __shared__ QT sTy[NTP][DIM][NYA];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   const int x0 = bx * TX, y0 = by * TY;
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < g.nx && y < g.ny;
   const int64_t N = g.N;
-  const S* const qsrc[5] = {Qin, Qin + N, Qin + 2 * N, Qin + 3 * N, Qin + 4 * N};
+  const RegionSrc<QT, QT, 5, 5> qsrc{{Qin, Qin + N, Qin + 2 * N, Qin + 3 * N, Qin + 4 * N}, {nullptr}};
 
   // stress at the R1 point (i, j) of plane slot m with z neighbours zp/zm
-  auto tau_point = [&](int m, int zp, int zm, int i, int j, S (&t)[3][3]) {
-    Sym<S> q, Lq, d[3];
-    stencil_lds<S, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
-    const Sym<S> H = molecular_field(q, Lq, c);
-    stress(q, H, d, c, t);
+  auto tau_point = [&](int m, int zp, int zm, int i, int j, QT (&t)[3][3]) {
+    Sym<QT> q, Lq, d[3];
+    stencil_lds<QT, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
+    const Sym<QT> H = molecular_field(q, Lq, cq);
+    stress(q, H, d, cq, t);
   };
   // stress of the whole region of plane slot m into sT[ts]; returns the
   // owner's tau_{a z}
-  auto tau_plane = [&](int m, int zp, int zm, int ts, S (&tz)[3]) {
+  auto tau_plane = [&](int m, int zp, int zm, int ts, QT (&tz)[3]) {
     // pass 0: the owner's site; pass 1: a ring site (threads tid < RING).
     // Both passes run the same code, so every site's stress is rounded the
     // same way wherever it falls in a tile.
@@ -210,7 +223,7 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
       if (pass == 1 && tid >= T::RING) break;
       int i = tx + 1, j = ty + 1;
       if (pass == 1) T::ring(tid, i, j);
-      S t[3][3];
+      QT t[3][3];
       tau_point(m, zp, zm, i, j, t);
       const bool row_ring = pass == 1 && (j == 0 || j == TY + 1);
       const bool col_ring = pass == 1 && !row_ring;
@@ -270,19 +283,19 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
   };
   // lattice-Boltzmann update of the owner's site in plane z; writes the
   // post-collision populations at the site (pull form)
-  auto lb_site = [&](int z, int ts, const S (&tzp)[3], const S (&tzm)[3], S (&f)[L::q]) {
+  auto lb_site = [&](int z, int ts, const QT (&tzp)[3], const QT (&tzm)[3], S (&f)[L::q]) {
     if (!own) return;
     const int kx = (tx + 1) + T::W1 * ty, ky = tx + TX * (ty + 1);
     S F[3] = {S(0), S(0), S(0)};
 #pragma unroll
     for (int a = 0; a < DIM; a++) {
-      S acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + TX] - sTy[ts][a][ky - TX]);
+      QT acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + TX] - sTy[ts][a][ky - TX]);
       if constexpr (DIM == 3) acc += tzp[a] - tzm[a];
-      F[a] = S(0.5) * acc;
+      F[a] = S(QT(0.5) * acc);
     }
     const uint32_t s = uint32_t(x) + uint32_t(g.nx) * (uint32_t(y) + uint32_t(g.ny) * uint32_t(z));
-    S rho, u[3];
-    moments<LAT, S, DEV>(f, F, rho, u);
+    S rho, mass, u[3];
+    moments<LAT, S, DEV>(f, F, rho, u, mass);
 #pragma unroll
     for (int a = 0; a < DIM; a++) (uout + size_t(a) * size_t(N))[s] = u[a];
     if (rec) {  // record rho and F of this step (reverse-mode replay)
@@ -291,17 +304,18 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
       for (int a = 0; a < DIM; a++) (rec + size_t(a + 1) * size_t(N))[s] = F[a];
     }
     if constexpr (MRT)
-      collide_mrt<LAT, S, DEV>(f, rho, u, F, c);
+      collide_mrt<LAT, S, DEV>(f, rho, mass, u, F, c);
     else
-      collide_pairs<LAT, S, DEV>(f, rho, u, F, c);
+      collide_pairs<LAT, S, DEV>(f, rho, mass, u, F, c);
 #pragma unroll
     for (int i = 0; i < L::q; i++) store_out(&(fout + size_t(i) * size_t(N))[s], f[i]);
   };
 
   if constexpr (DIM == 2) {
-    load_region<S, TX, TY, 5>(&sQ[0][0][0], qsrc, x0, y0, 0, g, tid);
+    load_region<QT, TX, TY, 5>(&sQ[0][0][0], qsrc, x0, y0, 0, g, tid);
     __syncthreads();
-    S tz[3], f[L::q];
+    QT tz[3];
+    S f[L::q];
     fetch_f(0, f);
     tau_plane(0, 0, 0, 0, tz);
     __syncthreads();
@@ -312,15 +326,15 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
     auto slot = [](int p) { return (p + 3) % 3; };  // p >= -3
     // software pipeline: the halo region of plane p+2 and the populations of
     // plane p are in flight while plane p's stress and plane p-1's update run
-    RegionRegs<S, TX, TY, 5> rq;
-    load_region<S, TX, TY, 5>(&sQ[slot(zb - 2)][0][0], qsrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
-    load_region<S, TX, TY, 5>(&sQ[slot(zb - 1)][0][0], qsrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
-    fetch_region<S, TX, TY, 5>(rq, qsrc, x0, y0, wrapi(zb, g.nz), g, tid);
-    S tzA[3] = {S(0), S(0), S(0)}, tzB[3] = {S(0), S(0), S(0)}, tzC[3];
+    RegionRegs<QT, TX, TY, 5> rq;
+    load_region<QT, TX, TY, 5>(&sQ[slot(zb - 2)][0][0], qsrc, x0, y0, wrapi(zb - 2, g.nz), g, tid);
+    load_region<QT, TX, TY, 5>(&sQ[slot(zb - 1)][0][0], qsrc, x0, y0, wrapi(zb - 1, g.nz), g, tid);
+    fetch_region<QT, TX, TY, 5>(rq, qsrc, x0, y0, wrapi(zb, g.nz), g, tid);
+    QT tzA[3] = {QT(0), QT(0), QT(0)}, tzB[3] = {QT(0), QT(0), QT(0)}, tzC[3];
     S f[L::q];
     for (int p = zb - 1; p <= ze; p++) {
-      store_region<S, TX, TY, 5>(rq, &sQ[slot(p + 1)][0][0], tid);
-      if (p + 2 <= ze + 1) fetch_region<S, TX, TY, 5>(rq, qsrc, x0, y0, wrapi(p + 2, g.nz), g, tid);
+      store_region<QT, TX, TY, 5>(rq, &sQ[slot(p + 1)][0][0], tid);
+      if (p + 2 <= ze + 1) fetch_region<QT, TX, TY, 5>(rq, qsrc, x0, y0, wrapi(p + 2, g.nz), g, tid);
       __syncthreads();
       tau_plane(slot(p), slot(p + 1), slot(p - 1), p & 1, tzC);
       __syncthreads();
@@ -335,20 +349,22 @@ __device__ __forceinline__ void split_lb_body(const S* __restrict__ Qin, const S
   }
 }
 
-template <int LAT, typename S, bool DEV, int TX, int TY, int WPE, bool MRT = false>
+template <int LAT, typename S, bool DEV, int TX, int TY, int WPE, bool MRT = false, typename QT = S>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
-    split_lb(const S* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ uout,
-             GridDims g, Coef<S> c, int zc, S* __restrict__ rec) {
+    split_lb(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ uout,
+             GridDims g, Coef<S> c, Coef<QT> cq, int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  split_lb_body<LAT, S, DEV, TX, TY, MRT>(Qin, fin, fout, uout, g, c, zc, t % gridDim.x,
-                                          (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y), rec);
+  split_lb_body<LAT, S, DEV, TX, TY, MRT, false, QT>(Qin, fin, fout, uout, g, c, cq, zc, t % gridDim.x,
+                                                     (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y), rec);
 }
 
 // ---------------------------------------------------------------------------
-// Sweep 2: predictor on tile + ring (LDS), corrector on the tile.
-template <int LAT, typename S, int TX, int TY>
-__device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S* __restrict__ uin,
+// Sweep 2: predictor on tile + ring (LDS), corrector on the tile.  S is the
+// type of Q and of the arithmetic; SU that of the stored velocity (float in
+// the mixed-precision form, read as S).
+template <int LAT, typename S, int TX, int TY, typename SU = S>
+__device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const SU* __restrict__ uin,
                                              S* __restrict__ Qout, const GridDims& g, const Coef<S>& c, int zc,
                                              int bx, int by, int bz, S* __restrict__ rec = nullptr) {
   using L = Lattice<LAT>;
@@ -372,12 +388,11 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < g.nx && y < g.ny;
   const int64_t N = g.N;
-  const S* src[NC];
+  RegionSrc<S, SU, NC, 5> csrc;
 #pragma unroll
-  for (int q = 0; q < 5; q++) src[q] = Qin + q * N;
+  for (int q = 0; q < 5; q++) csrc.a[q] = Qin + q * N;
 #pragma unroll
-  for (int a = 0; a < DIM; a++) src[5 + a] = uin + a * N;
-  const S* const* csrc = src;
+  for (int a = 0; a < DIM; a++) csrc.b[a] = uin + a * N;
 
   // What the owner keeps from its predictor for its corrector: Q, R(Q) and
   // the flow terms (from u/2 and the undivided velocity differences; RAW
@@ -539,13 +554,13 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   }
 }
 
-template <int LAT, typename S, int TX, int TY, int WPE>
+template <int LAT, typename S, int TX, int TY, int WPE, typename SU = S>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
-    split_q(const S* __restrict__ Qin, const S* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
+    split_q(const S* __restrict__ Qin, const SU* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
             int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  split_q_body<LAT, S, TX, TY>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
+  split_q_body<LAT, S, TX, TY, SU>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
                                t / (gridDim.x * gridDim.y), rec);
 }
 

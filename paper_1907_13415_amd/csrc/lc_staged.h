@@ -74,8 +74,13 @@ __device__ __forceinline__ void body_force(const S* __restrict__ tau, int64_t N,
 
 // Density and force-corrected velocity (Eq. 9) from the populations at s.
 // With DEV the stored values are f_i - w_i (rho0 = 1); sum_i w_i c_i = 0.
+// mass receives the sum of the stored values: rho itself, or in DEV form
+// the deviation rho - 1 as summed, which the collision uses for the
+// density part of f_eq (forming it again as rho - 1 from the rounded rho
+// would lose the deviation's low bits at every site and step).
 template <int LAT, typename S, bool DEV>
-__device__ __forceinline__ void moments(const S (&f)[Lattice<LAT>::q], const S (&F)[3], S& rho, S (&u)[3]) {
+__device__ __forceinline__ void moments(const S (&f)[Lattice<LAT>::q], const S (&F)[3], S& rho, S (&u)[3],
+                                        S& mass) {
   using L = Lattice<LAT>;
   S m = S(0), jx = S(0), jy = S(0), jz = S(0);
 #pragma unroll
@@ -88,6 +93,7 @@ __device__ __forceinline__ void moments(const S (&f)[Lattice<LAT>::q], const S (
     if (L::cz(i) == 1) jz += f[i];
     if (L::cz(i) == -1) jz -= f[i];
   }
+  mass = m;
   rho = DEV ? S(1) + m : m;
   const S inv = S(1) / rho;
   u[0] = (jx + S(0.5) * F[0]) * inv;
@@ -95,16 +101,24 @@ __device__ __forceinline__ void moments(const S (&f)[Lattice<LAT>::q], const S (
   u[2] = L::dim == 3 ? (jz + S(0.5) * F[2]) * inv : S(0);
 }
 
+template <int LAT, typename S, bool DEV>
+__device__ __forceinline__ void moments(const S (&f)[Lattice<LAT>::q], const S (&F)[3], S& rho, S (&u)[3]) {
+  S mass;
+  moments<LAT, S, DEV>(f, F, rho, u, mass);
+}
+
 // BGK collision with the forcing term of Sec. 1.2.1, in place on f.
 // Equilibrium Eq. (8) with c_s^2 = 1/3; in DEV form the rest weight w_i is
 // removed from both f and f_eq, so only deviations are formed.
+// mass: the sum of the stored populations from moments (rho, or rho - 1 in
+// DEV form).
 template <int LAT, typename S, bool DEV>
-__device__ __forceinline__ void collide(S (&f)[Lattice<LAT>::q], S rho, const S (&u)[3], const S (&F)[3],
+__device__ __forceinline__ void collide(S (&f)[Lattice<LAT>::q], S rho, S mass, const S (&u)[3], const S (&F)[3],
                                         const Coef<S>& c) {
   using L = Lattice<LAT>;
   const S uu15 = S(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const S uF3 = S(3) * (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]);
-  const S drho = DEV ? rho - S(1) : rho;
+  const S drho = mass;
 #pragma unroll
   for (int i = 0; i < L::q; i++) {
     const S w = S(L::w(i));
@@ -122,12 +136,12 @@ __device__ __forceinline__ void collide(S (&f)[Lattice<LAT>::q], S rho, const S 
 // -c the even parts (in c) of f_eq and of the forcing term are shared and
 // the odd parts change sign.
 template <int LAT, typename S, bool DEV>
-__device__ __forceinline__ void collide_pairs(S (&f)[Lattice<LAT>::q], S rho, const S (&u)[3], const S (&F)[3],
-                                              const Coef<S>& c) {
+__device__ __forceinline__ void collide_pairs(S (&f)[Lattice<LAT>::q], S rho, S mass, const S (&u)[3],
+                                              const S (&F)[3], const Coef<S>& c) {
   using L = Lattice<LAT>;
   const S uu15 = S(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const S uF3 = S(3) * (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]);
-  const S base = DEV ? rho - S(1) : rho;
+  const S base = mass;
   const S keep = S(1) - c.omega;
   const S om_rho = c.omega * rho;
   // rest population: c = 0
@@ -161,13 +175,13 @@ __device__ __forceinline__ void collide_pairs(S (&f)[Lattice<LAT>::q], S rho, co
 // the bracket being the BGK result.  The ghost projections use the pair
 // sums h_i + h_-i for even ghosts and differences for odd ones.
 template <int LAT, typename S, bool DEV>
-__device__ __forceinline__ void collide_mrt(S (&f)[Lattice<LAT>::q], S rho, const S (&u)[3], const S (&F)[3],
-                                            const Coef<S>& c) {
+__device__ __forceinline__ void collide_mrt(S (&f)[Lattice<LAT>::q], S rho, S mass, const S (&u)[3],
+                                            const S (&F)[3], const Coef<S>& c) {
   using L = Lattice<LAT>;
   using Gh = Ghosts<LAT>;
   const S uu15 = S(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const S uF3 = S(3) * (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]);
-  const S base = DEV ? rho - S(1) : rho;
+  const S base = mass;
   S hs[L::q], hd[L::q];  // per pair representative i: h_i + h_-i, h_i - h_-i; hs[0] = h_0
   {
     const S w = S(L::w(0));
@@ -268,14 +282,14 @@ __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const
   body_force<LAT, S>(tau, N, s, nb, F);
   S f[L::q];
   gather_f<LAT, S>(fin, N, s, nb, f);
-  S rho, u[3];
-  moments<LAT, S, DEV>(f, F, rho, u);
+  S rho, mass, u[3];
+  moments<LAT, S, DEV>(f, F, rho, u, mass);
 #pragma unroll
   for (int a = 0; a < L::dim; a++) uout[a * N + s] = u[a];
   if constexpr (MRT)
-    collide_mrt<LAT, S, DEV>(f, rho, u, F, c);
+    collide_mrt<LAT, S, DEV>(f, rho, mass, u, F, c);
   else
-    collide<LAT, S, DEV>(f, rho, u, F, c);
+    collide<LAT, S, DEV>(f, rho, mass, u, F, c);
 #pragma unroll
   for (int i = 0; i < L::q; i++) fout[i * N + s] = f[i];
 }

@@ -98,6 +98,32 @@ def test_buffer_bytes():
     assert fb == 9 * 128 * 8 and qb == 5 * 128 * 8
 
 
+def test_mixed_precision_sizes_and_unsupported_paths():
+    """LC_MIXED: float populations and double Q (buffer sizes), no staged
+    variant, no reverse step and no batched form, refused on the host."""
+    from paper_1907_13415_amd import lc
+    fb, qb, sb = lc.lc_buffer_bytes(lc.make_grid(lc.LC_D3Q19, lc.LC_MIXED, 16, 8, 4))
+    assert fb == 19 * 512 * 4 and qb == 5 * 512 * 8
+    sb32 = lc.lc_buffer_bytes(lc.make_grid(lc.LC_D3Q19, lc.LC_FP32_DEV, 16, 8, 4))[2]
+    assert sb > sb32  # the stress scratch of the exports is double
+    params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
+    ctx = lc.lc_init(lc.make_grid(lc.LC_D2Q9, lc.LC_MIXED, 16, 16, 1), params, _fake_bufs(lc), 0)
+    try:
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_set_variant(ctx, lc.LC_VARIANT_STAGED)
+        assert e.value.code == lc.LC_EUNSUPPORTED
+        lc.lc_set_variant(ctx, lc.LC_VARIANT_SPLIT)
+        dummy = 1 << 40
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_step(ctx, dummy, dummy, dummy, dummy, dummy)
+        assert e.value.code == lc.LC_EUNSUPPORTED
+    finally:
+        lc.lc_free(ctx)
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_batch_layout([lc.make_grid(lc.LC_D2Q9, lc.LC_MIXED, 64, 64, 1)])
+    assert e.value.code == lc.LC_EUNSUPPORTED
+
+
 def test_host_side_validation_of_settings_and_reverse_calls():
     """Collision, variant and chunk settings and the reverse-sweep entry
     points reject bad arguments on the host, before any device work."""
