@@ -124,6 +124,18 @@ def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False):
     return dict(ms=ms_step, kernel_ms=[ms_k[0] / max(n_k[0], 1), ms_k[1] / max(n_k[1], 1)], S=S, obs=obs)
 
 
+def mixed_leg(torch, lc, w, args, dev, stream, N, S64):
+    """The slab in the mixed form (float populations, double Q): throughput,
+    roofline on its own compulsory bytes and |S - S64| after the same steps."""
+    rm = run_slab(torch, lc, w, "mixed", args.steps, args.warmup, dev, stream)
+    dS = float((rm["S"] - S64).abs().max().item())
+    b = 2 * (19 * 4 + 5 * 8)
+    return {"mlups": round(N / (rm["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(rm["ms"], 5),
+            "kernel_ms": [round(v, 5) for v in rm["kernel_ms"]], "bytes_per_site": b,
+            "roofline_frac": round(b * N / (sum(rm["kernel_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "max_abs_dS_vs_fp64": dS}
+
+
 def mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site):
     rm = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream, mrt=True)
     return {"mlups": round(N / (rm["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(rm["ms"], 5),
@@ -138,8 +150,9 @@ def s_nematic(g):
 
 
 def run_droplets(torch, lc, dev, stream, steps=20000):
-    """256^2 droplet at gamma = 2.7, 2.705, 2.71 for 20000 steps in FP64 and
-    FP32: max |u|, radius drift and the FP32 errors."""
+    """256^2 droplet at gamma = 2.7, 2.705, 2.71 for 20000 steps in FP64,
+    FP32 and the mixed form: max |u|, radius drift and the errors of the
+    other two forms against FP64."""
     from paper_1907_13415_amd import inputs
     recs = []
     for dg in (0.0, 0.005, 0.01):
@@ -147,7 +160,7 @@ def run_droplets(torch, lc, dev, stream, steps=20000):
         g = w.params[1]
         sn = s_nematic(g)
         res = {}
-        for prec in ("fp64", "fp32dev"):
+        for prec in ("fp64", "fp32dev", "mixed"):
             with torch.cuda.stream(stream):
                 s = lc.Solver("D2Q9", prec, w.shape, w.params, device=dev, stream=stream)
                 s.load(w.q5)
@@ -159,13 +172,17 @@ def run_droplets(torch, lc, dev, stream, steps=20000):
                 res[prec] = dict(umax=o["umax"], r0=r0, r1=math.sqrt(o["ssum"] / (math.pi * sn)),
                                  S=s.export(lc.LC_FIELD_S), mlups=w.shape[1] * w.shape[2] * steps / dt / 1e6)
                 del s
-        a, b = res["fp64"], res["fp32dev"]
+        a, b, m = res["fp64"], res["fp32dev"], res["mixed"]
         recs.append({"gamma": round(g, 4), "umax": a["umax"], "radius": [round(a["r0"], 4), round(a["r1"], 4)],
                      "radius_drift_per_step": (a["r1"] - a["r0"]) / steps,
                      "fp32_max_abs_dS": float(abs(a["S"] - b["S"]).max()),
                      "fp32_umax_rel_err": abs(b["umax"] - a["umax"]) / a["umax"],
                      "fp32_radius_err": abs(b["r1"] - a["r1"]),
-                     "mlups_fp64": round(a["mlups"], 1), "mlups_fp32": round(b["mlups"], 1)})
+                     "mixed_max_abs_dS": float(abs(a["S"] - m["S"]).max()),
+                     "mixed_umax_rel_err": abs(m["umax"] - a["umax"]) / a["umax"],
+                     "mixed_radius_err": abs(m["r1"] - a["r1"]),
+                     "mlups_fp64": round(a["mlups"], 1), "mlups_fp32": round(b["mlups"], 1),
+                     "mlups_mixed": round(m["mlups"], 1)})
     return dict(workload="droplet256_d2q9", steps=steps, runs=recs)
 
 
@@ -319,6 +336,7 @@ def main():
     r32 = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream)
     r64 = run_slab(torch, lc, w, "fp64", args.steps, args.warmup, dev, stream)
     dS = float((r32["S"] - r64["S"]).abs().max().item())
+    mixed = None if args.quick else mixed_leg(torch, lc, w, args, dev, stream, N, r64["S"])
     del r32["S"], r64["S"]
     torch.cuda.empty_cache()
 
@@ -363,6 +381,7 @@ def main():
         "fp32_steps_compared": args.warmup + args.steps,
     }
     if not args.quick:
+        out["mixed"] = mixed
         out["mrt_fp32"] = mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)
         out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)
         out["droplets"] = run_droplets(torch, lc, dev, stream)
