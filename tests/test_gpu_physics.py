@@ -227,32 +227,38 @@ def test_circle_with_mrt():
 
 
 def test_fp32_errors_on_interface_and_spurious_velocity():
-    """The FP32 deviation form against double precision (which matches the
-    oracle to 1e-12) on the observables of Sec. 2: S(x) and the front speed
-    of the flat interface at gamma = 2.701, and the spurious currents of the
-    circle near its static temperature.  These runs are long and slow: the
-    rates near a slow front are small differences of much larger float
-    terms (molecular field, Laplacian), and their rounding biases the front
-    by ~1% over 3e5 steps.  The 1e-5 bound on S holds for the short
-    workloads (the 1000-step flat interface, the 256^3 slab); here the
-    measured errors are bounded at about twice their observed size."""
+    """The FP32 deviation form and the mixed form against double precision
+    (which matches the oracle to 1e-12) on the observables of Sec. 2: S(x)
+    and the front speed of the flat interface at gamma = 2.701, and the
+    spurious currents of the circle near its static temperature.  These runs
+    are long and slow: the front position integrates every rounding of the
+    float Q update (front speed off by 4e-4 over 3e5 steps).  The 1e-5 bound
+    on S holds for the FP32 form on the short workloads (the 1000-step flat
+    interface, the 256^3 slab) and for the mixed form here; the FP32 errors
+    are bounded at about five times their observed size."""
     require_gpu()
     from paper_1907_13415_amd import lc
     nx, ny, g = 256, 4, 2.701
     res = {}
-    for prec in ("fp64", "fp32dev"):
+    for prec in ("fp64", "fp32dev", "mixed"):
         s = _solver(inputs.paper_flat(nx, ny), g, prec=prec)
         o0 = _run_to(s, 100000)
         o1 = _run_to(s, 300000)
         v = (o1["ssum_half"] - o0["ssum_half"]) / (s_nematic(g) * ny) / 200000
         res[prec] = (v, s.export(lc.LC_FIELD_S))
-    dv = abs(res["fp32dev"][0] - res["fp64"][0]) / abs(res["fp64"][0])
-    dS = float(np.abs(res["fp32dev"][1] - res["fp64"][1]).max())
+    err = {p: (abs(res[p][0] - res["fp64"][0]) / abs(res["fp64"][0]),
+               float(np.abs(res[p][1] - res["fp64"][1]).max())) for p in ("fp32dev", "mixed")}
     c64 = _circle(2.707628)
-    c32 = _circle(2.707628, prec="fp32dev")
-    du = abs(c32[2] - c64[2]) / c64[2]
-    dSc = float(np.abs(c32[3].export(lc.LC_FIELD_S) - c64[3].export(lc.LC_FIELD_S)).max())
-    _say("fp32 vs fp64: flat front speed rel err %.2e, max|dS| %.2e after 3e5 steps; circle max|u| %.4e vs "
-         "%.4e (rel err %.2e), max|dS| %.2e after 35000 steps" % (dv, dS, c32[2], c64[2], du, dSc))
-    assert dv < 2.5e-2 and dS < 2.5e-2  # observed 1.1e-2, 1.1e-2 (the front moved ~20 sites)
-    assert du < 4e-2 and dSc < 5e-4     # observed 1.9e-2, 2.1e-4
+    circ = {}
+    for p in ("fp32dev", "mixed"):
+        c = _circle(2.707628, prec=p)
+        circ[p] = (abs(c[2] - c64[2]) / c64[2], float(np.abs(c[3].export(lc.LC_FIELD_S) -
+                                                              c64[3].export(lc.LC_FIELD_S)).max()))
+    for p in ("fp32dev", "mixed"):
+        _say("%s vs fp64: flat front speed rel err %.2e, max|dS| %.2e after 3e5 steps; circle max|u| rel err "
+             "%.2e, max|dS| %.2e after 35000 steps" % (p, err[p][0], err[p][1], circ[p][0], circ[p][1]))
+    dv, dS = err["fp32dev"]
+    du, dSc = circ["fp32dev"]
+    assert dv < 2e-3 and dS < 2e-3   # observed 3.9e-4, 3.5e-4 (the front moved ~20 sites)
+    assert du < 3e-2 and dSc < 2e-4  # observed 6.5e-3, 4.1e-5
+    assert err["mixed"][1] < 1e-5 and circ["mixed"][1] < 1e-5
