@@ -49,6 +49,30 @@ def test_degenerate_grids_match_oracle(variant, lat, shape):
     assert ef < 1e-12 and eq < 1e-12
 
 
+@pytest.mark.parametrize("lat,shape", [(0, (1, 1, 9)), (0, (1, 7, 1)), (0, (1, 1, 1)), (0, (1, 2, 3)),
+                                       (1, (1, 5, 7)), (1, (6, 1, 5)), (1, (4, 5, 1)), (1, (1, 1, 1)),
+                                       (1, (2, 3, 2))])
+def test_degenerate_grids_mixed_form(lat, shape):
+    """The same degenerate grids in the mixed form (float populations,
+    double Q): float rounding only (f, and Q through the float velocity)."""
+    lc = _lc()
+    _say("degenerate mixed lat %d shape %s" % (lat, shape))
+    rng = np.random.default_rng(420 + lat)
+    q = 9 if lat == 0 else 19
+    q5 = inputs.random_q5(shape, rng, amp=0.12)
+    rel = inputs.random_rel(q, shape, rng, amp=2e-3)
+    p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
+    _, w = lc.lc_lattice_info(lat)
+    s = lc.Solver("D2Q9" if lat == 0 else "D3Q19", "mixed", shape, p)
+    s.load(q5, w.reshape((q, 1, 1, 1)) * (1.0 + rel))
+    s.step(7)
+    f_ref, q_ref = oracle.run(lat, oracle.rest_populations(lat, shape, rel=rel), q5, p, 7)
+    ef = rel_err(s.export(lc.LC_FIELD_F), f_ref, SCALES["f"])
+    eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
+    _say("  err f %.2e Q %.2e" % (ef, eq))
+    assert ef < 1e-7 and eq < 1e-7
+
+
 def test_zero_steps_leave_the_state():
     lc = _lc()
     shape = (3, 10, 12)
