@@ -146,6 +146,43 @@ def test_temperature_sweep_workload_full_size():
     assert all(o["nonfinite"] == 0 for o in obs)
 
 
+def test_sweep_front_speeds_fp32_against_fp64():
+    """The reported quantity of the sweep, the front speed of each grid
+    between steps 1000 and 5000, in the FP32 deviation form against double
+    precision: grids whose front moves (neither melted nor filled) agree to
+    a small fraction of their speed."""
+    lc = _lc()
+    ws = inputs.config3()
+    shapes = [w.shape[1:] for w in ws]
+    half = {}
+    for prec in ("fp64", "fp32dev"):
+        b = lc.BatchSolver(prec, shapes, [w.params for w in ws])
+        for k, w in enumerate(ws):
+            b.load(k, w.q5)
+        b.step(1000)
+        o0 = b.observe(half_axis=0)
+        b.step(4000)
+        o1 = b.observe(half_axis=0)
+        half[prec] = [(a["ssum_half"], c["ssum_half"], c["ssum"]) for a, c in zip(o0, o1)]
+        del b
+    worst, n = 0.0, 0
+    for w, h64, h32 in zip(ws, half["fp64"], half["fp32dev"]):
+        L, g = w.shape[2], w.params[1]
+        if g < 8.0 / 3.0:
+            continue
+        sn = 0.25 + 0.75 * (1.0 - 8.0 / (3.0 * g)) ** 0.5
+        if h64[2] < 1e-6 * L * L or h64[2] > 0.99 * sn * L * L:
+            continue  # melted or filled
+        v64 = (h64[1] - h64[0]) / (sn * L) / 4000
+        v32 = (h32[1] - h32[0]) / (sn * L) / 4000
+        if abs(v64) < 1e-7:
+            continue
+        worst = max(worst, abs(v32 - v64) / abs(v64))
+        n += 1
+    print("sweep front speeds, %d moving grids: worst FP32 relative error %.2e" % (n, worst), flush=True)
+    assert n >= 10 and worst < 1e-3  # measured 1.2e-5 over 24 moving grids
+
+
 def test_batch_tile_shapes_agree_bitwise():
     """Every site runs the same code wherever it falls in a tile, so every
     tile shape of either sweep gives identical results (seven pairings that
