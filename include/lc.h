@@ -26,8 +26,8 @@
  *    stores the deviation f_i - w_i*rho0 (rho0 = 1) and Q as float and does
  *    all per-site arithmetic in float; reductions accumulate in double.
  *    LC_MIXED stores f as LC_FP32_DEV does (float deviations, float moments
- *    and collision, float velocity) and Q as double, with the molecular
- *    field, stress, body force and Q update in double: the float rounding
+ *    and collision) and Q as double, with the molecular field, stress, body
+ *    force and Q update in double: the float rounding
  *    of the Q right-hand side, which moves slow interfaces in LC_FP32_DEV,
  *    is gone, at 2(q*4 + 5*8) bytes per site update.  LC_MIXED runs the
  *    split variant only (LC_VARIANT_STAGED: LC_EUNSUPPORTED) and single

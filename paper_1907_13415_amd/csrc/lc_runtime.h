@@ -15,8 +15,8 @@ namespace lc {
 struct Layout {
   int64_t N;
   int q;
-  size_t es;    // element size of f and u
-  size_t es_q;  // element size of Q and of the stress scratch
+  size_t es;    // element size of f
+  size_t es_q;  // element size of Q, u and the stress scratch
   size_t f_bytes, q_bytes;
   size_t off_tau, off_u, off_qp, off_r;
   size_t off_partial, off_obs;

@@ -106,7 +106,7 @@ Layout layout_of(const lc_grid& g) {
   L.off_tau = off;
   off = up(off + size_t(ntau) * N * es_q);
   L.off_u = off;
-  off = up(off + size_t(dim) * N * es);
+  off = up(off + size_t(dim) * N * es_q);
   L.off_qp = off;
   off = up(off + size_t(5) * N * es_q);
   L.off_r = off;
@@ -232,7 +232,7 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
 // rec_lb / rec_q, when not null, record rho and F / the predictor for
 // reverse-mode replay.  With mark, timing events bracket the two sweeps.
 template <int LAT, typename S, bool DEV, typename QT = S>
-static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const QT* q0, S* f1, QT* q1, S* u,
+static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const QT* q0, S* f1, QT* q1, QT* u,
                             S* rec_lb, QT* rec_q) {
   // tile shapes of the order-tensor type, whose LDS regions dominate
   using C = SplitCfg<LAT, QT>;
@@ -253,14 +253,14 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
     hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, false, QT>), g1,
                        dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
   if (mark) ctx_mark(c);
-  hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE, S>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1,
+  hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1,
                      gd, kq, zc2, rec_q);
   if (mark) ctx_mark(c);
 }
 
 template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps_split(lc_ctx* c, int64_t n) {
-  S* u = reinterpret_cast<S*>(static_cast<char*>(c->b.scratch) + c->L.off_u);
+  QT* u = reinterpret_cast<QT*>(static_cast<char*>(c->b.scratch) + c->L.off_u);
   for (int64_t it = 0; it < n; it++) {
     step_split_ptrs<LAT, S, DEV, QT>(c, c->stream, true, static_cast<const S*>(c->b.f[c->parity]),
                                      static_cast<const QT*>(c->b.Q[c->parity]),

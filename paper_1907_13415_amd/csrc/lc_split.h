@@ -179,11 +179,11 @@ __device__ __forceinline__ void store_out(S* p, S v) {
 // one site only; measured to help where many grids share the caches, and to
 // hurt a single small grid that stays resident in them).  QT: the type of Q
 // and of the molecular field, stress and body force (S, or double in the
-// mixed-precision form, whose populations and collision stay in S); cq
-// holds the constants in that type.
+// mixed-precision form, whose populations and collision stay in S), and of
+// the velocity handed to sweep 2; cq holds the constants in that type.
 template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false, bool STREAM_F = false, typename QT = S>
 __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const S* __restrict__ fin,
-                                              S* __restrict__ fout, S* __restrict__ uout, const GridDims& g,
+                                              S* __restrict__ fout, QT* __restrict__ uout, const GridDims& g,
                                               const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz,
                                               S* __restrict__ rec = nullptr) {
   using L = Lattice<LAT>;
@@ -297,7 +297,7 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
     S rho, mass, u[3];
     moments<LAT, S, DEV>(f, F, rho, u, mass);
 #pragma unroll
-    for (int a = 0; a < DIM; a++) (uout + size_t(a) * size_t(N))[s] = u[a];
+    for (int a = 0; a < DIM; a++) (uout + size_t(a) * size_t(N))[s] = QT(u[a]);
     if (rec) {  // record rho and F of this step (reverse-mode replay)
       rec[s] = rho;
 #pragma unroll
@@ -351,7 +351,7 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
 
 template <int LAT, typename S, bool DEV, int TX, int TY, int WPE, bool MRT = false, typename QT = S>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
-    split_lb(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, S* __restrict__ uout,
+    split_lb(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, QT* __restrict__ uout,
              GridDims g, Coef<S> c, Coef<QT> cq, int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
@@ -361,10 +361,9 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
 
 // ---------------------------------------------------------------------------
 // Sweep 2: predictor on tile + ring (LDS), corrector on the tile.  S is the
-// type of Q and of the arithmetic; SU that of the stored velocity (float in
-// the mixed-precision form, read as S).
-template <int LAT, typename S, int TX, int TY, typename SU = S>
-__device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const SU* __restrict__ uin,
+// type of Q, of the velocity and of the arithmetic.
+template <int LAT, typename S, int TX, int TY>
+__device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S* __restrict__ uin,
                                              S* __restrict__ Qout, const GridDims& g, const Coef<S>& c, int zc,
                                              int bx, int by, int bz, S* __restrict__ rec = nullptr) {
   using L = Lattice<LAT>;
@@ -388,7 +387,7 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const SU
   const int x = x0 + tx, y = y0 + ty;
   const bool own = x < g.nx && y < g.ny;
   const int64_t N = g.N;
-  RegionSrc<S, SU, NC, 5> csrc;
+  RegionSrc<S, S, NC, 5> csrc;
 #pragma unroll
   for (int q = 0; q < 5; q++) csrc.a[q] = Qin + q * N;
 #pragma unroll
@@ -554,13 +553,13 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const SU
   }
 }
 
-template <int LAT, typename S, int TX, int TY, int WPE, typename SU = S>
+template <int LAT, typename S, int TX, int TY, int WPE>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
-    split_q(const S* __restrict__ Qin, const SU* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
+    split_q(const S* __restrict__ Qin, const S* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
             int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  split_q_body<LAT, S, TX, TY, SU>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
+  split_q_body<LAT, S, TX, TY>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
                                t / (gridDim.x * gridDim.y), rec);
 }
 

@@ -54,7 +54,7 @@ def test_degenerate_grids_match_oracle(variant, lat, shape):
                                        (1, (2, 3, 2))])
 def test_degenerate_grids_mixed_form(lat, shape):
     """The same degenerate grids in the mixed form (float populations,
-    double Q): float rounding only (f, and Q through the float velocity)."""
+    double Q): float rounding only (f, and Q through the velocity of the float populations)."""
     lc = _lc()
     _say("degenerate mixed lat %d shape %s" % (lat, shape))
     rng = np.random.default_rng(420 + lat)

@@ -3,7 +3,7 @@ collided as float deviations, Q stored and updated in double.
 
 Against the double-precision oracle the populations carry float rounding
 (a few 1e-8 of the weight scale per step) and Q only what reaches it through
-the float velocity; the point of the form is S: within 1e-5 of double
+the velocity, a moment of the float populations; the point of the form is S: within 1e-5 of double
 precision on the 20000-step droplet, where the all-float form is not.
 """
 import sys
@@ -57,8 +57,9 @@ def test_mixed_against_oracle_random_state(lat, shape, mrt):
     eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
     _say("mixed %s %s: err f %.3e  Q %.3e" % (shape, "MRT" if mrt else "BGK", ef, eq))
     # float deviations: float roundings of the weight scale per step; Q is
-    # double and sees only the float velocity, whose relative rounding (6e-8)
-    # the rate carries (measured: f 4e-9, Q 1e-8 after 12 steps)
+    # double and sees only the velocity of the float populations, whose
+    # relative rounding (6e-8) the rate carries (measured: f 4e-9, Q 1e-8
+    # after 12 steps)
     assert ef < 1e-7 and eq < 1e-7
 
 
