@@ -31,22 +31,33 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 
 
+def compile_source(src: str, out: str) -> str:
+    """Compile an oracle source file into a shared library at `out` (gcc,
+    -O2, no floating-point contraction)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no floating-point contraction)."""
+    """Compile the oracle (see compile_source) if its library is missing or
+    older than the source."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 
 def _load():
+    """Load the oracle library: the one built from lc_oracle.c, or, when the
+    environment names one in LC_ORACLE_LIBRARY, that library (the tests that
+    plant mistakes in a copy of the source run the pins against it)."""
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("LC_ORACLE_LIBRARY") or build()
+        lib = ctypes.CDLL(path)
         lib.lco_lattice.argtypes = [ctypes.c_int, _ip, _dp]
         lib.lco_lattice.restype = ctypes.c_int
         lib.lco_run.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_long]

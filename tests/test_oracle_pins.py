@@ -271,6 +271,85 @@ def test_mass_and_momentum_conserved(lat, shape):
     np.testing.assert_allclose(j1, j0, rtol=0, atol=1e-14 * f.size)
 
 
+@pytest.mark.parametrize("lat,shape", [(D2, (1, 32, 32)), (D3, (32, 32, 32))])
+def test_density_pulse_carried_by_the_flow(lat, shape):
+    """Continuity: a density pulse in a uniform flow u0 (no body force, Q = 0
+    and xi = 0 so that Q stays zero) moves its centre of mass by exactly u0
+    per step, however the pulse spreads into sound waves, because the mass
+    flux is the momentum and the collision conserves it.  Populations must
+    stream along their own velocities for this."""
+    c, w = oracle.lattice(lat)
+    dim = 2 if lat == D2 else 3
+    nz, ny, nx = shape
+    u0 = np.array([0.04, -0.03, 0.02 if dim == 3 else 0.0])
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (x - nx / 2) ** 2 + (y - ny / 2) ** 2 + ((z - nz / 2) ** 2 if dim == 3 else 0)
+    drho = 1e-3 * np.exp(-r2 / 2.5 ** 2)
+    # first-order populations: density 1 + drho, momentum (1 + drho) u0
+    f = np.stack([wi * (1.0 + drho) * (1.0 + 3.0 * (ci @ u0)) for ci, wi in zip(c, w)])
+    q5 = np.zeros((5,) + shape)
+    p = (1.0, 2.5, 0.04, 0.3, 0.0, 0.8)
+    steps = 5
+    f1, q1 = oracle.run(lat, f, q5, p, steps)
+    assert np.abs(q1).max() == 0.0
+    # density deviations summed from population deviations, less the level
+    # of the undisturbed far corner (the uniform flow's own rounding)
+    wv = w.reshape((-1, 1, 1, 1))
+    d0, d1 = (f - wv).sum(axis=0), (f1 - wv).sum(axis=0)
+    d0, d1 = d0 - d0[0, 0, 0], d1 - d1[0, 0, 0]
+    m = d0.sum()
+    assert abs(d1.sum() - m) < 1e-10 * m
+    for a, coord in enumerate((x, y, z)[:dim]):
+        shift = (coord * d1).sum() / m - (coord * d0).sum() / m
+        assert abs(shift - steps * u0[a]) < 1e-8, (a, shift)
+
+
+@pytest.mark.parametrize("lat,shape", [(D2, (1, 9, 11)), (D3, (5, 6, 7))])
+def test_collision_adds_the_body_force_to_the_momentum(lat, shape):
+    """With the velocity of Eq. (9) (half the force added) and the forcing
+    term of Sec. 1.2.1, the collision changes the momentum at every site by
+    exactly F, for any tau: j* - j = F.  The post-collision populations are
+    read back from the streamed ones, f*_i(x) = f_i(x + c_i, n + 1)."""
+    rng = np.random.default_rng(16)
+    c, w = oracle.lattice(lat)
+    q5 = inputs.random_q5(shape, rng, amp=0.15)
+    f = oracle.rest_populations(lat, shape, rel=inputs.random_rel(len(w), shape, rng, amp=2e-3))
+    for tau in (0.8, 1.7):
+        p = (1.0, 2.7, 0.06, 0.3, 0.7, tau)
+        F = oracle.fields(lat, f, q5, p)["F"]
+        assert np.abs(F).max() > 1e-3
+        f1, _ = oracle.run(lat, f, q5, p, 1)
+        post = np.stack([np.roll(f1[i], shift=(-ci[2], -ci[1], -ci[0]), axis=(0, 1, 2)) for i, ci in enumerate(c)])
+        dj = np.tensordot(c.T, post - f, axes=1)
+        np.testing.assert_allclose(dj, F, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("lat,shape", [(D2, (1, 9, 11)), (D3, (5, 6, 7))])
+def test_step_force_is_the_pinned_stress_divergence(lat, shape):
+    """The body force the step applies is the stress divergence whose work
+    balances the free-energy rate (test_stress_work_balances_free_energy_rate)
+    and that sums by parts against the stress power of Eq. (6):
+    sum_x F.v = -sum_x tau_ab d_b v_a for any periodic v."""
+    rng = np.random.default_rng(17)
+    c, w = oracle.lattice(lat)
+    q5 = inputs.random_q5(shape, rng, amp=0.15)
+    f = oracle.rest_populations(lat, shape)
+    p = (1.0, 2.7, 0.06, 0.3, 0.7, 1.0)
+    fl = oracle.fields(lat, f, q5, p)
+    tau, F_ref, _ = oracle.stress(q5, p)
+    np.testing.assert_array_equal(fl["tau"], tau)
+    dim = 2 if lat == D2 else 3
+    np.testing.assert_allclose(fl["F"][:dim], F_ref[:dim], rtol=0, atol=1e-15)
+    assert np.abs(fl["F"][dim:]).max(initial=0.0) == 0.0
+    v = rng.normal(size=(3,) + shape)
+    v[dim:] = 0.0
+    dv = np.stack([np.stack([(np.roll(v[a], -1, axis=ax) - np.roll(v[a], 1, axis=ax)) / 2
+                             for ax in (2, 1, 0)]) for a in range(3)])  # dv[a][b] = d_b v_a
+    lhs = (fl["F"] * v).sum()
+    rhs = -(tau[:dim] * dv[:dim]).sum()
+    assert abs(lhs - rhs) < 1e-13 * np.abs(tau).max() * v.size
+
+
 # --------------------------------------------------- stress / co-rotation
 def _divfree_velocity(shape, rng, amp=1e-3):
     """u = (d_y psi, -d_x psi, 0) with central differences, so the discrete
