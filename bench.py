@@ -22,6 +22,7 @@ import json
 import math
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -249,7 +250,9 @@ def run_batch(torch, lc, stream, dev, steps, tiles=None, physics=True):
                 nonfinite=int(sum(o["nonfinite"] for o in obs)), sweep=sweep)
 
 
-def run_adjoint(torch):
+def run_adjoint(torch, repeats=5):
+    """Gradient of a 2000-step droplet loss: wall time of the forward and of
+    the backward (median of `repeats` runs after one warm-up)."""
     from paper_1907_13415_amd import adjoint, inputs
     w = inputs.config4()
     dev = torch.device("cuda:0")
@@ -266,20 +269,24 @@ def run_adjoint(torch):
         return ((torch.sqrt((1.5 * qq).clamp_min(1e-300)) - st) ** 2).sum()
 
     loss(adjoint.solve(q0, tg, tK, tG, **cfg)).backward()  # warm-up
-    q0.grad = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L = loss(adjoint.solve(q0, tg, tK, tG, **cfg))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    L.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    fwd, bwd = t1 - t0, t2 - t1
+    fwds, bwds = [], []
+    for _ in range(repeats):
+        q0.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = loss(adjoint.solve(q0, tg, tK, tG, **cfg))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwds.append(t1 - t0)
+        bwds.append(t2 - t1)
+    fwd, bwd = statistics.median(fwds), statistics.median(bwds)
     # the backward replays every segment once (a forward pass with recording,
     # on a second stream, overlapping the reverse steps of the next segment)
     return dict(workload="adjoint_droplet256_d2q9_fp64", steps=w.steps, checkpoint_every=100,
-                forward_s=round(fwd, 4), backward_s=round(bwd, 4),
+                repeats=repeats, forward_s=round(fwd, 4), backward_s=round(bwd, 4),
                 backward_over_forward=round(bwd / fwd, 2), includes_replay=True)
 
 
