@@ -150,10 +150,17 @@ def s_nematic(g):
     return 0.25 + 0.75 * math.sqrt(1.0 - 8.0 / (3.0 * g)) if g >= 8.0 / 3.0 else 0.0
 
 
+def _vel_err(x, ref):
+    """Relative error of the mean interface velocity (radius drift over the
+    run) of one form against the double-precision run."""
+    return abs((x["r1"] - x["r0"]) - (ref["r1"] - ref["r0"])) / abs(ref["r1"] - ref["r0"])
+
+
 def run_droplets(torch, lc, dev, stream, steps=20000):
     """256^2 droplet at gamma = 2.7, 2.705, 2.71 for 20000 steps in FP64,
     FP32 and the mixed form: max |u|, radius drift and the errors of the
-    other two forms against FP64."""
+    other two forms against FP64 (S, interface position and velocity, max
+    |u|)."""
     from paper_1907_13415_amd import inputs
     recs = []
     for dg in (0.0, 0.005, 0.01):
@@ -179,9 +186,11 @@ def run_droplets(torch, lc, dev, stream, steps=20000):
                      "fp32_max_abs_dS": float(abs(a["S"] - b["S"]).max()),
                      "fp32_umax_rel_err": abs(b["umax"] - a["umax"]) / a["umax"],
                      "fp32_radius_err": abs(b["r1"] - a["r1"]),
+                     "fp32_interface_velocity_rel_err": _vel_err(b, a),
                      "mixed_max_abs_dS": float(abs(a["S"] - m["S"]).max()),
                      "mixed_umax_rel_err": abs(m["umax"] - a["umax"]) / a["umax"],
                      "mixed_radius_err": abs(m["r1"] - a["r1"]),
+                     "mixed_interface_velocity_rel_err": _vel_err(m, a),
                      "mlups_fp64": round(a["mlups"], 1), "mlups_fp32": round(b["mlups"], 1),
                      "mlups_mixed": round(m["mlups"], 1)})
     return dict(workload="droplet256_d2q9", steps=steps, runs=recs)
