@@ -65,31 +65,46 @@ def measured_traffic(key="hbm_bytes_per_step"):
     return float(t.group(1))
 
 
-def cpu_baseline(n=128, min_s=10.0, max_steps=200):
-    """The oracle (as written) on the host cores: the slab recipe at n^3,
-    one step at a time until about min_s seconds have passed."""
+def _oracle_rate(oracle, inputs, n, min_s, max_steps):
+    """Steps of the oracle on the slab recipe at n^3, one at a time until
+    about min_s seconds have passed: (MLUPS, steps, seconds)."""
     import numpy as np
-    import oracle
-    from paper_1907_13415_amd import inputs
     rng = np.random.default_rng(2)
     q5, _ = inputs.slab_3d(n, rng)
     f = oracle.rest_populations(oracle.D3Q19, q5.shape[1:])
-    oracle.build()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     steps = 0
     t = time.perf_counter()
     while steps < max_steps and time.perf_counter() - t < min_s:
         f, q5 = oracle.run(oracle.D3Q19, f, q5, inputs.WORKLOAD_PARAMS, 1)
         steps += 1
     dt = time.perf_counter() - t
+    return n ** 3 * steps / dt / 1e6, steps, dt
+
+
+def cpu_baseline(n=128, min_s=10.0, max_steps=200):
+    """The oracle (as written) on the host cores: the slab recipe at n^3,
+    one step at a time until about min_s seconds have passed; then the same
+    on one thread at 64^3 for about a third of that."""
+    import oracle
+    from paper_1907_13415_amd import inputs
+    oracle.build()
+    threads = oracle.threads()
+    rate, steps, dt = _oracle_rate(oracle, inputs, n, min_s, max_steps)
+    oracle.set_threads(1)
+    try:
+        rate1, steps1, dt1 = _oracle_rate(oracle, inputs, 64, min_s / 3, max_steps)
+    finally:
+        oracle.set_threads(threads)
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    return dict(value=round(n ** 3 * steps / dt / 1e6, 4), unit="MLUPS", cores=threads, kind="oracle",
+    return dict(value=round(rate, 4), unit="MLUPS", cores=threads, kind="oracle",
                 sample="oracle FP64 on the D3Q19 slab recipe at %d^3, %d steps in %.1f s" % (n, steps, dt),
+                single_thread=dict(value=round(rate1, 4), unit="MLUPS", cores=1,
+                                   sample="the same at 64^3, %d steps in %.1f s" % (steps1, dt1)),
                 cpu_model=model, nproc=os.cpu_count())
 
 

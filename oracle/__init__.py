@@ -78,6 +78,10 @@ def _load():
         lib.lco_source.restype = None
         lib.lco_observe.argtypes = [ctypes.c_int] * 4 + [_dp, _dp, _dp, ctypes.c_int, _dp]
         lib.lco_observe.restype = ctypes.c_int
+        lib.lco_set_threads.argtypes = [ctypes.c_int]
+        lib.lco_set_threads.restype = None
+        lib.lco_threads.argtypes = []
+        lib.lco_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -93,6 +97,16 @@ def _params(p):
     a = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
     assert a.shape == (6,), "params = (A0, gamma, K, Gamma, xi, tau)"
     return a
+
+
+def threads() -> int:
+    """Host threads the oracle's whole-grid loops use."""
+    return int(_load().lco_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the host threads of the oracle's whole-grid loops (n >= 1)."""
+    _load().lco_set_threads(int(n))
 
 
 def lattice(lat: int):

@@ -36,6 +36,7 @@
  *     which is how a two-dimensional grid is handled.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
@@ -84,6 +85,13 @@ static int get_lattice(int lattice, lattice_t *L) {
   }
   return -1;
 }
+
+/* Host threads of the whole-grid loops (OpenMP): set, and query. */
+void lco_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
+int lco_threads(void) { return omp_get_max_threads(); }
 
 /* Velocity table export: c[i*3 + a], w[i].  Returns q, or -1. */
 int lco_lattice(int lattice, int *c, double *w) {
