@@ -32,6 +32,8 @@ int lattice_q(int lattice);
 lc_status check_grid(const lc_grid* g);
 lc_status check_params(const lc_params* p);
 Layout layout_of(const lc_grid& g);
+// one site per thread: blocks of SITE_TX x SITE_TY sites, one z plane each
+constexpr int SITE_TX = 64, SITE_TY = 4;
 dim3 site_block();
 dim3 site_grid(const lc_grid& g);
 

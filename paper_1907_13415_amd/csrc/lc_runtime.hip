@@ -126,7 +126,7 @@ Layout layout_of(const lc_grid& g) {
   return L;
 }
 
-dim3 site_block() { return dim3(64, 4, 1); }
+dim3 site_block() { return dim3(SITE_TX, SITE_TY, 1); }
 
 dim3 site_grid(const lc_grid& g) {
   const dim3 b = site_block();
@@ -597,9 +597,12 @@ static void vjp_reverse(lc_ctx* c, const VjpFields& v, const double* q_n, double
   const GridDims gd{c->g.nx, c->g.ny, 1, c->L.N};
   const Coef<double> k = make_coef<double>(c->p);
   const dim3 grid = site_grid(c->g), block = site_block();
-  hipLaunchKernelGGL(vjp_r1, grid, block, 0, c->stream, adj_f, adj_q, fold ? 1 : 0, v, gd, k);
-  hipLaunchKernelGGL(vjp_r2, grid, block, 0, c->stream, q_n, adj_q, v, gd, k);
-  hipLaunchKernelGGL(vjp_r34, grid, block, 0, c->stream, adj_f, q_n, v, gd, k);
+  // two threads per site (two halves of each block along z), same tiles
+  static_assert(REV_TX == SITE_TX && REV_TY == SITE_TY, "reverse tiles are the site tiles");
+  const dim3 block2(REV_TX, REV_TY, 2);
+  hipLaunchKernelGGL(vjp_r1, grid, block2, 0, c->stream, adj_f, adj_q, fold ? 1 : 0, v, gd, k);
+  hipLaunchKernelGGL(vjp_r2, grid, block2, 0, c->stream, q_n, adj_q, v, gd, k);
+  hipLaunchKernelGGL(vjp_r34, grid, block2, 0, c->stream, adj_f, q_n, v, gd, k);
   if (finish) hipLaunchKernelGGL(vjp_r5, grid, block, 0, c->stream, adj_q, v, gd);
 }
 

@@ -11,7 +11,12 @@
 //   force-corrected velocity -> body force and stress -> molecular field.
 // Stencil adjoints are applied as gathers: the compact Laplacian is
 // self-adjoint and the central difference D has adjoint -D on a periodic
-// grid.  Each kernel handles one site per thread.
+// grid.  The three kernels of a reverse step run two threads per site: the
+// block is REV_TX x REV_TY sites by two halves (threadIdx.z), each half
+// takes an independent part of the site's work, and the halves meet in LDS
+// (a grid of 65 536 sites would otherwise give one wave per SIMD).  The
+// results do not depend on the split: launched with blockDim.z == 1, one
+// thread takes both halves in turn and computes the same values bit for bit.
 #pragma once
 
 #include "lc_adjoint.h"
@@ -29,11 +34,14 @@ struct VjpFields {
 };
 constexpr int VJP_COMPS = 4 + 1 + 2 + 2 + 5 + 5 + 9 + 5 + 5 + 10 + 2 + 4 + 1 + 2 + 5 + 5 + 10 + 5;
 
+// sites per block of the reverse kernels (the block has two halves)
+constexpr int REV_TX = 64, REV_TY = 4, REV_SITES = REV_TX * REV_TY;
+
 __device__ __forceinline__ void block_reduce3(double (&v)[3], double* __restrict__ dst) {
   __shared__ double part[16][3];
-  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
   const int lane = tid & 63, wid = tid >> 6;
-  const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+  const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) >> 6;
 #pragma unroll
   for (int k = 0; k < 3; k++) v[k] = wave_sum(v[k]);
   if (lane == 0) {
@@ -133,12 +141,19 @@ __global__ void __launch_bounds__(256) vjp_fwd_moments(const double* __restrict_
 // adjoint is first assembled from the previous reverse step's qb, lb, dqb
 // (the Laplacian and gradient gathers of vjp_r5) and stored to adj_q; the
 // gathered fields are only read here, and adj_q only at the own site.
-__global__ void __launch_bounds__(256) vjp_r1(const double* __restrict__ adj_f, double* __restrict__ adj_q, int fold,
-                                              VjpFields v, GridDims g, Coef<double> c) {
+// Half 0 takes the collision, half 1 the corrector; the velocity adjoint is
+// the sum of the two (collision first).
+__global__ void __launch_bounds__(2 * REV_SITES) vjp_r1(const double* __restrict__ adj_f, double* __restrict__ adj_q,
+                                                        int fold, VjpFields v, GridDims g, Coef<double> c) {
   using L = Lattice<0>;
   LC_SITE_2D
+  const int half = threadIdx.z;
+  const bool one = blockDim.z == 1;  // one thread takes both halves
+  const int slot = threadIdx.x + blockDim.x * threadIdx.y;
+  __shared__ double s_ub[2][REV_SITES];
   double d[3] = {0.0, 0.0, 0.0};
-  if (in) {
+  double ub[3] = {0.0, 0.0, 0.0};
+  if (in && (one || half == 0)) {
     double fbs[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
@@ -152,8 +167,17 @@ __global__ void __launch_bounds__(256) vjp_r1(const double* __restrict__ adj_f, 
     const double rho = v.rho[s];
     const double u3[3] = {v.u[s], v.u[N + s], 0.0};
     const double F3[3] = {v.F[s], v.F[N + s], 0.0};
-    double fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, rhob = 0.0, ub[3] = {0, 0, 0}, Fb[3] = {0, 0, 0};
-    collide_vjp<0, double>(fbs, rho, u3, F3, c, fb, rhob, ub, Fb);
+    double fb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, rhob = 0.0, ubc[3] = {0, 0, 0}, Fb[3] = {0, 0, 0};
+    collide_vjp<0, double>(fbs, rho, u3, F3, c, fb, rhob, ubc, Fb);
+#pragma unroll
+    for (int i = 0; i < 9; i++) v.fbar[i * N + s] = fb[i];
+    v.rhob[s] = rhob;
+    v.fb[s] = Fb[0];
+    v.fb[N + s] = Fb[1];
+    s_ub[0][slot] = ubc[0];
+    s_ub[1][slot] = ubc[1];
+  }
+  if (in && (one || half == 1)) {
     Sym<double> aq;
     if (fold) {
       aq = load_sym(v.qb, N, s);
@@ -175,43 +199,62 @@ __global__ void __launch_bounds__(256) vjp_r1(const double* __restrict__ adj_f, 
     double Gb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     be_rate_vjp(P, HP, dP, uc, G, Rpb, c, Pb, HPb, dPb, ub, Gb, d);
     molecular_field_vjp(P, LP, HPb, c, Pb, LPb, d);
-#pragma unroll
-    for (int i = 0; i < 9; i++) v.fbar[i * N + s] = fb[i];
     put5(v.qpb, N, s, Pb);
     put5(v.lpb, N, s, LPb);
     put5(v.dqpb, N, s, dPb[0]);
     put5(v.dqpb + 5 * N, N, s, dPb[1]);
-    v.ub[s] = ub[0];
-    v.ub[N + s] = ub[1];
     v.gb[s] = Gb[0][0];
     v.gb[N + s] = Gb[0][1];
     v.gb[2 * N + s] = Gb[1][0];
     v.gb[3 * N + s] = Gb[1][1];
-    v.rhob[s] = rhob;
-    v.fb[s] = Fb[0];
-    v.fb[N + s] = Fb[1];
+  }
+  __syncthreads();
+  if (in && (one || half == 1)) {
+    // ub holds the corrector's part alone (it started from zero and was
+    // decremented once per component), so adding it to the collision's part
+    // rounds as decrementing that part would
+    v.ub[s] = s_ub[0][slot] + ub[0];
+    v.ub[N + s] = s_ub[1][slot] + ub[1];
   }
   block_reduce3(d, v.part + (0 * v.nblocks + blk) * 3);
 }
 
-// predictor-rate adjoint at Q
-__global__ void __launch_bounds__(256) vjp_r2(const double* __restrict__ Q, const double* __restrict__ adj_q,
-                                              VjpFields v, GridDims g, Coef<double> c) {
+// predictor-rate adjoint at Q.  Half 0 gathers the predictor's adjoint and
+// forms the rate adjoint; half 1 evaluates the stencil, H and the velocity
+// gradient at Q, then takes the rate adjoint from LDS.
+__global__ void __launch_bounds__(2 * REV_SITES) vjp_r2(const double* __restrict__ Q, const double* __restrict__ adj_q,
+                                                        VjpFields v, GridDims g, Coef<double> c) {
   LC_SITE_2D
+  const int half = threadIdx.z;
+  const bool one = blockDim.z == 1;  // one thread takes both halves
+  const int slot = threadIdx.x + blockDim.x * threadIdx.y;
+  __shared__ double s_rb[5][REV_SITES], s_qb[5][REV_SITES];
   double d[3] = {0.0, 0.0, 0.0};
-  if (in) {
+  Sym<double> q, dq[3], Lq, H;
+  double G[3][3], uc[3];
+  if (in && (one || half == 0)) {
     Sym<double> qpb = load_sym(v.qpb, N, s);
     add_to(qpb, lap2(v.lpb, N, s, nb));
     add_to(qpb, negdiv2(v.dqpb, N, s, nb));
     const Sym<double> aq = load_sym(adj_q, N, s);
-    const Sym<double> Rb{0.5 * aq.xx + qpb.xx, 0.5 * aq.xy + qpb.xy, 0.5 * aq.xz + qpb.xz, 0.5 * aq.yy + qpb.yy,
-                         0.5 * aq.yz + qpb.yz};
-    Sym<double> qb{aq.xx + qpb.xx, aq.xy + qpb.xy, aq.xz + qpb.xz, aq.yy + qpb.yy, aq.yz + qpb.yz};
-    Sym<double> q, dq[3], Lq;
+    const double rb[5] = {0.5 * aq.xx + qpb.xx, 0.5 * aq.xy + qpb.xy, 0.5 * aq.xz + qpb.xz, 0.5 * aq.yy + qpb.yy,
+                          0.5 * aq.yz + qpb.yz};
+    const double qb[5] = {aq.xx + qpb.xx, aq.xy + qpb.xy, aq.xz + qpb.xz, aq.yy + qpb.yy, aq.yz + qpb.yz};
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+      s_rb[k][slot] = rb[k];
+      s_qb[k][slot] = qb[k];
+    }
+  }
+  if (in && (one || half == 1)) {
     stencil<double, 2>(Q, N, s, nb, q, dq, Lq);
-    const Sym<double> H = molecular_field(q, Lq, c);
-    double G[3][3], uc[3];
+    H = molecular_field(q, Lq, c);
     velgrad2(v.u, N, s, nb, G, uc);
+  }
+  __syncthreads();
+  if (in && (one || half == 1)) {
+    const Sym<double> Rb{s_rb[0][slot], s_rb[1][slot], s_rb[2][slot], s_rb[3][slot], s_rb[4][slot]};
+    Sym<double> qb{s_qb[0][slot], s_qb[1][slot], s_qb[2][slot], s_qb[3][slot], s_qb[4][slot]};
     Sym<double> Hb = sym_zero<double>();
     Sym<double> dqb[3] = {sym_zero<double>(), sym_zero<double>(), sym_zero<double>()};
     double ub[3] = {v.ub[s], v.ub[N + s], 0.0};
@@ -259,12 +302,20 @@ __device__ __forceinline__ void force_adj(const VjpFields& v, const GridDims& g,
 // Velocity-gradient and moment adjoints (writes the population adjoint),
 // then body-force, stress and molecular-field adjoints at Q.  The force
 // adjoint of the four neighbours is recomputed here rather than stored.
-__global__ void __launch_bounds__(256) vjp_r34(double* __restrict__ adj_f, const double* __restrict__ Q, VjpFields v,
-                                               GridDims g, Coef<double> c) {
+// Half 0 takes the population adjoint and the stress adjoint (from the four
+// neighbours' force adjoints); half 1 evaluates the stencil and H at Q and
+// then the stress and molecular-field adjoints.
+__global__ void __launch_bounds__(2 * REV_SITES) vjp_r34(double* __restrict__ adj_f, const double* __restrict__ Q,
+                                                         VjpFields v, GridDims g, Coef<double> c) {
   using L = Lattice<0>;
   LC_SITE_2D
+  const int half = threadIdx.z;
+  const bool one = blockDim.z == 1;  // one thread takes both halves
+  const int slot = threadIdx.x + blockDim.x * threadIdx.y;
+  __shared__ double s_tb[4][REV_SITES];
   double d[3] = {0.0, 0.0, 0.0};
-  if (in) {
+  Sym<double> q, dq[3], Lq, H;
+  if (in && (one || half == 0)) {
     {
       double ub[2], jb[2];
       momentum_adj(v, N, s, nb, ub, jb);
@@ -279,15 +330,24 @@ __global__ void __launch_bounds__(256) vjp_r34(double* __restrict__ adj_f, const
     force_adj(v, g, xm, y, fxm);
     force_adj(v, g, x, yp, fyp);
     force_adj(v, g, x, ym, fym);
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      s_tb[2 * a + 0][slot] = -0.5 * (fxp[a] - fxm[a]);
+      s_tb[2 * a + 1][slot] = -0.5 * (fyp[a] - fym[a]);
+    }
+  }
+  if (in && (one || half == 1)) {
+    stencil<double, 2>(Q, N, s, nb, q, dq, Lq);
+    H = molecular_field(q, Lq, c);
+  }
+  __syncthreads();
+  if (in && (one || half == 1)) {
     double tb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int a = 0; a < 2; a++) {
-      tb[a][0] = -0.5 * (fxp[a] - fxm[a]);
-      tb[a][1] = -0.5 * (fyp[a] - fym[a]);
+      tb[a][0] = s_tb[2 * a + 0][slot];
+      tb[a][1] = s_tb[2 * a + 1][slot];
     }
-    Sym<double> q, dq[3], Lq;
-    stencil<double, 2>(Q, N, s, nb, q, dq, Lq);
-    const Sym<double> H = molecular_field(q, Lq, c);
     Sym<double> qb = load_sym(v.qb, N, s);
     Sym<double> Hb = load_sym(v.hb, N, s);
     Sym<double> dqb[3] = {load_sym(v.dqb, N, s), load_sym(v.dqb + 5 * N, N, s), sym_zero<double>()};
