@@ -11,6 +11,8 @@
    Richardson extrapolation of differences at h = 1e-4 and 2e-4.
 3. The overlapped reverse sweep (lc_vjp_backward) against one
    lc_vjp_segment call per segment, on uneven segments.
+4. A dot-product test of lc_vjp_step against central differences of the GPU
+   forward step itself.
 """
 import sys
 import time
@@ -67,6 +69,60 @@ def test_vjp_step_matches_autograd_twin():
     ep = np.abs(dp.cpu().numpy() - want) / np.maximum(np.abs(want), 1e-12)
     _say("vjp vs twin: f %.2e Q %.2e params %s" % (ef, eq, ep))
     assert ef < 1e-12 and eq < 1e-12 and ep.max() < 1e-11
+
+
+def test_vjp_is_the_transpose_of_the_gpu_step():
+    """Dot-product test against the GPU forward itself (independent of the
+    CPU twin): for random state directions w and adjoint seeds v,
+    <v, J w> from central differences of one GPU step equals <J^T v, w> from
+    lc_vjp_step; the three parameter derivatives likewise against central
+    differences in gamma, K and Gamma."""
+    require_gpu()
+    from paper_1907_13415_amd import lc
+    shape = (1, 17, 11)
+    rng = np.random.default_rng(31)
+    p = (0.9, 2.72, 0.06, 0.31, 0.7, 1.3)
+    q5 = inputs.random_q5(shape, rng, amp=0.12)
+    f = oracle.rest_populations(oracle.D2Q9, shape, rel=inputs.random_rel(9, shape, rng, amp=2e-3))
+    wf = rng.normal(size=f.shape) * 1e-2
+    wq = rng.normal(size=q5.shape) * 1e-1
+    af = rng.normal(size=f.shape)
+    aq = rng.normal(size=q5.shape)
+
+    def fwd(ff, qq, pp):
+        s = lc.Solver("D2Q9", "fp64", shape, pp)
+        s.load(qq, ff)
+        s.step(1)
+        return s.export(lc.LC_FIELD_F), s.export(lc.LC_FIELD_Q)
+
+    def seed_dot(a, b):
+        return float((af * (a[0] - b[0])).sum() + (aq * (a[1] - b[1])).sum())
+
+    h = 1e-6
+    jw = seed_dot(fwd(f + h * wf, q5 + h * wq, p), fwd(f - h * wf, q5 - h * wq, p)) / (2 * h)
+    s = lc.Solver("D2Q9", "fp64", shape, p)
+    dev = s.device
+    fd = torch.tensor(f, device=dev)
+    qd = torch.tensor(q5, device=dev)
+    afd = torch.tensor(af, device=dev).contiguous()
+    aqd = torch.tensor(aq, device=dev).contiguous()
+    dp = torch.zeros(3, dtype=torch.float64, device=dev)
+    with torch.cuda.stream(s.stream):
+        lc.lc_vjp_step(s.ctx, fd.data_ptr(), qd.data_ptr(), afd.data_ptr(), aqd.data_ptr(), dp.data_ptr())
+    s.stream.synchronize()
+    vjw = float((afd.cpu().numpy() * wf).sum() + (aqd.cpu().numpy() * wq).sum())
+    _say("dot-product test: <v, J w> %.12e  <J^T v, w> %.12e" % (jw, vjw))
+    assert abs(jw - vjw) <= 1e-7 * abs(vjw)
+    dps = dp.cpu().numpy()
+    for k, idx in enumerate((1, 2, 3)):  # gamma, K, Gamma
+        step = h * abs(p[idx])
+        pp = list(p)
+        pp[idx] = p[idx] + step
+        pm = list(p)
+        pm[idx] = p[idx] - step
+        d = seed_dot(fwd(f, q5, tuple(pp)), fwd(f, q5, tuple(pm))) / (2 * step)
+        _say("  parameter %d: differences %.10e  reverse %.10e" % (idx, d, dps[k]))
+        assert abs(d - dps[k]) <= 1e-6 * abs(d)
 
 
 def _loss_fn(s_target):
