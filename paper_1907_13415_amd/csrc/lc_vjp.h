@@ -14,9 +14,9 @@
 // grid.  The three kernels of a reverse step run two threads per site: the
 // block is REV_TX x REV_TY sites by two halves (threadIdx.z), each half
 // takes an independent part of the site's work, and the halves meet in LDS
-// (a grid of 65 536 sites would otherwise give one wave per SIMD).  The
-// results do not depend on the split: launched with blockDim.z == 1, one
-// thread takes both halves in turn and computes the same values bit for bit.
+// (a grid of 65 536 sites would otherwise give one wave per SIMD).  Each
+// value is formed by the same operations in the same order as with one
+// thread per site, so the split does not change any result.
 #pragma once
 
 #include "lc_adjoint.h"
@@ -148,12 +148,11 @@ __global__ void __launch_bounds__(2 * REV_SITES) vjp_r1(const double* __restrict
   using L = Lattice<0>;
   LC_SITE_2D
   const int half = threadIdx.z;
-  const bool one = blockDim.z == 1;  // one thread takes both halves
   const int slot = threadIdx.x + blockDim.x * threadIdx.y;
   __shared__ double s_ub[2][REV_SITES];
   double d[3] = {0.0, 0.0, 0.0};
   double ub[3] = {0.0, 0.0, 0.0};
-  if (in && (one || half == 0)) {
+  if (in && half == 0) {
     double fbs[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
@@ -177,7 +176,7 @@ __global__ void __launch_bounds__(2 * REV_SITES) vjp_r1(const double* __restrict
     s_ub[0][slot] = ubc[0];
     s_ub[1][slot] = ubc[1];
   }
-  if (in && (one || half == 1)) {
+  if (in && half == 1) {
     Sym<double> aq;
     if (fold) {
       aq = load_sym(v.qb, N, s);
@@ -209,7 +208,7 @@ __global__ void __launch_bounds__(2 * REV_SITES) vjp_r1(const double* __restrict
     v.gb[3 * N + s] = Gb[1][1];
   }
   __syncthreads();
-  if (in && (one || half == 1)) {
+  if (in && half == 1) {
     // ub holds the corrector's part alone (it started from zero and was
     // decremented once per component), so adding it to the collision's part
     // rounds as decrementing that part would
@@ -226,13 +225,12 @@ __global__ void __launch_bounds__(2 * REV_SITES) vjp_r2(const double* __restrict
                                                         VjpFields v, GridDims g, Coef<double> c) {
   LC_SITE_2D
   const int half = threadIdx.z;
-  const bool one = blockDim.z == 1;  // one thread takes both halves
   const int slot = threadIdx.x + blockDim.x * threadIdx.y;
   __shared__ double s_rb[5][REV_SITES], s_qb[5][REV_SITES];
   double d[3] = {0.0, 0.0, 0.0};
   Sym<double> q, dq[3], Lq, H;
   double G[3][3], uc[3];
-  if (in && (one || half == 0)) {
+  if (in && half == 0) {
     Sym<double> qpb = load_sym(v.qpb, N, s);
     add_to(qpb, lap2(v.lpb, N, s, nb));
     add_to(qpb, negdiv2(v.dqpb, N, s, nb));
@@ -246,13 +244,13 @@ __global__ void __launch_bounds__(2 * REV_SITES) vjp_r2(const double* __restrict
       s_qb[k][slot] = qb[k];
     }
   }
-  if (in && (one || half == 1)) {
+  if (in && half == 1) {
     stencil<double, 2>(Q, N, s, nb, q, dq, Lq);
     H = molecular_field(q, Lq, c);
     velgrad2(v.u, N, s, nb, G, uc);
   }
   __syncthreads();
-  if (in && (one || half == 1)) {
+  if (in && half == 1) {
     const Sym<double> Rb{s_rb[0][slot], s_rb[1][slot], s_rb[2][slot], s_rb[3][slot], s_rb[4][slot]};
     Sym<double> qb{s_qb[0][slot], s_qb[1][slot], s_qb[2][slot], s_qb[3][slot], s_qb[4][slot]};
     Sym<double> Hb = sym_zero<double>();
@@ -310,12 +308,11 @@ __global__ void __launch_bounds__(2 * REV_SITES) vjp_r34(double* __restrict__ ad
   using L = Lattice<0>;
   LC_SITE_2D
   const int half = threadIdx.z;
-  const bool one = blockDim.z == 1;  // one thread takes both halves
   const int slot = threadIdx.x + blockDim.x * threadIdx.y;
   __shared__ double s_tb[4][REV_SITES];
   double d[3] = {0.0, 0.0, 0.0};
   Sym<double> q, dq[3], Lq, H;
-  if (in && (one || half == 0)) {
+  if (in && half == 0) {
     {
       double ub[2], jb[2];
       momentum_adj(v, N, s, nb, ub, jb);
@@ -336,12 +333,12 @@ __global__ void __launch_bounds__(2 * REV_SITES) vjp_r34(double* __restrict__ ad
       s_tb[2 * a + 1][slot] = -0.5 * (fyp[a] - fym[a]);
     }
   }
-  if (in && (one || half == 1)) {
+  if (in && half == 1) {
     stencil<double, 2>(Q, N, s, nb, q, dq, Lq);
     H = molecular_field(q, Lq, c);
   }
   __syncthreads();
-  if (in && (one || half == 1)) {
+  if (in && half == 1) {
     double tb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
     for (int a = 0; a < 2; a++) {
