@@ -235,7 +235,7 @@ template <int LAT, typename S, bool DEV, typename QT = S>
 static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const QT* q0, S* f1, QT* q1, QT* u,
                             S* rec_lb, QT* rec_q) {
   // tile shapes of the order-tensor type, whose LDS regions dominate
-  using C = SplitCfg<LAT, QT>;
+  using C = SplitCfg<LAT, QT, S>;
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = ctx_coef<S>(c);
   const Coef<QT> kq = ctx_coef<QT>(c);

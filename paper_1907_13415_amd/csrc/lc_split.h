@@ -564,15 +564,18 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
 }
 
 // Tile shapes of the two-sweep kernels (measured on 256^3; LDS per block at
-// most 77 KB, so at least two blocks fit a CU).
-template <int LAT, typename S>
+// most 77 KB, so at least two blocks fit a CU).  S: the type of Q, which
+// sets the LDS footprint of the tiles; SF: that of the populations (float
+// in the mixed-precision form).
+template <int LAT, typename S, typename SF = S>
 struct SplitCfg {
   static constexpr bool d3 = Lattice<LAT>::dim == 3;
   static constexpr bool f64 = sizeof(S) == 8;
   static constexpr int LB_TX = (d3 && !f64) ? 64 : 32, LB_TY = 8;
   static constexpr int Q_TX = (d3 && f64) ? 16 : 32, Q_TY = 8;
-  // planes per block along z in each sweep
-  static constexpr int ZC_LB = f64 ? 16 : 32, ZC_Q = 128;
+  // planes per block along z in each sweep (float populations: 32, which
+  // the mixed form measured 2% faster than 16)
+  static constexpr int ZC_LB = sizeof(SF) == 8 ? 16 : 32, ZC_Q = 128;
   // waves per SIMD the register allocation is held to (the single-precision
   // 3D stress sweep runs two blocks of eight waves per CU)
   static constexpr int LB_WPE = (d3 && !f64) ? 4 : 1;
