@@ -693,8 +693,10 @@ int lco_observe(int lattice, int nx, int ny, int nz, const double *p,
   const size_t N = g.N;
   double *u3 = malloc(3 * N * sizeof(double));
   if (!u3) return -2;
-  if (lco_fields(lattice, nx, ny, nz, p, f, q5, NULL, u3, NULL, NULL, NULL, NULL, NULL, NULL, NULL))
+  if (lco_fields(lattice, nx, ny, nz, p, f, q5, NULL, u3, NULL, NULL, NULL, NULL, NULL, NULL, NULL)) {
+    free(u3);
     return -1;
+  }
   double mass = 0.0, mom[3] = {0, 0, 0}, umax = 0.0, ssum = 0.0, shalf = 0.0;
   int n_ax = half_axis == 0 ? nx : (half_axis == 1 ? ny : nz);
   long c0 = n_ax / 2, c1 = n_ax / 2 + n_ax / 2;

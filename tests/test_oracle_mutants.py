@@ -73,6 +73,14 @@ MUTANTS = {
                         "site(g, x - L->c[i][0], y - L->c[i][1], z - L->c[i][2])"),
     # lattice: one axis weight of D3Q19 wrong
     "d3q19_weight": ("1.0 / 3.0,  1.0 / 18.0,", "1.0 / 3.0,  1.0 / 36.0,"),
+    # a13 observables: end planes of the half domain weighted 1, the half
+    # domain shifted by one plane, the momentum summed with the wrong sign,
+    # max |u| taken of |u|^2, S without its factor 3/2
+    "observe_end_weight": ("shalf += 0.5 * S;", "shalf += S;"),
+    "observe_half_start": ("long c0 = n_ax / 2, c1", "long c0 = n_ax / 2 - 1, c1"),
+    "observe_mom_sign": ("mom[a] += L.c[i][a] * fi;", "mom[a] -= L.c[i][a] * fi;"),
+    "observe_umax_squared": ("if (sqrt(uu) > umax) umax = sqrt(uu);", "if (uu > umax) umax = uu;"),
+    "observe_s_factor": ("double S = sqrt(1.5 * qq);", "double S = sqrt(qq);"),
     # MRT: forcing relaxed with (1 - s) instead of (1 - s/2)
     "mrt_forcing": ("(1.0 - op->s[k] / 2.0) * mgk", "(1.0 - op->s[k]) * mgk"),
 }

@@ -550,3 +550,113 @@ def test_interface_velocity_sign_and_relaxational_estimate():
     for dg, (v, est) in res.items():
         assert np.sign(v) == np.sign(dg)
         assert abs(v / est - 1) < 0.25, res
+
+
+# ------------------------------------------------------------- observables
+# The reductions the GPU observables are compared with: mass and lattice
+# momentum (sums of the populations and their first moment), max |u| of the
+# force-corrected velocity of Eq. (9), and the sum of S = sqrt(1.5 Q:Q) over
+# the grid and over the half domain whose trapezoid integral locates the
+# right-hand interface of a centred slab (Sec. 2.1).  Each is fixed here by
+# a closed form that does not come from the oracle.
+OBS_CASES = [(D2, (1, 10, 12), 0), (D2, (1, 9, 11), 1), (D2, (1, 7, 12), 0), (D3, (6, 5, 7), 2),
+             (D3, (7, 6, 5), 0), (D3, (5, 8, 6), 1)]
+
+
+def _random_director(shape, rng):
+    g = rng.standard_normal((3,) + tuple(shape))
+    return g / np.sqrt((g * g).sum(axis=0))
+
+
+@pytest.mark.parametrize("lat,shape,axis", OBS_CASES)
+def test_observe_sums_of_a_uniform_scalar_order(lat, shape, axis):
+    """Q = S0 (n n - I/3) with a random director at every site has S = S0
+    everywhere: the sum over the grid is N S0, and the trapezoid over the
+    half domain, an interval of floor(n/2) lattice spacings along the axis,
+    is S0 floor(n/2) N / n."""
+    rng = np.random.default_rng(40)
+    S0 = 0.27
+    q5 = inputs.uniaxial_q5(np.full(shape, S0), _random_director(shape, rng))
+    f = oracle.rest_populations(lat, shape)
+    o = oracle.observe(lat, f, q5, BASE, half_axis=axis)
+    N = int(np.prod(shape))
+    n = shape[::-1][axis]
+    assert abs(o["ssum"] - N * S0) < 1e-13 * N
+    assert abs(o["ssum_half"] - S0 * (n // 2) * N / n) < 1e-13 * N
+
+
+@pytest.mark.parametrize("lat,shape,axis", OBS_CASES)
+def test_observe_half_sum_integrates_a_linear_profile_exactly(lat, shape, axis):
+    """S = a + b (k - c) on the planes c <= k <= c + h (c = floor(n/2),
+    h = floor(n/2), the last plane taken modulo n) and S = 5 elsewhere: the
+    trapezoid rule integrates the linear part exactly, so the half-domain sum
+    is (N/n)(a h + b h^2/2), and the large values outside must not enter."""
+    rng = np.random.default_rng(41)
+    nz, ny, nx = shape
+    n = (nx, ny, nz)[axis]
+    c = h = n // 2
+    a, b = 0.1, 0.013
+    prof = np.full(n, 5.0)
+    for j in range(h + 1):
+        prof[(c + j) % n] = a + b * j
+    coord = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")[2 - axis]
+    S = prof[coord]
+    q5 = inputs.uniaxial_q5(S, _random_director(shape, rng))
+    f = oracle.rest_populations(lat, shape)
+    o = oracle.observe(lat, f, q5, BASE, half_axis=axis)
+    N = int(np.prod(shape))
+    assert abs(o["ssum_half"] - (N / n) * (a * h + b * h * h / 2.0)) < 1e-12 * N
+    assert abs(o["ssum"] - (N / n) * prof.sum()) < 1e-12 * N
+
+
+def _hermite_equilibrium(lat, rho, u):
+    """Second-order equilibrium (Eq. 8) from the lattice table; its zeroth
+    and first moments are rho and rho u for any velocity set with the
+    isotropy of test_lattice_quadrature."""
+    c, w = oracle.lattice(lat)
+    cu = np.tensordot(c.astype(float), u, axes=1)
+    uu = (u * u).sum(axis=0)
+    return np.stack([w[i] * rho * (1 + 3 * cu[i] + 4.5 * cu[i] ** 2 - 1.5 * uu) for i in range(len(w))])
+
+
+@pytest.mark.parametrize("lat,shape", [(D2, (1, 10, 12)), (D3, (5, 6, 7))])
+def test_observe_mass_momentum_and_speed_without_force(lat, shape):
+    """Q = 0 gives F = 0, so u = sum c f / rho.  For populations at the
+    equilibrium of a density rho(x) and velocity u(x): mass = sum rho,
+    momentum = sum rho u, max |u| = the largest |u(x)|, which sits at one
+    chosen site."""
+    rng = np.random.default_rng(42)
+    dim = 2 if lat == D2 else 3
+    rho = 1.0 + 0.05 * rng.standard_normal(shape)
+    u = np.zeros((3,) + shape)
+    u[:dim] = 0.02 * rng.uniform(-1, 1, (dim,) + shape)
+    u[:, 0, 1, 2] = [0.05, -0.04, 0.03 if dim == 3 else 0.0]
+    f = _hermite_equilibrium(lat, rho, u)
+    q5 = np.zeros((5,) + shape)
+    o = oracle.observe(lat, f, q5, BASE)
+    N = int(np.prod(shape))
+    assert abs(o["mass"] - rho.sum()) < 1e-13 * N
+    np.testing.assert_allclose(o["mom"], (rho * u).reshape(3, -1).sum(axis=1), rtol=0, atol=1e-14 * N)
+    assert abs(o["umax"] - np.linalg.norm(u[:, 0, 1, 2])) < 1e-15
+    assert o["ssum"] == 0.0 and o["ssum_half"] == 0.0
+
+
+@pytest.mark.parametrize("lat,shape", [(D2, (1, 10, 12)), (D3, (5, 6, 7))])
+def test_observe_speed_is_half_the_force_over_density(lat, shape):
+    """Populations at rest (f_i = w_i rho, zero lattice momentum) under an
+    order-tensor field: Eq. (9) leaves u = F/(2 rho), so max |u| is the
+    largest |F|/(2 rho), with F the stress divergence pinned by
+    test_step_force_is_the_pinned_stress_divergence; the lattice momentum
+    stays zero."""
+    rng = np.random.default_rng(43)
+    _, w = oracle.lattice(lat)
+    rho = 1.0 + 0.1 * rng.uniform(-1, 1, shape)
+    f = np.stack([wi * rho for wi in w])
+    q5 = inputs.random_q5(shape, rng, amp=0.15)
+    F = oracle.fields(lat, f, q5, BASE)["F"]
+    speed = np.sqrt((F * F).sum(axis=0)) / (2 * rho)
+    assert speed.max() > 1e-3
+    o = oracle.observe(lat, f, q5, BASE)
+    assert abs(o["umax"] - speed.max()) < 1e-15
+    np.testing.assert_allclose(o["mom"], 0.0, rtol=0, atol=1e-15 * f.size)
+    assert abs(o["mass"] - rho.sum()) < 1e-13 * rho.size
