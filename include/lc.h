@@ -36,8 +36,9 @@
  *    whatever the storage precision.
  *  - Memory ownership.  The caller allocates and owns every device buffer
  *    (for example as torch tensors); the library never allocates device
- *    memory.  It keeps only a small host-side context and, for the batched
- *    form, a captured HIP graph.  All work is enqueued on the HIP stream
+ *    memory.  It keeps only a small host-side context, for the batched
+ *    form a captured HIP graph, and one fixed device array per GPU that
+ *    serves lc_step_static.  All work is enqueued on the HIP stream
  *    given at init; only calls documented as synchronising wait for it.
  *  - Errors.  Every call returns an lc_status; on failure lc_last_error()
  *    gives a message (thread-local).  Asynchronous device errors surface at
@@ -287,6 +288,30 @@ int64_t lc_step_count(const lc_ctx *ctx);
 
 /* Destroy the context (device buffers stay with the caller). */
 lc_status lc_free(lc_ctx *ctx);
+
+/* Size of the library's own device scratch used by lc_step_static. */
+#define LC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lc_step
+ * without a context or a scratch buffer.  Advances n >= 0 steps of the
+ * split sweeps with BGK collision (exactly what lc_step computes on a
+ * context with the default variant, collision and chunk) of the state held
+ * in storage form in f[parity], Q[parity] (as a context over the same four
+ * buffers holds it after lc_load_state or lc_step; f[0], f[1], Q[0], Q[1]
+ * device pointers, 256-byte aligned, sized by lc_buffer_bytes), alternating
+ * between the two buffers of each pair: the result is in f[parity ^ (n & 1)],
+ * Q[parity ^ (n & 1)].  The velocity between the sweeps goes to a fixed
+ * device array of LC_STATIC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends; grids whose velocity field (2 or
+ * 3 components of N values, 4 bytes each in LC_FP32_DEV, else 8) exceeds
+ * it are rejected with LC_ENOMEM.  The call allocates nothing, host or
+ * device.  All calls on one GPU share that array: calls that overlap on one
+ * GPU (other streams, other threads) race and must be ordered by the
+ * caller.  Asynchronous on `stream` (a hipStream_t, NULL = default).
+ * LC_EINVAL for a bad grid, parameters, parity, n or buffer. */
+lc_status lc_step_static(const lc_grid *grid, const lc_params *params, void *const *f, void *const *Q,
+                         int32_t parity, int64_t n, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent two-dimensional D2Q9 grids of their own

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -834,6 +835,111 @@ lc_status lc_free(lc_ctx* c) {
   if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
   return LC_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Steps without allocation: the velocity between the two sweeps lives in a
+// fixed device array of the library instead of a caller-provided scratch.
+// ===========================================================================
+namespace lc {
+
+// One copy per GPU, held from the library's load until the process ends.
+static __device__ __align__(256) unsigned char scratch[LC_STATIC_SCRATCH_BYTES];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+static std::mutex g_static_mu;
+static void* g_static_ptr[STATIC_MAX_DEVICES];
+
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device with that device current.  The array's name is a host-side
+// stand-in and never reaches a kernel; only this address does.
+static lc_status static_scratch_ptr(void** out) {
+  int dev = -1;
+  lc_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st) return st;
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(LC_EDEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (st) return st;
+    if (!p) return fail(LC_EDEVICE, "static scratch has no device address");
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return LC_OK;
+}
+
+// Bytes of the velocity the split sweeps hand from the first to the second.
+static size_t static_velocity_bytes(const lc_grid& g) {
+  const size_t N = size_t(g.nx) * g.ny * g.nz;
+  const size_t dim = g.lattice == LC_D2Q9 ? 2 : 3;
+  return dim * N * (g.precision == LC_FP32_DEV ? 4 : 8);
+}
+
+template <int LAT, typename S, bool DEV, typename QT = S>
+static lc_status run_static(lc_ctx* c, void* u_dev, int64_t n) {
+  QT* u = static_cast<QT*>(u_dev);
+  for (int64_t it = 0; it < n; it++) {
+    step_split_ptrs<LAT, S, DEV, QT>(c, c->stream, false, static_cast<const S*>(c->b.f[c->parity]),
+                                     static_cast<const QT*>(c->b.Q[c->parity]),
+                                     static_cast<S*>(c->b.f[c->parity ^ 1]), static_cast<QT*>(c->b.Q[c->parity ^ 1]),
+                                     u, nullptr, nullptr);
+    c->parity ^= 1;
+  }
+  return hip_check(hipGetLastError(), "step launch");
+}
+
+}  // namespace lc
+
+extern "C" {
+
+lc_status lc_step_static(const lc_grid* grid, const lc_params* params, void* const* f, void* const* Q,
+                         int32_t parity, int64_t n, void* stream) {
+  clear_error();
+  lc_status st = check_grid(grid);
+  if (st) return st;
+  st = check_params(params);
+  if (st) return st;
+  if (!f || !Q) return fail(LC_EINVAL, "buffer array is NULL");
+  if (parity != 0 && parity != 1) return fail(LC_EINVAL, "parity must be 0 or 1");
+  if (n < 0) return fail(LC_EINVAL, "n must be >= 0");
+  const void* ptrs[4] = {f[0], f[1], Q[0], Q[1]};
+  for (const void* p : ptrs) {
+    if (!p) return fail(LC_EINVAL, "a buffer pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(p) & 255) return fail(LC_EINVAL, "buffers must be 256-byte aligned");
+  }
+  const size_t need = static_velocity_bytes(*grid);
+  if (need > LC_STATIC_SCRATCH_BYTES)
+    return fail(LC_ENOMEM, "grid needs %zu bytes of velocity scratch; the static buffer holds %zu", need,
+                size_t(LC_STATIC_SCRATCH_BYTES));
+  void* u = nullptr;
+  st = static_scratch_ptr(&u);
+  if (st) return st;
+  if (n == 0) return LC_OK;
+  // a context on the stack (no allocation): the split sweeps with BGK and
+  // the default chunks, over the caller's buffers
+  lc_ctx c;
+  c.g = *grid;
+  c.p = *params;
+  c.b.f[0] = f[0];
+  c.b.f[1] = f[1];
+  c.b.Q[0] = Q[0];
+  c.b.Q[1] = Q[1];
+  c.b.scratch = nullptr;
+  c.stream = static_cast<hipStream_t>(stream);
+  c.L = layout_of(*grid);
+  c.parity = parity;
+  c.step = 0;
+  c.loaded = true;
+  c.variant = LC_VARIANT_SPLIT;
+  c.zchunk = 0;
+  c.coll = LC_COLL_BGK;
+  for (double& r : c.mrt) r = 0.0;
+  c.timing = false;
+  return LC_DISPATCH((&c), run_static, u, n);
 }
 
 }  // extern "C"

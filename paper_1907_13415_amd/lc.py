@@ -98,6 +98,8 @@ def _load():
         "lc_batch_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
         "lc_batch_export": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
         "lc_batch_free": ([ctypes.c_void_p], ctypes.c_int32),
+        "lc_step_static": ([P(lc_grid), P(lc_params), P(ctypes.c_void_p), P(ctypes.c_void_p), ctypes.c_int32,
+                            ctypes.c_int64, ctypes.c_void_p], ctypes.c_int32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -242,6 +244,17 @@ def lc_step_count(ctx):
 
 def lc_free(ctx):
     _check(_lib.lc_free(ctx))
+
+
+LC_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def lc_step_static(grid, params, f_ptrs, q_ptrs, parity, n, stream):
+    """f_ptrs, q_ptrs: the two device pointers of each buffer pair."""
+    fa = (ctypes.c_void_p * 2)(*f_ptrs)
+    qa = (ctypes.c_void_p * 2)(*q_ptrs)
+    _check(_lib.lc_step_static(ctypes.byref(grid), ctypes.byref(params), fa, qa, int(parity), int(n),
+                               ctypes.c_void_p(stream)))
 
 
 # ------------------------------------------------------------ convenience

@@ -180,3 +180,26 @@ def test_host_side_validation_of_settings_and_reverse_calls():
     finally:
         lc.lc_free(ctx3)
         lc.lc_free(ctx2)
+
+
+def test_static_step_validates_before_touching_the_device():
+    """lc_step_static rejects a grid whose velocity field exceeds its fixed
+    scratch array (LC_ENOMEM) and bad arguments (LC_EINVAL) on the host."""
+    from paper_1907_13415_amd import lc
+    base = 1 << 40
+    f = [base, base + (1 << 30)]
+    q = [base + (2 << 30), base + (3 << 30)]
+    params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
+    big = lc.make_grid(lc.LC_D3Q19, lc.LC_FP32_DEV, 256, 256, 256)
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_step_static(big, params, f, q, 0, 1, None)
+    assert e.value.code == lc.LC_ENOMEM and "static" in str(e.value)
+    big64 = lc.make_grid(lc.LC_D2Q9, lc.LC_FP64, 2049, 2048, 1)
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_step_static(big64, params, f, q, 0, 1, None)
+    assert e.value.code == lc.LC_ENOMEM
+    small = lc.make_grid(lc.LC_D2Q9, lc.LC_FP64, 16, 16, 1)
+    for args in ((f, q, 2, 1), (f, q, 0, -1), ([0, f[1]], q, 0, 1), (f, [q[0], q[1] + 8], 0, 1)):
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_step_static(small, params, *args, None)
+        assert e.value.code == lc.LC_EINVAL
