@@ -78,7 +78,7 @@ typedef int32_t lc_status;
 #define LC_VARIANT_AUTO 0
 #define LC_VARIANT_STAGED 1 /* one kernel per stage, intermediates in scratch */
 #define LC_VARIANT_SPLIT 2  /* two sweeps: LB update + velocity, then Q update */
-#define LC_VARIANT_FUSED 3  /* reserved (single sweep); returns LC_EUNSUPPORTED */
+#define LC_VARIANT_FUSED 3  /* one pass: reads f and Q once, writes them once */
 
 /* A periodic grid of nx * ny * nz sites (nz == 1 for D2Q9).  Every
  * dimension >= 1, ny and nz <= 65535, at most 4e9 sites; any other grid is
@@ -173,9 +173,13 @@ lc_status lc_init(const lc_grid *grid, const lc_params *params, const lc_buffers
 /* Replace the parameters (same validation as lc_init); for sweeps. */
 lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 
-/* Choose the kernel variant (LC_VARIANT_*); AUTO picks the fastest the
- * build provides for this grid.  LC_EUNSUPPORTED if not available (the
- * fused variant; the staged variant for LC_MIXED). */
+/* Choose the kernel variant (LC_VARIANT_*) of the step of Sec. 1.2 (the
+ * same arithmetic in each; SPLIT and FUSED agree bit for bit).  AUTO picks
+ * the fastest the build provides (the two-sweep variant).  FUSED runs every
+ * stage of a step in one pass over the grid: a block recomputes the
+ * stress, moments and predictor on shrinking rings around its tile instead
+ * of reading them back from HBM.  LC_EUNSUPPORTED for the staged variant in
+ * LC_MIXED. */
 lc_status lc_set_variant(lc_ctx *ctx, int32_t variant);
 
 /* Collision operator of the lattice-Boltzmann update.  LC_COLL_BGK (the
@@ -276,10 +280,13 @@ lc_status lc_vjp_backward(lc_ctx *ctx, int32_t nseg, const double *const *f_cks,
 lc_status lc_sync(lc_ctx *ctx);
 
 /* Per-launch timing of the step kernels.  While enabled, lc_step records
- * HIP events on the context stream around each of its two sweeps (split
- * variant).  lc_get_timing synchronises, returns the summed durations in
- * milliseconds of sweep 1 (LB update) and sweep 2 (Q update) since the last
- * call and the number of launches of each, and resets the record. */
+ * HIP events on the context stream around each launch of the split and
+ * fused variants (every 1024 launches the context waits for the recorded
+ * ones and folds them into running sums, so the number of events it holds
+ * stays bounded).  lc_get_timing synchronises, returns the summed
+ * durations in milliseconds and the number of launches of kind 0 (the
+ * stress/LB sweep, or the single pass of the fused variant) and kind 1 (the
+ * Q sweep) since the last call, and resets the record. */
 lc_status lc_set_timing(lc_ctx *ctx, int32_t enable);
 lc_status lc_get_timing(lc_ctx *ctx, double *ms /*[2]*/, int64_t *launches /*[2]*/);
 

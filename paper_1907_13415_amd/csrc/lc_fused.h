@@ -1,0 +1,389 @@
+// lc_fused.h -- the step as one pass over the grid: every block reads the
+// populations and Q of its sites once (plus halos, mostly from cache) and
+// writes the populations and Q of the next step once; nothing goes through
+// HBM in between.
+//
+// One step maps (f, Q)(n) to (f, Q)(n+1) (Sec. 1.2; Sec. 1.2.2 steps 1-5;
+// Eq. 7).  The new Q at a site depends on Q^P at distance 1, which depends
+// on u and Q at distance 2; u depends on the body force there, which
+// depends on the stress at distance 3, which depends on Q at distance 4.  A
+// block owns a TX x TY column of sites and marches along z.  In the plane
+// directions each stage is computed on a rectangle that shrinks by one site
+// per stage (stress on radius 3, moments on radius 2, predictor on radius
+// 1, corrector on the tile), so the block needs no data of its neighbours'
+// stages; along z the stages run on different planes of the march (the
+// stress one plane behind the newest Q plane, the moments two, the
+// predictor three, the corrector four), and each keeps the planes its
+// successor needs in LDS rings.  Blocks march through chunks of planes and
+// recompute the stages of the few planes around a chunk's ends.
+//
+// Per iteration p (Q plane p newest), in this order, separated by barriers:
+//   (a) load Q(p) on the radius-4 rectangle;
+//   (b) stress of plane p-1 on the radius-3 rectangle (corners excepted);
+//   (c) body force, moments and velocity of plane p-2 on the radius-2
+//       rectangle; at the tile's own sites also the collision and the
+//       store of the post-collision populations (pull form);
+//   (d) predictor of plane p-3 on the radius-1 rectangle;
+//   (e) corrector of plane p-4 at the tile's sites, store of Q(n+1).
+// Region loops visit the tile's own sites first, in thread order, so the
+// thread that computes a site's predictor also computes its corrector from
+// values it keeps in registers, and the tile's collisions store whole rows.
+#pragma once
+
+#include "lc_split.h"
+
+namespace lc {
+
+// Rectangle of radius r around a TX x TY tile.
+template <int TX, int TY, int r>
+struct Rect {
+  static constexpr int W = TX + 2 * r, H = TY + 2 * r, N = W * H;
+};
+
+// Rectangle coordinates (i, j) of entry k when the tile's own sites come
+// first (row-major, k < TX*TY), then the rows above and below the tile,
+// then the columns left and right of it.
+template <int TX, int TY, int r>
+__device__ __forceinline__ void tile_first(int k, int& i, int& j) {
+  constexpr int NT = TX * TY, W = TX + 2 * r, BAND = W * r;
+  if (k < NT) {
+    i = r + k % TX;
+    j = r + k / TX;
+    return;
+  }
+  int m = k - NT;
+  if (m < BAND) {
+    i = m % W;
+    j = m / W;
+    return;
+  }
+  m -= BAND;
+  if (m < BAND) {
+    i = m % W;
+    j = r + TY + m / W;
+    return;
+  }
+  m -= BAND;
+  const int row = m / (2 * r), c = m % (2 * r);
+  j = r + row;
+  i = c < r ? c : TX + c;
+}
+
+// Tile shapes of the single pass (LDS per block: FP32 D3Q19 about 132 KB,
+// FP64 D3Q19 about 152 KB, so one block per CU in 3D).
+template <int LAT, typename QT>
+struct FusedCfg {
+  static constexpr bool d3 = Lattice<LAT>::dim == 3;
+  static constexpr bool f64 = sizeof(QT) == 8;
+  static constexpr int TX = (d3 && f64) ? 16 : 32, TY = 8;
+  static constexpr int ZC = 64;  // planes per block along z
+};
+
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT>
+__device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* __restrict__ fin,
+                                           S* __restrict__ fout, QT* __restrict__ Qout, const GridDims& g,
+                                           const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz) {
+  using L = Lattice<LAT>;
+  constexpr int DIM = L::dim;
+  constexpr int NT = TX * TY;
+  using R4 = Rect<TX, TY, 4>;
+  using R3 = Rect<TX, TY, 3>;
+  using R2 = Rect<TX, TY, 2>;
+  using R1 = Rect<TX, TY, 1>;
+  // stress columns kept: tau_{a x} at x-range of radius 3 and y-range of
+  // radius 2 (for d_x at the radius-2 sites), tau_{a y} the other way round
+  constexpr int WX = R3::W, NXA = R3::W * R2::H;
+  constexpr int WY = R2::W, NYA = R2::W * R3::H;
+  constexpr int NQS = DIM == 3 ? 5 : 1;  // Q planes p-4 .. p
+  constexpr int NTS = DIM == 3 ? 2 : 1;  // in-plane stress planes
+  constexpr int NZS = DIM == 3 ? 3 : 1;  // tau_{a z} planes
+  constexpr int NUS = DIM == 3 ? 3 : 1;  // velocity planes
+  constexpr int NPS = DIM == 3 ? 2 : 1;  // predictor planes
+  __shared__ QT sQ[NQS][5][R4::N];
+  __shared__ QT sTx[NTS][DIM][NXA];
+  __shared__ QT sTy[NTS][DIM][NYA];
+  __shared__ QT sTz[NZS][DIM == 3 ? 3 : 1][DIM == 3 ? R2::N : 1];
+  __shared__ QT sU[NUS][DIM][R2::N];
+  __shared__ QT sP[NPS][5][R1::N];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int64_t N = g.N;
+  const bool own = x0 + tx < g.nx && y0 + ty < g.ny;
+
+  // In-plane site indices (periodic) of the thread's points of the
+  // radius-4 rectangle (Q loads) and of the radius-2 rectangle with their
+  // neighbour offsets (population pulls); the same in every plane.
+  constexpr int P4 = (R4::N + NT - 1) / NT, P2 = (R2::N + NT - 1) / NT;
+  const uint32_t sy = uint32_t(g.nx), sz = uint32_t(g.nx) * uint32_t(g.ny);
+  uint32_t q_off[P4];
+#pragma unroll
+  for (int n = 0; n < P4; n++) {
+    const int k = tid + n * NT;
+    const int i = k % R4::W, j = k / R4::W;
+    q_off[n] = k < R4::N ? uint32_t(wrapi(x0 - 4 + i, g.nx)) + sy * uint32_t(wrapi(y0 - 4 + j, g.ny)) : 0u;
+  }
+  struct InPlane {
+    uint32_t s, xp, xm, yp, ym;
+  };
+  InPlane ip[P2];
+#pragma unroll
+  for (int n = 0; n < P2; n++) {
+    const int k = tid + n * NT;
+    int i2 = 0, j2 = 0;
+    if (k < R2::N) tile_first<TX, TY, 2>(k, i2, j2);
+    const int gx = wrapi(x0 - 2 + i2, g.nx), gy = wrapi(y0 - 2 + j2, g.ny);
+    ip[n].s = uint32_t(gx) + sy * uint32_t(gy);
+    ip[n].xp = (gx + 1 == g.nx) ? 0u - uint32_t(g.nx - 1) : 1u;
+    ip[n].xm = (gx == 0) ? uint32_t(g.nx - 1) : 0u - 1u;
+    ip[n].yp = (gy + 1 == g.ny) ? 0u - uint32_t(g.ny - 1) * sy : sy;
+    ip[n].ym = (gy == 0) ? uint32_t(g.ny - 1) * sy : 0u - sy;
+  }
+
+  // (a) Q of plane gz on the radius-4 rectangle into slot m
+  auto load_q = [&](int m, int gz) {
+    const uint32_t plane = sz * uint32_t(gz);
+#pragma unroll
+    for (int n = 0; n < P4; n++) {
+      const int k = tid + n * NT;
+      if (n == P4 - 1 && k >= R4::N) break;
+      const uint32_t s = plane + q_off[n];
+#pragma unroll
+      for (int q = 0; q < 5; q++) sQ[m][q][k] = Qin[size_t(q) * size_t(N) + s];
+    }
+  };
+
+  // (b) stress of the plane in slot m (z neighbours in zp, zm) on the
+  // radius-3 rectangle without its corners
+  auto stress_plane = [&](int m, int zp, int zm, int ts, int zs) {
+    for (int k = tid; k < R3::N; k += NT) {
+      const int i3 = k % R3::W, j3 = k / R3::W;
+      const bool xin = i3 >= 1 && i3 < R3::W - 1, yin = j3 >= 1 && j3 < R3::H - 1;
+      if (!xin && !yin) continue;  // a corner: neither d_x nor d_y needs it
+      Sym<QT> q, Lq, d[3];
+      stencil_lds<QT, DIM, R4::W, R4::N>(sQ[m], sQ[zp], sQ[zm], (i3 + 1) + R4::W * (j3 + 1), q, d, Lq);
+      const Sym<QT> H = molecular_field(q, Lq, cq);
+      QT t[3][3];
+      stress(q, H, d, cq, t);
+      if (yin) {
+        const int kx = i3 + WX * (j3 - 1);
+#pragma unroll
+        for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = t[a][0];
+      }
+      if (xin) {
+        const int ky = (i3 - 1) + WY * j3;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
+      }
+      if constexpr (DIM == 3) {
+        if (xin && yin) {
+          const int k2 = (i3 - 1) + R2::W * (j3 - 1);
+#pragma unroll
+          for (int a = 0; a < 3; a++) sTz[zs][a][k2] = t[a][2];
+        }
+      }
+    }
+  };
+
+  // (c) body force, moments and velocity of plane z on the radius-2
+  // rectangle; the tile's own sites also collide and store (write: plane in
+  // the block's chunk)
+  auto lb_plane = [&](int z, int ts, int zsp, int zsm, int us, bool write) {
+    const int gz = wrapi(z, g.nz);
+    const uint32_t plane = sz * uint32_t(gz);
+    const uint32_t zpo = (gz + 1 == g.nz) ? 0u - uint32_t(g.nz - 1) * sz : sz;
+    const uint32_t zmo = (gz == 0) ? uint32_t(g.nz - 1) * sz : 0u - sz;
+#pragma unroll
+    for (int n = 0; n < P2; n++) {
+      const int k = tid + n * NT;
+      if (n == P2 - 1 && k >= R2::N) break;
+      int i2, j2;
+      tile_first<TX, TY, 2>(k, i2, j2);
+      const int k2 = i2 + R2::W * j2;
+      S F[3] = {S(0), S(0), S(0)};
+#pragma unroll
+      for (int a = 0; a < DIM; a++) {
+        const int kx = (i2 + 1) + WX * j2, ky = i2 + WY * (j2 + 1);
+        QT acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + WY] - sTy[ts][a][ky - WY]);
+        if constexpr (DIM == 3) acc += sTz[zsp][a][k2] - sTz[zsm][a][k2];
+        F[a] = S(QT(0.5) * acc);
+      }
+      const uint32_t site = plane + ip[n].s;
+      S f[L::q];
+#pragma unroll
+      for (int i = 0; i < L::q; i++) {
+        uint32_t d = site;
+        if (L::cx(i) == 1) d += ip[n].xm;
+        if (L::cx(i) == -1) d += ip[n].xp;
+        if (L::cy(i) == 1) d += ip[n].ym;
+        if (L::cy(i) == -1) d += ip[n].yp;
+        if (L::cz(i) == 1) d += zmo;
+        if (L::cz(i) == -1) d += zpo;
+        f[i] = fin[size_t(i) * size_t(N) + d];
+      }
+      S rho, mass, u[3];
+      moments<LAT, S, DEV>(f, F, rho, u, mass);
+#pragma unroll
+      for (int a = 0; a < DIM; a++) sU[us][a][k2] = QT(u[a]);
+      if (write && k < NT && own) {
+        if constexpr (MRT)
+          collide_mrt<LAT, S, DEV>(f, rho, mass, u, F, c);
+        else
+          collide_pairs<LAT, S, DEV>(f, rho, mass, u, F, c);
+#pragma unroll
+        for (int i = 0; i < L::q; i++) store_out(&(fout + size_t(i) * size_t(N))[site], f[i]);
+      }
+    }
+  };
+
+  // What a tile site keeps from its predictor for its corrector (the same
+  // quantities the two-sweep Q update keeps).
+  struct Stash {
+    Sym<QT> r;
+    Flow<QT> fl;
+    Sym<QT> q;
+  };
+  auto qp_of = [](const Stash& st) {
+    return Sym<QT>{st.q.xx + st.r.xx, st.q.xy + st.r.xy, st.q.xz + st.r.xz, st.q.yy + st.r.yy, st.q.yz + st.r.yz};
+  };
+  // rate and predictor at radius-1 point (i1, j1): Q from slots m (centre
+  // plane), zp, zm; velocity from slots um, uzp, uzm
+  auto pred_point = [&](int m, int zp, int zm, int um, int uzp, int uzm, int i1, int j1, Stash& st) {
+    const int k4 = (i1 + 3) + R4::W * (j1 + 3);
+    const int k2 = (i1 + 1) + R2::W * (j1 + 1);
+    Sym<QT> q, Lq, d[3];
+    stencil_lds<QT, DIM, R4::W, R4::N, false>(sQ[m], sQ[zp], sQ[zm], k4, q, d, Lq);
+    const Sym<QT> H = molecular_field(q, Lq, cq);
+    QT u[3], G[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      u[a] = a < DIM ? sU[um][a][k2] * QT(0.5) : QT(0);
+      G[a][0] = a < DIM ? sU[um][a][k2 + 1] - sU[um][a][k2 - 1] : QT(0);
+      G[a][1] = a < DIM ? sU[um][a][k2 + R2::W] - sU[um][a][k2 - R2::W] : QT(0);
+      if constexpr (DIM == 3)
+        G[a][2] = sU[uzp][a][k2] - sU[uzm][a][k2];
+      else
+        G[a][2] = QT(0);
+    }
+    st.fl = flow_terms<QT, true>(u, G, cq);
+    st.r = be_rate_flow<QT, true>(q, H, d, st.fl, cq);
+    st.q = q;
+    return qp_of(st);
+  };
+  // (d) predictor on the radius-1 rectangle into sP[ps]; the tile site's
+  // stash into `own_st`
+  auto pred_plane = [&](int m, int zp, int zm, int um, int uzp, int uzm, int ps, Stash& own_st) {
+    for (int k = tid; k < R1::N; k += NT) {
+      int i1, j1;
+      tile_first<TX, TY, 1>(k, i1, j1);
+      Stash tmp;
+      Stash& st = k < NT ? own_st : tmp;
+      const Sym<QT> qp = pred_point(m, zp, zm, um, uzp, uzm, i1, j1, st);
+      const int k1 = i1 + R1::W * j1;
+      sP[ps][0][k1] = qp.xx;
+      sP[ps][1][k1] = qp.xy;
+      sP[ps][2][k1] = qp.xz;
+      sP[ps][3][k1] = qp.yy;
+      sP[ps][4][k1] = qp.yz;
+    }
+  };
+  // (e) corrector of the tile site in plane z: in-plane neighbours of Q^P
+  // from sP[ps], the centre pc and the z neighbours pzp / pzm from registers
+  const int k1 = (tx + 1) + R1::W * (ty + 1);
+  auto corr_site = [&](int z, int ps, const Stash& st, const Sym<QT>& pc, const Sym<QT>& pzp, const Sym<QT>& pzm) {
+    if (!own) return;
+    const QT vc[5] = {pc.xx, pc.xy, pc.xz, pc.yy, pc.yz};
+    const QT vzp[5] = {pzp.xx, pzp.xy, pzp.xz, pzp.yy, pzp.yz};
+    const QT vzm[5] = {pzm.xx, pzm.xy, pzm.xz, pzm.yy, pzm.yz};
+    QT lap[5], dx[5], dy[5], dz[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+      const QT cc = vc[q];
+      const QT xp = sP[ps][q][k1 + 1], xm = sP[ps][q][k1 - 1];
+      const QT yp = sP[ps][q][k1 + R1::W], ym = sP[ps][q][k1 - R1::W];
+      dx[q] = xp - xm;
+      dy[q] = yp - ym;
+      QT l = (xp + xm) + (yp + ym);
+      if constexpr (DIM == 3) {
+        dz[q] = vzp[q] - vzm[q];
+        l += vzp[q] + vzm[q];
+        lap[q] = l - QT(6) * cc;
+      } else {
+        dz[q] = QT(0);
+        lap[q] = l - QT(4) * cc;
+      }
+    }
+    const Sym<QT> d[3] = {Sym<QT>{dx[0], dx[1], dx[2], dx[3], dx[4]}, Sym<QT>{dy[0], dy[1], dy[2], dy[3], dy[4]},
+                          Sym<QT>{dz[0], dz[1], dz[2], dz[3], dz[4]}};
+    const Sym<QT> Lp{lap[0], lap[1], lap[2], lap[3], lap[4]};
+    const Sym<QT> H = molecular_field(pc, Lp, cq);
+    const Sym<QT> Rp = be_rate_flow<QT, true>(pc, H, d, st.fl, cq);
+    const uint32_t s = uint32_t(x0 + tx) + uint32_t(g.nx) * (uint32_t(y0 + ty) + uint32_t(g.ny) * uint32_t(z));
+    const Sym<QT>& q = st.q;
+    store_out(&Qout[s], q.xx + QT(0.5) * (st.r.xx + Rp.xx));
+    store_out(&Qout[size_t(N) + s], q.xy + QT(0.5) * (st.r.xy + Rp.xy));
+    store_out(&Qout[2 * size_t(N) + s], q.xz + QT(0.5) * (st.r.xz + Rp.xz));
+    store_out(&Qout[3 * size_t(N) + s], q.yy + QT(0.5) * (st.r.yy + Rp.yy));
+    store_out(&Qout[4 * size_t(N) + s], q.yz + QT(0.5) * (st.r.yz + Rp.yz));
+  };
+
+  if constexpr (DIM == 2) {
+    load_q(0, 0);
+    __syncthreads();
+    stress_plane(0, 0, 0, 0, 0);
+    __syncthreads();
+    lb_plane(0, 0, 0, 0, 0, true);
+    __syncthreads();
+    Stash st;
+    pred_plane(0, 0, 0, 0, 0, 0, 0, st);
+    __syncthreads();
+    const Sym<QT> pc = qp_of(st);
+    corr_site(0, 0, st, pc, pc, pc);
+  } else {
+    const int zb = bz * zc;
+    const int ze = min(zb + zc, g.nz);
+    // ring slots of plane p (p >= zb - 8 > -2^30)
+    auto s5 = [](int p) { return (p + (1 << 30)) % 5; };
+    auto s3 = [](int p) { return (p + (1 << 30)) % 3; };
+    auto s2 = [](int p) { return (p + (1 << 30)) & 1; };
+    Sym<QT> pm = sym_zero<QT>();  // Q^P of plane p-5 at the tile site
+    // one iteration of the march (Q plane p newest); `prev` holds the stash
+    // of plane p-4, `cur` receives that of plane p-3
+    auto iteration = [&](int p, Stash& prev, Stash& cur) {
+      // slot s5(p) = s5(p-5) was last read by the predictor of iteration p-1
+      __syncthreads();
+      load_q(s5(p), wrapi(p, g.nz));
+      __syncthreads();
+      if (p - 1 >= zb - 3) stress_plane(s5(p - 1), s5(p), s5(p - 2), s2(p - 1), s3(p - 1));
+      __syncthreads();
+      if (p - 2 >= zb - 2) lb_plane(p - 2, s2(p - 2), s3(p - 1), s3(p - 3), s3(p - 2), p - 2 >= zb && p - 2 < ze);
+      __syncthreads();
+      if (p - 3 >= zb - 1)
+        pred_plane(s5(p - 3), s5(p - 2), s5(p - 4), s3(p - 3), s3(p - 2), s3(p - 4), s2(p - 3), cur);
+      const Sym<QT> pc = qp_of(prev);  // Q^P of plane p-4
+      if (p - 4 >= zb) corr_site(wrapi(p - 4, g.nz), s2(p - 4), prev, pc, qp_of(cur), pm);
+      pm = pc;
+    };
+    // two planes per trip, so the two stashes swap roles without copies
+    Stash stA{}, stB{};
+    int p = zb - 4;
+    for (; p + 1 <= ze + 3; p += 2) {
+      iteration(p, stA, stB);
+      iteration(p + 1, stB, stA);
+    }
+    if (p <= ze + 3) iteration(p, stA, stB);
+  }
+}
+
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT>
+__global__ void __launch_bounds__(TX* TY)
+    fused_step(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, QT* __restrict__ Qout,
+               GridDims g, Coef<S> c, Coef<QT> cq, int zc) {
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+  fused_body<LAT, S, DEV, TX, TY, MRT, QT>(Qin, fin, fout, Qout, g, c, cq, zc, t % gridDim.x,
+                                           (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y));
+}
+
+}  // namespace lc

@@ -13,6 +13,7 @@
 #include "../../include/lc.h"
 #include "lc_aux.h"
 #include "lc_split.h"
+#include "lc_fused.h"
 #include "lc_batch.h"
 #include "lc_vjp.h"
 
@@ -151,10 +152,20 @@ struct lc_ctx {
   int zchunk;  // 0: default
   int coll;        // LC_COLL_*
   double mrt[5];   // MRT rates of the ghost groups
-  // optional per-launch timing of the step kernels (events on the stream)
+  // optional per-launch timing of the step kernels: events recorded on the
+  // stream before and after each launch (kind 0: the stress/LB sweep or the
+  // single pass, kind 1: the Q sweep), folded into the sums below whenever
+  // the record reaches its cap, so a long timed run holds a bounded number
+  // of events
   bool timing;
-  std::vector<hipEvent_t> ev;     // recorded around each launch, 3 per step
+  struct Timed {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Timed> ev;
   std::vector<hipEvent_t> pool;   // idle events for reuse
+  double acc_ms[2] = {0.0, 0.0};
+  int64_t acc_n[2] = {0, 0};
   // second stream and ordering events of the overlapped reverse sweep
   // (created on first use)
   hipStream_t aux = nullptr;
@@ -182,13 +193,45 @@ static Coef<S> ctx_coef(const lc_ctx* c) {
   return k;
 }
 
-static void ctx_mark(lc_ctx* c) {
-  if (!c->timing) return;
-  hipEvent_t e = ctx_event(c);
-  if (e) {
-    (void)hipEventRecord(e, c->stream);
-    c->ev.push_back(e);
+// Launches whose events the context holds before folding them.
+constexpr size_t TIMED_CAP = 1024;
+
+// Add the elapsed times of every recorded launch to the sums and return the
+// events to the pool (waits for the last recorded event).
+static lc_status ctx_fold(lc_ctx* c) {
+  if (c->ev.empty()) return LC_OK;
+  lc_status st = hip_check(hipEventSynchronize(c->ev.back().b), "timing sync");
+  if (st) return st;
+  for (const auto& t : c->ev) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, t.a, t.b);
+    c->acc_ms[t.kind] += ms;
+    c->acc_n[t.kind]++;
+    c->pool.push_back(t.a);
+    c->pool.push_back(t.b);
   }
+  c->ev.clear();
+  return LC_OK;
+}
+
+// Event before a timed launch (nullptr when timing is off or no event).
+static hipEvent_t ctx_begin(lc_ctx* c, hipStream_t st) {
+  if (!c->timing) return nullptr;
+  if (c->ev.size() >= TIMED_CAP) (void)ctx_fold(c);
+  hipEvent_t e = ctx_event(c);
+  if (e) (void)hipEventRecord(e, st);
+  return e;
+}
+
+static void ctx_end(lc_ctx* c, hipStream_t st, hipEvent_t a, int kind) {
+  if (!a) return;
+  hipEvent_t b = ctx_event(c);
+  if (!b) {
+    c->pool.push_back(a);
+    return;
+  }
+  (void)hipEventRecord(b, st);
+  c->ev.push_back(lc_ctx::Timed{a, b, kind});
 }
 }  // namespace lc
 
@@ -246,17 +289,49 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
                 unsigned((c->g.nz + zc1 - 1) / zc1));
   const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY,
                 unsigned((c->g.nz + zc2 - 1) / zc2));
-  if (mark) ctx_mark(c);
+  hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
   if (c->coll == LC_COLL_MRT)
     hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, true, QT>), g1,
                        dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
   else
     hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, false, QT>), g1,
                        dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
-  if (mark) ctx_mark(c);
+  ctx_end(c, st, e, 0);
+  e = mark ? ctx_begin(c, st) : nullptr;
   hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1,
                      gd, kq, zc2, rec_q);
-  if (mark) ctx_mark(c);
+  ctx_end(c, st, e, 1);
+}
+
+// One step of the single pass between explicit buffers on stream st.
+template <int LAT, typename S, bool DEV, typename QT = S>
+static void step_fused_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const QT* q0, S* f1, QT* q1) {
+  using C = FusedCfg<LAT, QT>;
+  const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
+  const Coef<S> k = ctx_coef<S>(c);
+  const Coef<QT> kq = ctx_coef<QT>(c);
+  const int zc = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC) : 1;
+  const dim3 grid((c->g.nx + C::TX - 1) / C::TX, (c->g.ny + C::TY - 1) / C::TY, unsigned((c->g.nz + zc - 1) / zc));
+  hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
+  if (c->coll == LC_COLL_MRT)
+    hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, true, QT>), grid, dim3(C::TX * C::TY), 0, st, q0, f0,
+                       f1, q1, gd, k, kq, zc);
+  else
+    hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, false, QT>), grid, dim3(C::TX * C::TY), 0, st, q0, f0,
+                       f1, q1, gd, k, kq, zc);
+  ctx_end(c, st, e, 0);
+}
+
+template <int LAT, typename S, bool DEV, typename QT = S>
+static lc_status run_steps_fused(lc_ctx* c, int64_t n) {
+  for (int64_t it = 0; it < n; it++) {
+    step_fused_ptrs<LAT, S, DEV, QT>(c, c->stream, true, static_cast<const S*>(c->b.f[c->parity]),
+                                     static_cast<const QT*>(c->b.Q[c->parity]),
+                                     static_cast<S*>(c->b.f[c->parity ^ 1]), static_cast<QT*>(c->b.Q[c->parity ^ 1]));
+    c->parity ^= 1;
+    c->step++;
+  }
+  return hip_check(hipGetLastError(), "step launch");
 }
 
 template <int LAT, typename S, bool DEV, typename QT = S>
@@ -276,6 +351,7 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
 template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps(lc_ctx* c, int64_t n) {
   if (c->variant == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV, QT>(c, n);
+  if (c->variant == LC_VARIANT_FUSED) return run_steps_fused<LAT, S, DEV, QT>(c, n);
   return run_steps_staged<LAT, S, DEV, QT>(c, n);
 }
 
@@ -478,7 +554,10 @@ lc_status lc_set_variant(lc_ctx* c, int32_t variant) {
     c->variant = LC_VARIANT_STAGED;
     return LC_OK;
   }
-  if (variant == LC_VARIANT_FUSED) return fail(LC_EUNSUPPORTED, "variant %d not available", variant);
+  if (variant == LC_VARIANT_FUSED) {
+    c->variant = LC_VARIANT_FUSED;
+    return LC_OK;
+  }
   return fail(LC_EINVAL, "unknown variant %d", variant);
 }
 
@@ -810,25 +889,24 @@ lc_status lc_get_timing(lc_ctx* c, double* ms, int64_t* launches) {
   launches[0] = launches[1] = 0;
   lc_status st = hip_check(hipStreamSynchronize(c->stream), "timing sync");
   if (st) return st;
-  // events come in triples per step: before sweep 1, between, after sweep 2
-  for (size_t i = 0; i + 2 < c->ev.size(); i += 3) {
-    float a = 0, b = 0;
-    (void)hipEventElapsedTime(&a, c->ev[i], c->ev[i + 1]);
-    (void)hipEventElapsedTime(&b, c->ev[i + 1], c->ev[i + 2]);
-    ms[0] += a;
-    ms[1] += b;
-    launches[0]++;
-    launches[1]++;
+  st = ctx_fold(c);
+  if (st) return st;
+  for (int k = 0; k < 2; k++) {
+    ms[k] = c->acc_ms[k];
+    launches[k] = c->acc_n[k];
+    c->acc_ms[k] = 0.0;
+    c->acc_n[k] = 0;
   }
-  for (hipEvent_t e : c->ev) c->pool.push_back(e);
-  c->ev.clear();
   return LC_OK;
 }
 
 lc_status lc_free(lc_ctx* c) {
   clear_error();
   if (!c) return LC_OK;
-  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (const auto& t : c->ev) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->vev)
     if (e) (void)hipEventDestroy(e);

@@ -55,6 +55,14 @@ class LCError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime under the same soname as ROCm's; the
+    # first one loaded serves the whole process.  Loading torch first makes
+    # the library share torch's runtime (and so its devices and streams)
+    # whichever module the caller imported first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("HIP library %s is missing: build it with "
                           "`python -m paper_1907_13415_amd.build`" % LIB_PATH)

@@ -25,7 +25,7 @@ def _lc():
     return lc
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("lat,shape", [(0, (1, 1, 9)), (0, (1, 7, 1)), (0, (1, 1, 1)), (0, (1, 2, 3)),
                                        (1, (1, 5, 7)), (1, (6, 1, 5)), (1, (4, 5, 1)), (1, (1, 1, 1)),
                                        (1, (2, 3, 2))])

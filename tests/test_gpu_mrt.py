@@ -42,7 +42,7 @@ def _state(lc, lat, shape, seed):
     return q5, rel, w.reshape((q, 1, 1, 1)) * (1.0 + rel)
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("lat,shape", [(0, (1, 23, 37)), (0, (1, 70, 130)), (1, (9, 11, 13)), (1, (17, 6, 67))])
 def test_mrt_parity_random_state_ragged(variant, lat, shape):
     lc = _lc()

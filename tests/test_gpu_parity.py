@@ -88,7 +88,7 @@ def _slab_reference(n, steps):
     return _SLAB_REF[key]
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_parity_slab_32cubed_d3q19_1000_steps(variant):
     """The slab recipe on a 32^3 D3Q19 grid in double precision for 1000
     steps (several z-chunks and tiles, periodic wrap in every direction)."""
@@ -226,7 +226,7 @@ def test_mass_conserved_on_gpu():
 
 
 @pytest.mark.parametrize("prec", ["fp32dev", "mixed"])
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_float_populations_conserve_mass(prec, variant):
     """The float deviation form on the 256^2 droplet for 5000 steps: total
     mass within float rounding of its start (summed per site it may drift by
@@ -377,7 +377,7 @@ def test_resume_from_export_is_bitexact(lat, shape):
     assert c.observe()["step"] == 20
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_shift_equivariance_on_gpu_bitexact(variant):
     """A one-site periodic shift of the initial state shifts the result bit
     for bit (per-site arithmetic does not depend on the tile position)."""
