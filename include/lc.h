@@ -32,6 +32,16 @@
  *    is gone, at 2(q*4 + 5*8) bytes per site update.  LC_MIXED runs the
  *    split variant only (LC_VARIANT_STAGED: LC_EUNSUPPORTED) and single
  *    grids only (the batched form rejects it).
+ *    LC_FP32_SR stores f and Q as LC_FP32_DEV does and computes as it does,
+ *    except in the Q update: the molecular field of Eq. (4) is summed in
+ *    double from the float Q and Laplacian (its bulk terms nearly cancel),
+ *    and Q(n+1) of Sec. 1.2.2 step 5 is rounded to float stochastically
+ *    (round up or down with probabilities given by the distances, from a
+ *    counter-based hash of the site index and the step count), so that
+ *    increments below half a unit in the last place are not lost at every
+ *    step; results depend on the step count since the last load, and are
+ *    reproducible.  Split and fused variants only; single grids only; no
+ *    lc_step_static.
  *    Every load/export entry point speaks double "logical" values (full f)
  *    whatever the storage precision.
  *  - Memory ownership.  The caller allocates and owns every device buffer
@@ -69,6 +79,7 @@ typedef int32_t lc_status;
 #define LC_FP64 0
 #define LC_FP32_DEV 1
 #define LC_MIXED 2
+#define LC_FP32_SR 3
 
 /* Collision operators for lc_set_collision. */
 #define LC_COLL_BGK 0 /* single relaxation time (default) */
@@ -85,7 +96,7 @@ typedef int32_t lc_status;
  * rejected with LC_EINVAL. */
 typedef struct {
   int32_t lattice;   /* LC_D2Q9 or LC_D3Q19 */
-  int32_t precision; /* LC_FP64, LC_FP32_DEV or LC_MIXED */
+  int32_t precision; /* LC_FP64, LC_FP32_DEV, LC_MIXED or LC_FP32_SR */
   int32_t nx, ny, nz;
 } lc_grid;
 

@@ -143,6 +143,9 @@ struct Coef {
   T A0;      // bulk coefficient (the adjoint needs d/dgamma of lin and quad)
   // MRT: rate of each ghost group minus 1/tau (unused by the BGK kernels)
   T mrt[5];
+  // lin, quad and K unrounded, for the molecular field of the float form
+  // with stochastic rounding (evaluated in double there)
+  double lin_d, quad_d, K_d;
 };
 
 template <typename T>
@@ -163,29 +166,82 @@ LC_HD T ddot(const Sym<T>& a, const Sym<T>& b) {
          T(2) * (a.xy * b.xy + a.xz * b.xz + a.yz * b.yz);
 }
 
-// Molecular field, Eq. (4), from Q and its Laplacian L:
+// Molecular field, Eq. (4), from Q and its Laplacian L, evaluated in type
+// E with coefficients lin, quad, K:
 //   H = lin Q + quad (Q.Q - Tr(Q^2) I/3) - quad Tr(Q^2) Q + K L.
-template <typename T>
-LC_HD Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>& L,
-                                                  const Coef<T>& c) {
-  const T zz = Q.zz();
-  const T sxx = Q.xx * Q.xx + Q.xy * Q.xy + Q.xz * Q.xz;
-  const T syy = Q.xy * Q.xy + Q.yy * Q.yy + Q.yz * Q.yz;
-  const T szz = Q.xz * Q.xz + Q.yz * Q.yz + zz * zz;
-  const T sxy = Q.xx * Q.xy + Q.xy * Q.yy + Q.xz * Q.yz;
-  const T sxz = Q.xx * Q.xz + Q.xy * Q.yz + Q.xz * zz;
-  const T syz = Q.xy * Q.xz + Q.yy * Q.yz + Q.yz * zz;
-  const T tr2 = sxx + syy + szz;
-  const T a = c.lin - c.quad * tr2;
-  const T third = c.quad * tr2 * T(1.0 / 3.0);
+template <typename E, typename T>
+LC_HD Sym<T> molecular_field_in(const Sym<T>& Qt, const Sym<T>& Lt, E lin, E quad, E K) {
+  const Sym<E> Q{E(Qt.xx), E(Qt.xy), E(Qt.xz), E(Qt.yy), E(Qt.yz)};
+  const E zz = Q.zz();
+  const E sxx = Q.xx * Q.xx + Q.xy * Q.xy + Q.xz * Q.xz;
+  const E syy = Q.xy * Q.xy + Q.yy * Q.yy + Q.yz * Q.yz;
+  const E szz = Q.xz * Q.xz + Q.yz * Q.yz + zz * zz;
+  const E sxy = Q.xx * Q.xy + Q.xy * Q.yy + Q.xz * Q.yz;
+  const E sxz = Q.xx * Q.xz + Q.xy * Q.yz + Q.xz * zz;
+  const E syz = Q.xy * Q.xz + Q.yy * Q.yz + Q.yz * zz;
+  const E tr2 = sxx + syy + szz;
+  const E a = lin - quad * tr2;
+  const E third = quad * tr2 * E(1.0 / 3.0);
   Sym<T> H;
-  H.xx = a * Q.xx + c.quad * sxx - third + c.K * L.xx;
-  H.yy = a * Q.yy + c.quad * syy - third + c.K * L.yy;
-  H.xy = a * Q.xy + c.quad * sxy + c.K * L.xy;
-  H.xz = a * Q.xz + c.quad * sxz + c.K * L.xz;
-  H.yz = a * Q.yz + c.quad * syz + c.K * L.yz;
+  H.xx = T(a * Q.xx + quad * sxx - third + K * E(Lt.xx));
+  H.yy = T(a * Q.yy + quad * syy - third + K * E(Lt.yy));
+  H.xy = T(a * Q.xy + quad * sxy + K * E(Lt.xy));
+  H.xz = T(a * Q.xz + quad * sxz + K * E(Lt.xz));
+  H.yz = T(a * Q.yz + quad * syz + K * E(Lt.yz));
   return H;
 }
+
+template <typename T>
+LC_HD Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>& L, const Coef<T>& c) {
+  return molecular_field_in<T, T>(Q, L, c.lin, c.quad, c.K);
+}
+
+// The molecular field of the float form with stochastic rounding: the bulk
+// terms nearly cancel near the nematic minimum and at an interface (they
+// balance K L there), and their float rounding, the same at a site from one
+// step to the next while the state there is unchanged, acts as a small
+// systematic force.  The sum is formed in double from the float Q and L
+// with the unrounded coefficients and rounded once.
+template <typename T>
+LC_HD Sym<T> molecular_field_exact(const Sym<T>& Q, const Sym<T>& L, const Coef<T>& c) {
+  return molecular_field_in<double, T>(Q, L, c.lin_d, c.quad_d, c.K_d);
+}
+
+// ---------------------------------------------------------------------------
+// Stochastic rounding of the Q update (float form with stochastic
+// rounding).  Where the increment of a step is below half a unit in the last
+// place of Q (a slowly relaxing bulk, a slowly moving front) round-to-nearest
+// drops it at every step and the stored Q stalls; rounding up or down with
+// probabilities proportional to the distances keeps the expected stored
+// value equal to the exact one.
+//
+// Counter-based uniform numbers: the PCG hash (the RXS-M-XS output
+// permutation of a one-step LCG, O'Neill 2014, as a hash: Jarzynski and
+// Olano, "Hash Functions for GPU Rendering", JCGT 2020) of the site index
+// xor a per-step key.
+LC_HD uint32_t pcg_hash(uint32_t v) {
+  const uint32_t state = v * 747796405u + 2891336453u;
+  const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
+
+// u in (0, 1] from 24 bits of a hash.
+LC_HD float unit_of(uint32_t h) { return float((h >> 8) + 1u) * (1.0f / 16777216.0f); }
+
+// q + inc rounded to float with probability of rounding away from the
+// nearest value equal to the distance to it in units in the last place (u
+// uniform in (0, 1]).  The remainder of the nearest sum is exact when
+// |q| >= |inc| (Fast2Sum); where Q is smaller than its increment it is
+// near zero and so is its unit in the last place.
+LC_HD float add_stochastic(float q, float inc, float u) {
+  const float s = q + inc;
+  const float e = inc - (s - q);
+  int ex = 0;
+  (void)frexpf(s, &ex);
+  const float ulp = ldexpf(1.0f, ex - 24);
+  return fabsf(e) > u * ulp ? s + copysignf(ulp, e) : s;
+}
+LC_HD double add_stochastic(double q, double inc, float) { return q + inc; }
 
 // Stress of Eq. (6) without the hydrostatic part, as a general 3x3 tensor:
 //   tau = 2 xi (Q + I/3)(Q:H) - xi [H (Q+I/3) + (Q+I/3) H]

@@ -79,10 +79,11 @@ struct FusedCfg {
   static constexpr int ZC = 64;  // planes per block along z
 };
 
-template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT>
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT, bool SR>
 __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* __restrict__ fin,
                                            S* __restrict__ fout, QT* __restrict__ Qout, const GridDims& g,
-                                           const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz) {
+                                           const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz,
+                                           uint32_t srkey) {
   using L = Lattice<LAT>;
   constexpr int DIM = L::dim;
   constexpr int NT = TX * TY;
@@ -254,7 +255,7 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     const int k2 = (i1 + 1) + R2::W * (j1 + 1);
     Sym<QT> q, Lq, d[3];
     stencil_lds<QT, DIM, R4::W, R4::N, false>(sQ[m], sQ[zp], sQ[zm], k4, q, d, Lq);
-    const Sym<QT> H = molecular_field(q, Lq, cq);
+    const Sym<QT> H = SR ? molecular_field_exact(q, Lq, cq) : molecular_field(q, Lq, cq);
     QT u[3], G[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -317,15 +318,10 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     const Sym<QT> d[3] = {Sym<QT>{dx[0], dx[1], dx[2], dx[3], dx[4]}, Sym<QT>{dy[0], dy[1], dy[2], dy[3], dy[4]},
                           Sym<QT>{dz[0], dz[1], dz[2], dz[3], dz[4]}};
     const Sym<QT> Lp{lap[0], lap[1], lap[2], lap[3], lap[4]};
-    const Sym<QT> H = molecular_field(pc, Lp, cq);
+    const Sym<QT> H = SR ? molecular_field_exact(pc, Lp, cq) : molecular_field(pc, Lp, cq);
     const Sym<QT> Rp = be_rate_flow<QT, true>(pc, H, d, st.fl, cq);
     const uint32_t s = uint32_t(x0 + tx) + uint32_t(g.nx) * (uint32_t(y0 + ty) + uint32_t(g.ny) * uint32_t(z));
-    const Sym<QT>& q = st.q;
-    store_out(&Qout[s], q.xx + QT(0.5) * (st.r.xx + Rp.xx));
-    store_out(&Qout[size_t(N) + s], q.xy + QT(0.5) * (st.r.xy + Rp.xy));
-    store_out(&Qout[2 * size_t(N) + s], q.xz + QT(0.5) * (st.r.xz + Rp.xz));
-    store_out(&Qout[3 * size_t(N) + s], q.yy + QT(0.5) * (st.r.yy + Rp.yy));
-    store_out(&Qout[4 * size_t(N) + s], q.yz + QT(0.5) * (st.r.yz + Rp.yz));
+    store_q_update<QT, SR>(Qout, N, int64_t(s), st.q, st.r, Rp, srkey);
   };
 
   if constexpr (DIM == 2) {
@@ -376,14 +372,14 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   }
 }
 
-template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT>
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT, bool SR>
 __global__ void __launch_bounds__(TX* TY)
     fused_step(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, QT* __restrict__ Qout,
-               GridDims g, Coef<S> c, Coef<QT> cq, int zc) {
+               GridDims g, Coef<S> c, Coef<QT> cq, int zc, uint32_t srkey) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  fused_body<LAT, S, DEV, TX, TY, MRT, QT>(Qin, fin, fout, Qout, g, c, cq, zc, t % gridDim.x,
-                                           (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y));
+  fused_body<LAT, S, DEV, TX, TY, MRT, QT, SR>(Qin, fin, fout, Qout, g, c, cq, zc, t % gridDim.x,
+                                               (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y), srkey);
 }
 
 }  // namespace lc

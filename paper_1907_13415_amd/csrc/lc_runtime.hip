@@ -46,7 +46,8 @@ int lattice_q(int lattice) { return lattice == LC_D2Q9 ? 9 : 19; }
 lc_status check_grid(const lc_grid* g) {
   if (!g) return fail(LC_EINVAL, "grid is NULL");
   if (g->lattice != LC_D2Q9 && g->lattice != LC_D3Q19) return fail(LC_EINVAL, "unknown lattice %d", g->lattice);
-  if (g->precision != LC_FP64 && g->precision != LC_FP32_DEV && g->precision != LC_MIXED)
+  if (g->precision != LC_FP64 && g->precision != LC_FP32_DEV && g->precision != LC_MIXED &&
+      g->precision != LC_FP32_SR)
     return fail(LC_EINVAL, "unknown precision %d", g->precision);
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(LC_EINVAL, "grid dimensions must be >= 1");
   if (g->lattice == LC_D2Q9 && g->nz != 1) return fail(LC_EINVAL, "D2Q9 requires nz == 1");
@@ -87,6 +88,9 @@ Coef<S> make_coef(const lc_params& p) {
   c.src = S(1.0 - 1.0 / (2.0 * p.tau));
   c.A0 = S(p.A0);
   for (int g = 0; g < 5; g++) c.mrt[g] = S(0);
+  c.lin_d = -p.A0 * (1.0 - p.gamma / 3.0);
+  c.quad_d = p.A0 * p.gamma;
+  c.K_d = p.K;
   return c;
 }
 
@@ -94,7 +98,7 @@ Layout layout_of(const lc_grid& g) {
   Layout L;
   const int64_t N = int64_t(g.nx) * g.ny * g.nz;
   const size_t es = g.precision == LC_FP64 ? 8 : 4;
-  const size_t es_q = g.precision == LC_FP32_DEV ? 4 : 8;
+  const size_t es_q = (g.precision == LC_FP32_DEV || g.precision == LC_FP32_SR) ? 4 : 8;
   const int dim = g.lattice == LC_D2Q9 ? 2 : 3;
   const int ntau = dim == 2 ? 4 : 9;
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
@@ -193,6 +197,10 @@ static Coef<S> ctx_coef(const lc_ctx* c) {
   return k;
 }
 
+// Key of the uniform numbers of the stochastic rounding at step `step` (the
+// hash of the step counter; sites hash their index xor this key).
+static uint32_t step_key(int64_t step) { return pcg_hash(uint32_t(step) * 0x9E3779B9u + 0x7F4A7C15u); }
+
 // Launches whose events the context holds before folding them.
 constexpr size_t TIMED_CAP = 1024;
 
@@ -243,6 +251,8 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
   if constexpr (!std::is_same<S, QT>::value) {
     return fail(LC_EUNSUPPORTED, "the staged variant has no mixed-precision form");
   } else {
+  if (c->g.precision == LC_FP32_SR)
+    return fail(LC_EUNSUPPORTED, "the staged variant has no stochastic-rounding form");
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = ctx_coef<S>(c);
   char* scr = static_cast<char*>(c->b.scratch);
@@ -298,8 +308,12 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
                        dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
   ctx_end(c, st, e, 0);
   e = mark ? ctx_begin(c, st) : nullptr;
-  hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1,
-                     gd, kq, zc2, rec_q);
+  if (std::is_same<QT, float>::value && c->g.precision == LC_FP32_SR)
+    hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE, std::is_same<QT, float>::value>), g2,
+                       dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1, gd, kq, zc2, rec_q, step_key(c->step));
+  else
+    hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE>), g2, dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1,
+                       gd, kq, zc2, rec_q, 0u);
   ctx_end(c, st, e, 1);
 }
 
@@ -312,13 +326,25 @@ static void step_fused_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   const Coef<QT> kq = ctx_coef<QT>(c);
   const int zc = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC) : 1;
   const dim3 grid((c->g.nx + C::TX - 1) / C::TX, (c->g.ny + C::TY - 1) / C::TY, unsigned((c->g.nz + zc - 1) / zc));
+  constexpr bool F32 = std::is_same<QT, float>::value;
+  const bool sr = F32 && c->g.precision == LC_FP32_SR;
+  const uint32_t key = step_key(c->step);
   hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
-  if (c->coll == LC_COLL_MRT)
-    hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, true, QT>), grid, dim3(C::TX * C::TY), 0, st, q0, f0,
-                       f1, q1, gd, k, kq, zc);
-  else
-    hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, false, QT>), grid, dim3(C::TX * C::TY), 0, st, q0, f0,
-                       f1, q1, gd, k, kq, zc);
+  if (c->coll == LC_COLL_MRT) {
+    if (sr)
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, true, QT, F32>), grid, dim3(C::TX * C::TY), 0, st,
+                         q0, f0, f1, q1, gd, k, kq, zc, key);
+    else
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, true, QT, false>), grid, dim3(C::TX * C::TY), 0, st,
+                         q0, f0, f1, q1, gd, k, kq, zc, key);
+  } else {
+    if (sr)
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, false, QT, F32>), grid, dim3(C::TX * C::TY), 0, st,
+                         q0, f0, f1, q1, gd, k, kq, zc, key);
+    else
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, false, QT, false>), grid, dim3(C::TX * C::TY), 0,
+                         st, q0, f0, f1, q1, gd, k, kq, zc, key);
+  }
   ctx_end(c, st, e, 0);
 }
 
@@ -445,6 +471,8 @@ static void fill_observables(const double* h, uint32_t mask, int half_axis, int6
   out->nonfinite = h[7] != 0.0 ? 1 : 0;
 }
 
+// LC_FP32_DEV and LC_FP32_SR share their storage and every kernel but the
+// Q update, which the step dispatch picks from the precision.
 #define LC_DISPATCH_LAT(ctx, LAT, FN, ...)                                              \
   ((ctx)->g.precision == LC_FP64    ? FN<LAT, double, false, double>(ctx, ##__VA_ARGS__) \
    : (ctx)->g.precision == LC_MIXED ? FN<LAT, float, true, double>(ctx, ##__VA_ARGS__)   \
@@ -551,6 +579,8 @@ lc_status lc_set_variant(lc_ctx* c, int32_t variant) {
   }
   if (variant == LC_VARIANT_STAGED) {
     if (c->g.precision == LC_MIXED) return fail(LC_EUNSUPPORTED, "the staged variant has no mixed-precision form");
+    if (c->g.precision == LC_FP32_SR)
+      return fail(LC_EUNSUPPORTED, "the staged variant has no stochastic-rounding form");
     c->variant = LC_VARIANT_STAGED;
     return LC_OK;
   }
@@ -954,7 +984,7 @@ static lc_status static_scratch_ptr(void** out) {
 static size_t static_velocity_bytes(const lc_grid& g) {
   const size_t N = size_t(g.nx) * g.ny * g.nz;
   const size_t dim = g.lattice == LC_D2Q9 ? 2 : 3;
-  return dim * N * (g.precision == LC_FP32_DEV ? 4 : 8);
+  return dim * N * (g.precision == LC_FP64 || g.precision == LC_MIXED ? 8 : 4);
 }
 
 template <int LAT, typename S, bool DEV, typename QT = S>
@@ -989,6 +1019,8 @@ lc_status lc_step_static(const lc_grid* grid, const lc_params* params, void* con
     if (!p) return fail(LC_EINVAL, "a buffer pointer is NULL");
     if (reinterpret_cast<uintptr_t>(p) & 255) return fail(LC_EINVAL, "buffers must be 256-byte aligned");
   }
+  if (grid->precision == LC_FP32_SR)
+    return fail(LC_EUNSUPPORTED, "the stochastic-rounding form needs the step counter of a context");
   const size_t need = static_velocity_bytes(*grid);
   if (need > LC_STATIC_SCRATCH_BYTES)
     return fail(LC_ENOMEM, "grid needs %zu bytes of velocity scratch; the static buffer holds %zu", need,
@@ -1043,6 +1075,8 @@ static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B
     if (st) return st;
     if (grids[k].lattice != LC_D2Q9) return fail(LC_EUNSUPPORTED, "the batched form runs D2Q9 grids");
     if (grids[k].precision == LC_MIXED) return fail(LC_EUNSUPPORTED, "the batched form has no mixed-precision form");
+    if (grids[k].precision == LC_FP32_SR)
+      return fail(LC_EUNSUPPORTED, "the batched form has no stochastic-rounding form");
     if (grids[k].precision != grids[0].precision) return fail(LC_EINVAL, "all grids must share one precision");
   }
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };

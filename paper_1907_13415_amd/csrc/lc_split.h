@@ -163,6 +163,29 @@ __device__ __forceinline__ void store_region(const RegionRegs<S, TX, TY, NC>& r,
   }
 }
 
+// Store of Q(n+1) = Q + (R(Q) + R(Q^P))/2 (Sec. 1.2.2, step 5) at site s;
+// with SR the float sums are rounded stochastically, one uniform number per
+// site (from the site index and the step's key) serving its five
+// components (each rounding stays unbiased).
+template <typename S, bool SR>
+__device__ __forceinline__ void store_q_update(S* __restrict__ Qout, int64_t N, int64_t s, const Sym<S>& q,
+                                               const Sym<S>& r, const Sym<S>& rp, uint32_t srkey) {
+  if constexpr (SR) {
+    const float u = unit_of(pcg_hash(uint32_t(s) ^ srkey));
+    __builtin_nontemporal_store(add_stochastic(q.xx, S(0.5) * (r.xx + rp.xx), u), &Qout[s]);
+    __builtin_nontemporal_store(add_stochastic(q.xy, S(0.5) * (r.xy + rp.xy), u), &Qout[N + s]);
+    __builtin_nontemporal_store(add_stochastic(q.xz, S(0.5) * (r.xz + rp.xz), u), &Qout[2 * N + s]);
+    __builtin_nontemporal_store(add_stochastic(q.yy, S(0.5) * (r.yy + rp.yy), u), &Qout[3 * N + s]);
+    __builtin_nontemporal_store(add_stochastic(q.yz, S(0.5) * (r.yz + rp.yz), u), &Qout[4 * N + s]);
+  } else {
+    __builtin_nontemporal_store(q.xx + S(0.5) * (r.xx + rp.xx), &Qout[s]);
+    __builtin_nontemporal_store(q.xy + S(0.5) * (r.xy + rp.xy), &Qout[N + s]);
+    __builtin_nontemporal_store(q.xz + S(0.5) * (r.xz + rp.xz), &Qout[2 * N + s]);
+    __builtin_nontemporal_store(q.yy + S(0.5) * (r.yy + rp.yy), &Qout[3 * N + s]);
+    __builtin_nontemporal_store(q.yz + S(0.5) * (r.yz + rp.yz), &Qout[4 * N + s]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sweep 1: stress in LDS, body force, moments, collision, streaming.
 // Store of a sweep's output (f or Q of the next step), which no block reads
@@ -362,10 +385,13 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
 // ---------------------------------------------------------------------------
 // Sweep 2: predictor on tile + ring (LDS), corrector on the tile.  S is the
 // type of Q, of the velocity and of the arithmetic.
-template <int LAT, typename S, int TX, int TY>
+// SR: the float form with stochastic rounding (molecular field summed in
+// double, Q(n+1) rounded stochastically with the per-step key srkey).
+template <int LAT, typename S, int TX, int TY, bool SR = false>
 __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S* __restrict__ uin,
                                              S* __restrict__ Qout, const GridDims& g, const Coef<S>& c, int zc,
-                                             int bx, int by, int bz, S* __restrict__ rec = nullptr) {
+                                             int bx, int by, int bz, S* __restrict__ rec = nullptr,
+                                             uint32_t srkey = 0) {
   using L = Lattice<LAT>;
   using T = Tile<TX, TY>;
   constexpr int DIM = L::dim;
@@ -411,7 +437,7 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     const int k = T::r2(i, j);
     Sym<S> q, Lq, d[3];
     stencil_lds<S, DIM, T::W2, T::R2, false>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
-    const Sym<S> H = molecular_field(q, Lq, c);
+    const Sym<S> H = SR ? molecular_field_exact(q, Lq, c) : molecular_field(q, Lq, c);
     S u[3], G[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -466,16 +492,11 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     const Sym<S> d[3] = {Sym<S>{dx[0], dx[1], dx[2], dx[3], dx[4]}, Sym<S>{dy[0], dy[1], dy[2], dy[3], dy[4]},
                          Sym<S>{dz[0], dz[1], dz[2], dz[3], dz[4]}};
     const Sym<S> Lp{lap[0], lap[1], lap[2], lap[3], lap[4]};
-    const Sym<S> H = molecular_field(pc, Lp, c);
+    const Sym<S> H = SR ? molecular_field_exact(pc, Lp, c) : molecular_field(pc, Lp, c);
     const Sym<S> Rp = be_rate_flow<S, true>(pc, H, d, st.fl, c);
     const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
     if (rec) store_sym(rec, N, s, pc);  // record the predictor (reverse-mode replay)
-    const Sym<S>& q = st.q;
-    store_out(&Qout[s], q.xx + S(0.5) * (st.r.xx + Rp.xx));
-    store_out(&Qout[N + s], q.xy + S(0.5) * (st.r.xy + Rp.xy));
-    store_out(&Qout[2 * N + s], q.xz + S(0.5) * (st.r.xz + Rp.xz));
-    store_out(&Qout[3 * N + s], q.yy + S(0.5) * (st.r.yy + Rp.yy));
-    store_out(&Qout[4 * N + s], q.yz + S(0.5) * (st.r.yz + Rp.yz));
+    store_q_update<S, SR>(Qout, N, s, st.q, st.r, Rp, srkey);
   };
 
   if constexpr (DIM == 2) {
@@ -553,14 +574,14 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   }
 }
 
-template <int LAT, typename S, int TX, int TY, int WPE>
+template <int LAT, typename S, int TX, int TY, int WPE, bool SR = false>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_q(const S* __restrict__ Qin, const S* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
-            int zc, S* __restrict__ rec) {
+            int zc, S* __restrict__ rec, uint32_t srkey) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  split_q_body<LAT, S, TX, TY>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
-                               t / (gridDim.x * gridDim.y), rec);
+  split_q_body<LAT, S, TX, TY, SR>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
+                                   t / (gridDim.x * gridDim.y), rec, srkey);
 }
 
 // Tile shapes of the two-sweep kernels (measured on 256^3; LDS per block at

@@ -19,14 +19,14 @@ LIB_PATH = os.path.join(_HERE, "liblc.so")
 
 LC_OK, LC_EINVAL, LC_ENOMEM, LC_EDEVICE, LC_ENONFINITE, LC_ESTATE, LC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 LC_D2Q9, LC_D3Q19 = 0, 1
-LC_FP64, LC_FP32_DEV, LC_MIXED = 0, 1, 2
+LC_FP64, LC_FP32_DEV, LC_MIXED, LC_FP32_SR = 0, 1, 2, 3
 LC_VARIANT_AUTO, LC_VARIANT_STAGED, LC_VARIANT_SPLIT, LC_VARIANT_FUSED = 0, 1, 2, 3
 LC_COLL_BGK, LC_COLL_MRT = 0, 1
 LC_OBS_MASS, LC_OBS_MOM, LC_OBS_UMAX, LC_OBS_S, LC_OBS_ALL = 1, 2, 4, 8, 15
 LC_FIELD_F, LC_FIELD_Q, LC_FIELD_RHO, LC_FIELD_U, LC_FIELD_FORCE, LC_FIELD_S = range(6)
 
 LATTICES = {"D2Q9": LC_D2Q9, "D3Q19": LC_D3Q19}
-PRECISIONS = {"fp64": LC_FP64, "fp32dev": LC_FP32_DEV, "mixed": LC_MIXED}
+PRECISIONS = {"fp64": LC_FP64, "fp32dev": LC_FP32_DEV, "mixed": LC_MIXED, "fp32sr": LC_FP32_SR}
 
 
 class lc_grid(ctypes.Structure):

@@ -51,7 +51,7 @@ def _same(lc, a, b, n):
     return torch.equal(a._f[p], b._f[p]) and torch.equal(a._Q[p], b._Q[p])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32dev", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32dev", "mixed", "fp32sr"])
 @pytest.mark.parametrize("lat,shape,chunk", [(0, (1, 23, 37), 0), (0, (1, 70, 130), 0), (1, (9, 11, 13), 0),
                                              (1, (17, 6, 67), 5), (1, (40, 20, 36), 0), (1, (13, 18, 35), 3),
                                              (1, (7, 9, 40), 1)])
