@@ -62,7 +62,7 @@ def test_init_rejects_bad_params(bad):
     assert e.value.code == lc.LC_EINVAL
 
 
-@pytest.mark.parametrize("grid", [(0, 0, 16, 16, 2), (0, 0, 0, 16, 1), (2, 0, 16, 16, 1), (0, 3, 16, 16, 1),
+@pytest.mark.parametrize("grid", [(0, 0, 16, 16, 2), (0, 0, 0, 16, 1), (2, 0, 16, 16, 1), (0, 4, 16, 16, 1),
                                   (1, 1, 8, -1, 8), (1, 1, 8, 65536, 8), (1, 1, 8, 8, 65536),
                                   (1, 1, 2000, 2000, 1001)])
 def test_init_rejects_bad_grid(grid):
