@@ -182,12 +182,13 @@ LC_HD Sym<T> molecular_field_in(const Sym<T>& Qt, const Sym<T>& Lt, E lin, E qua
   const E tr2 = sxx + syy + szz;
   const E a = lin - quad * tr2;
   const E third = quad * tr2 * E(1.0 / 3.0);
+  // grouped so that each component is one chain of fused multiply-adds
   Sym<T> H;
-  H.xx = T(a * Q.xx + quad * sxx - third + K * E(Lt.xx));
-  H.yy = T(a * Q.yy + quad * syy - third + K * E(Lt.yy));
-  H.xy = T(a * Q.xy + quad * sxy + K * E(Lt.xy));
-  H.xz = T(a * Q.xz + quad * sxz + K * E(Lt.xz));
-  H.yz = T(a * Q.yz + quad * syz + K * E(Lt.yz));
+  H.xx = T(a * Q.xx + (quad * sxx + (K * E(Lt.xx) - third)));
+  H.yy = T(a * Q.yy + (quad * syy + (K * E(Lt.yy) - third)));
+  H.xy = T(a * Q.xy + (quad * sxy + K * E(Lt.xy)));
+  H.xz = T(a * Q.xz + (quad * sxz + K * E(Lt.xz)));
+  H.yz = T(a * Q.yz + (quad * syz + K * E(Lt.yz)));
   return H;
 }
 
@@ -316,22 +317,28 @@ LC_HD Sym<T> be_rate_flow(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3
   const T Qp[3][3] = {{Q.xx + T(1.0 / 3.0), Q.xy, Q.xz},
                       {Q.xy, Q.yy + T(1.0 / 3.0), Q.yz},
                       {Q.xz, Q.yz, Q.zz() + T(1.0 / 3.0)}};
-  // A = B Qp; only the entries needed for the five stored components of S.
-  auto A = [&](int a, int b) { return f.B[a][0] * Qp[0][b] + f.B[a][1] * Qp[1][b] + f.B[a][2] * Qp[2][b]; };
+  // S_ab = A_ab + A_ba with A = B Qp.  Each component is accumulated as one
+  // chain of fused multiply-adds, starting from the advection term.
   const T qg = Q.xx * f.g[0] + Q.yy * f.g[1] + Q.xy * f.g[2] + Q.xz * f.g[3] + Q.yz * f.g[4];
   const T k = RAW ? c.xi * qg : T(2) * c.xi * qg;
   const T(&u)[3] = f.u;
+  // -(u . grad) of one component, then - k Qp_ab
+  auto base = [&](T d0, T d1, T d2, T qp) { return -(u[0] * d0) - (u[1] * d1 + (u[2] * d2 + k * qp)); };
+  // sum_g B_ag Qp_gb + B_bg Qp_ga added to x
+  auto sym = [&](int a, int b, T x) {
+    return f.B[a][0] * Qp[0][b] + (f.B[a][1] * Qp[1][b] + (f.B[a][2] * Qp[2][b] +
+           (f.B[b][0] * Qp[0][a] + (f.B[b][1] * Qp[1][a] + (f.B[b][2] * Qp[2][a] + x)))));
+  };
+  // 2 A_aa added to x
+  auto diag = [&](int a, T x) {
+    return T(2) * (f.B[a][0] * Qp[0][a] + f.B[a][1] * Qp[1][a] + f.B[a][2] * Qp[2][a]) + x;
+  };
   Sym<T> R;
-  R.xx = c.Gam * H.xx + T(2) * A(0, 0) - k * Qp[0][0] -
-         (u[0] * dQ[0].xx + u[1] * dQ[1].xx + u[2] * dQ[2].xx);
-  R.yy = c.Gam * H.yy + T(2) * A(1, 1) - k * Qp[1][1] -
-         (u[0] * dQ[0].yy + u[1] * dQ[1].yy + u[2] * dQ[2].yy);
-  R.xy = c.Gam * H.xy + A(0, 1) + A(1, 0) - k * Qp[0][1] -
-         (u[0] * dQ[0].xy + u[1] * dQ[1].xy + u[2] * dQ[2].xy);
-  R.xz = c.Gam * H.xz + A(0, 2) + A(2, 0) - k * Qp[0][2] -
-         (u[0] * dQ[0].xz + u[1] * dQ[1].xz + u[2] * dQ[2].xz);
-  R.yz = c.Gam * H.yz + A(1, 2) + A(2, 1) - k * Qp[1][2] -
-         (u[0] * dQ[0].yz + u[1] * dQ[1].yz + u[2] * dQ[2].yz);
+  R.xx = c.Gam * H.xx + diag(0, base(dQ[0].xx, dQ[1].xx, dQ[2].xx, Qp[0][0]));
+  R.yy = c.Gam * H.yy + diag(1, base(dQ[0].yy, dQ[1].yy, dQ[2].yy, Qp[1][1]));
+  R.xy = c.Gam * H.xy + sym(0, 1, base(dQ[0].xy, dQ[1].xy, dQ[2].xy, Qp[0][1]));
+  R.xz = c.Gam * H.xz + sym(0, 2, base(dQ[0].xz, dQ[1].xz, dQ[2].xz, Qp[0][2]));
+  R.yz = c.Gam * H.yz + sym(1, 2, base(dQ[0].yz, dQ[1].yz, dQ[2].yz, Qp[1][2]));
   return R;
 }
 

@@ -70,16 +70,18 @@ __device__ __forceinline__ void tile_first(int k, int& i, int& j) {
 }
 
 // Tile shapes of the single pass (LDS per block: FP32 D3Q19 about 132 KB,
-// FP64 D3Q19 about 152 KB, so one block per CU in 3D).
+// FP64 D3Q19 about 152 KB, so one block per CU in 3D) and threads per block
+// (more threads than tile sites share the ring work and hide latency).
 template <int LAT, typename QT>
 struct FusedCfg {
   static constexpr bool d3 = Lattice<LAT>::dim == 3;
   static constexpr bool f64 = sizeof(QT) == 8;
   static constexpr int TX = (d3 && f64) ? 16 : 32, TY = 8;
+  static constexpr int NTHR = d3 ? (f64 ? 256 : 512) : TX * TY;
   static constexpr int ZC = 64;  // planes per block along z
 };
 
-template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT, bool SR>
+template <int LAT, typename S, bool DEV, int TX, int TY, int NTHR, bool MRT, typename QT, bool SR>
 __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* __restrict__ fin,
                                            S* __restrict__ fout, QT* __restrict__ Qout, const GridDims& g,
                                            const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz,
@@ -107,21 +109,23 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   __shared__ QT sU[NUS][DIM][R2::N];
   __shared__ QT sP[NPS][5][R1::N];
 
+  static_assert(NTHR >= NT, "one thread per tile site at least");
   const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
+  const int tx = tid % TX, ty = (tid / TX) % TY;
   const int x0 = bx * TX, y0 = by * TY;
   const int64_t N = g.N;
-  const bool own = x0 + tx < g.nx && y0 + ty < g.ny;
+  // threads tid < NT own the tile's sites; the others take ring sites only
+  const bool own = tid < NT && x0 + tx < g.nx && y0 + ty < g.ny;
 
   // In-plane site indices (periodic) of the thread's points of the
   // radius-4 rectangle (Q loads) and of the radius-2 rectangle with their
   // neighbour offsets (population pulls); the same in every plane.
-  constexpr int P4 = (R4::N + NT - 1) / NT, P2 = (R2::N + NT - 1) / NT;
+  constexpr int P4 = (R4::N + NTHR - 1) / NTHR, P2 = (R2::N + NTHR - 1) / NTHR;
   const uint32_t sy = uint32_t(g.nx), sz = uint32_t(g.nx) * uint32_t(g.ny);
   uint32_t q_off[P4];
 #pragma unroll
   for (int n = 0; n < P4; n++) {
-    const int k = tid + n * NT;
+    const int k = tid + n * NTHR;
     const int i = k % R4::W, j = k / R4::W;
     q_off[n] = k < R4::N ? uint32_t(wrapi(x0 - 4 + i, g.nx)) + sy * uint32_t(wrapi(y0 - 4 + j, g.ny)) : 0u;
   }
@@ -131,7 +135,7 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   InPlane ip[P2];
 #pragma unroll
   for (int n = 0; n < P2; n++) {
-    const int k = tid + n * NT;
+    const int k = tid + n * NTHR;
     int i2 = 0, j2 = 0;
     if (k < R2::N) tile_first<TX, TY, 2>(k, i2, j2);
     const int gx = wrapi(x0 - 2 + i2, g.nx), gy = wrapi(y0 - 2 + j2, g.ny);
@@ -147,7 +151,7 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     const uint32_t plane = sz * uint32_t(gz);
 #pragma unroll
     for (int n = 0; n < P4; n++) {
-      const int k = tid + n * NT;
+      const int k = tid + n * NTHR;
       if (n == P4 - 1 && k >= R4::N) break;
       const uint32_t s = plane + q_off[n];
 #pragma unroll
@@ -158,7 +162,7 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   // (b) stress of the plane in slot m (z neighbours in zp, zm) on the
   // radius-3 rectangle without its corners
   auto stress_plane = [&](int m, int zp, int zm, int ts, int zs) {
-    for (int k = tid; k < R3::N; k += NT) {
+    for (int k = tid; k < R3::N; k += NTHR) {
       const int i3 = k % R3::W, j3 = k / R3::W;
       const bool xin = i3 >= 1 && i3 < R3::W - 1, yin = j3 >= 1 && j3 < R3::H - 1;
       if (!xin && !yin) continue;  // a corner: neither d_x nor d_y needs it
@@ -197,7 +201,7 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     const uint32_t zmo = (gz == 0) ? uint32_t(g.nz - 1) * sz : 0u - sz;
 #pragma unroll
     for (int n = 0; n < P2; n++) {
-      const int k = tid + n * NT;
+      const int k = tid + n * NTHR;
       if (n == P2 - 1 && k >= R2::N) break;
       int i2, j2;
       tile_first<TX, TY, 2>(k, i2, j2);
@@ -275,7 +279,7 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   // (d) predictor on the radius-1 rectangle into sP[ps]; the tile site's
   // stash into `own_st`
   auto pred_plane = [&](int m, int zp, int zm, int um, int uzp, int uzm, int ps, Stash& own_st) {
-    for (int k = tid; k < R1::N; k += NT) {
+    for (int k = tid; k < R1::N; k += NTHR) {
       int i1, j1;
       tile_first<TX, TY, 1>(k, i1, j1);
       Stash tmp;
@@ -372,13 +376,13 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   }
 }
 
-template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT, typename QT, bool SR>
-__global__ void __launch_bounds__(TX* TY)
+template <int LAT, typename S, bool DEV, int TX, int TY, int NTHR, bool MRT, typename QT, bool SR>
+__global__ void __launch_bounds__(NTHR)
     fused_step(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, QT* __restrict__ Qout,
                GridDims g, Coef<S> c, Coef<QT> cq, int zc, uint32_t srkey) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  fused_body<LAT, S, DEV, TX, TY, MRT, QT, SR>(Qin, fin, fout, Qout, g, c, cq, zc, t % gridDim.x,
+  fused_body<LAT, S, DEV, TX, TY, NTHR, MRT, QT, SR>(Qin, fin, fout, Qout, g, c, cq, zc, t % gridDim.x,
                                                (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y), srkey);
 }
 

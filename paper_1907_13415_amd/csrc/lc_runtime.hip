@@ -332,17 +332,17 @@ static void step_fused_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
   if (c->coll == LC_COLL_MRT) {
     if (sr)
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, true, QT, F32>), grid, dim3(C::TX * C::TY), 0, st,
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, true, QT, F32>), grid, dim3(C::NTHR), 0, st,
                          q0, f0, f1, q1, gd, k, kq, zc, key);
     else
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, true, QT, false>), grid, dim3(C::TX * C::TY), 0, st,
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, true, QT, false>), grid, dim3(C::NTHR), 0, st,
                          q0, f0, f1, q1, gd, k, kq, zc, key);
   } else {
     if (sr)
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, false, QT, F32>), grid, dim3(C::TX * C::TY), 0, st,
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, false, QT, F32>), grid, dim3(C::NTHR), 0, st,
                          q0, f0, f1, q1, gd, k, kq, zc, key);
     else
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, false, QT, false>), grid, dim3(C::TX * C::TY), 0,
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, false, QT, false>), grid, dim3(C::NTHR), 0,
                          st, q0, f0, f1, q1, gd, k, kq, zc, key);
   }
   ctx_end(c, st, e, 0);
