@@ -5,16 +5,19 @@ Headline workload: the 256^3 D3Q19 planar nematic slab (random director,
 tau = 1) in the FP32 deviation storage form.  A step is one full lattice
 update (molecular field, stress, body force, moments, Heun update of Q,
 collision, streaming).  The same grid is timed in double precision for the
-FP32/FP64 ratio and the FP32 error in S.  Also reported: the 64-grid
+FP32/FP64 ratio and the FP32 error in S, and in the float form with
+stochastic rounding.  Each of these legs runs W untimed steps and then
+`--repeats` timed runs of exactly K steps; ms_per_step is the median run.
+Also reported: the single-pass variant, the mixed form, the 64-grid
 temperature sweep in the batched form, the same slab with the MRT
-collision, and the cost of the checkpointed reverse sweep on the 256^2
-droplet.
+collision, the 256^2 droplets over 20000 steps, and the cost of the
+checkpointed reverse sweep on the 256^2 droplet.
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region;
 timings use HIP events recorded on the stream the library launches on.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
-                  [--only batch|adjoint] [--calibrate]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--no-cpu]
+                  [--quick] [--only batch|adjoint|mrt] [--calibrate]
 """
 import argparse
 import hashlib
@@ -113,9 +116,15 @@ def cpu_baseline(n=128, min_s=10.0, max_steps=200):
 MRT_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
 
 
-def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False):
+def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False, repeats=1, variant=None):
+    """The slab for `warmup` untimed steps, then `repeats` timed runs of
+    exactly `steps` steps each (HIP events on the library stream around each
+    run, and around each kernel launch): the median run's ms per step and
+    the launches' average durations over all runs."""
     with torch.cuda.stream(stream):
         s = lc.Solver("D3Q19", prec, w.shape, w.params, device=dev, stream=stream)
+        if variant is not None:
+            s.set_variant(variant)
         if mrt:
             s.set_collision(lc.LC_COLL_MRT, MRT_RATES)
         s.load(w.q5)
@@ -123,13 +132,16 @@ def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False):
         torch.cuda.synchronize()
         lc.lc_set_timing(s.ctx, True)
         lc.lc_get_timing(s.ctx)  # clear
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        s.step(steps)
-        t1.record(stream)
-        torch.cuda.synchronize()
-        ms_step = t0.elapsed_time(t1) / steps
+        runs = []
+        for _ in range(repeats):
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record(stream)
+            s.step(steps)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            runs.append(t0.elapsed_time(t1) / steps)
         ms_k, n_k = lc.lc_get_timing(s.ctx)
         lc.lc_set_timing(s.ctx, False)
         S = torch.empty((1,) + w.shape, dtype=torch.float64, device=dev)
@@ -137,13 +149,31 @@ def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False):
         obs = s.observe(half_axis=2)
         torch.cuda.synchronize()
         del s
-    return dict(ms=ms_step, kernel_ms=[ms_k[0] / max(n_k[0], 1), ms_k[1] / max(n_k[1], 1)], S=S, obs=obs)
+    return dict(ms=statistics.median(runs), runs=runs, steps_total=warmup + repeats * steps,
+                kernel_ms=[ms_k[0] / max(n_k[0], 1), ms_k[1] / max(n_k[1], 1)], launches=list(n_k), S=S, obs=obs)
+
+
+def fused_leg(torch, lc, w, args, dev, stream, N, bytes_site, ms_split32, ms_split64):
+    """The single-pass variant on the slab (FP32 and FP64), beside the two
+    sweeps timed above."""
+    out = {}
+    for prec, es, ref in (("fp32dev", 4, ms_split32), ("fp64", 8, ms_split64)):
+        r = run_slab(torch, lc, w, prec, args.steps, args.warmup, dev, stream, repeats=3,
+                     variant=lc.LC_VARIANT_FUSED)
+        del r["S"]
+        b = alg_bytes_per_site(19, es)
+        out[prec] = {"mlups": round(N / (r["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(r["ms"], 5),
+                     "kernel_ms": round(r["kernel_ms"][0], 5),
+                     "roofline_frac": round(b * N / (r["kernel_ms"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "over_split": round(r["ms"] / ref, 3)}
+        torch.cuda.empty_cache()
+    return out
 
 
 def mixed_leg(torch, lc, w, args, dev, stream, N, S64):
     """The slab in the mixed form (float populations, double Q): throughput,
     roofline on its own compulsory bytes and |S - S64| after the same steps."""
-    rm = run_slab(torch, lc, w, "mixed", args.steps, args.warmup, dev, stream)
+    rm = run_slab(torch, lc, w, "mixed", args.steps, args.warmup, dev, stream, repeats=args.repeats)
     dS = float((rm["S"] - S64).abs().max().item())
     b = 2 * (19 * 4 + 5 * 8)
     return {"mlups": round(N / (rm["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(rm["ms"], 5),
@@ -183,7 +213,7 @@ def run_droplets(torch, lc, dev, stream, steps=20000):
         g = w.params[1]
         sn = s_nematic(g)
         res = {}
-        for prec in ("fp64", "fp32dev", "mixed"):
+        for prec in ("fp64", "fp32dev", "mixed", "fp32sr"):
             with torch.cuda.stream(stream):
                 s = lc.Solver("D2Q9", prec, w.shape, w.params, device=dev, stream=stream)
                 s.load(w.q5)
@@ -195,7 +225,7 @@ def run_droplets(torch, lc, dev, stream, steps=20000):
                 res[prec] = dict(umax=o["umax"], r0=r0, r1=math.sqrt(o["ssum"] / (math.pi * sn)),
                                  S=s.export(lc.LC_FIELD_S), mlups=w.shape[1] * w.shape[2] * steps / dt / 1e6)
                 del s
-        a, b, m = res["fp64"], res["fp32dev"], res["mixed"]
+        a, b, m, r = res["fp64"], res["fp32dev"], res["mixed"], res["fp32sr"]
         recs.append({"gamma": round(g, 4), "umax": a["umax"], "radius": [round(a["r0"], 4), round(a["r1"], 4)],
                      "radius_drift_per_step": (a["r1"] - a["r0"]) / steps,
                      "fp32_max_abs_dS": float(abs(a["S"] - b["S"]).max()),
@@ -206,8 +236,12 @@ def run_droplets(torch, lc, dev, stream, steps=20000):
                      "mixed_umax_rel_err": abs(m["umax"] - a["umax"]) / a["umax"],
                      "mixed_radius_err": abs(m["r1"] - a["r1"]),
                      "mixed_interface_velocity_rel_err": _vel_err(m, a),
+                     "fp32sr_max_abs_dS": float(abs(a["S"] - r["S"]).max()),
+                     "fp32sr_umax_rel_err": abs(r["umax"] - a["umax"]) / a["umax"],
+                     "fp32sr_radius_err": abs(r["r1"] - a["r1"]),
+                     "fp32sr_interface_velocity_rel_err": _vel_err(r, a),
                      "mlups_fp64": round(a["mlups"], 1), "mlups_fp32": round(b["mlups"], 1),
-                     "mlups_mixed": round(m["mlups"], 1)})
+                     "mlups_mixed": round(m["mlups"], 1), "mlups_fp32sr": round(r["mlups"], 1)})
     return dict(workload="droplet256_d2q9", steps=steps, runs=recs)
 
 
@@ -322,6 +356,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=256, help="edge of the cubic grid")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--repeats", type=int, default=5, help="timed runs of --steps steps; the median is reported")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--calibrate", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM counters)")
@@ -365,16 +400,20 @@ def main():
     if args.only == "mrt":
         print(json.dumps({"mrt_fp32": mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)}), flush=True)
         return
-    r32 = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream)
-    r64 = run_slab(torch, lc, w, "fp64", args.steps, args.warmup, dev, stream)
+    rep = args.repeats
+    r32 = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream, repeats=rep)
+    r64 = run_slab(torch, lc, w, "fp64", args.steps, args.warmup, dev, stream, repeats=rep)
+    rsr = run_slab(torch, lc, w, "fp32sr", args.steps, args.warmup, dev, stream, repeats=rep)
     dS = float((r32["S"] - r64["S"]).abs().max().item())
+    dS_sr = float((rsr["S"] - r64["S"]).abs().max().item())
     mixed = None if args.quick else mixed_leg(torch, lc, w, args, dev, stream, N, r64["S"])
-    del r32["S"], r64["S"]
+    del r32["S"], r64["S"], rsr["S"]
     torch.cuda.empty_cache()
 
     ms32 = r32["ms"]
     mlups32 = N / (ms32 * 1e-3) / 1e6
     mlups64 = N / (r64["ms"] * 1e-3) / 1e6
+    mlups_sr = N / (rsr["ms"] * 1e-3) / 1e6
     kernel_ms = sum(r32["kernel_ms"])  # the two sweeps of one step
     achieved = bytes_site * N / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic()
@@ -390,6 +429,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "repeats": rep,
         "ms_per_step": round(ms32, 5),
         "higher_is_better": True,
         "scaling": "weak",
@@ -398,8 +438,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "slab%d^3_d3q19_fp32dev" % args.n, "lattice": "D3Q19", "grid": [args.n] * 3,
                    "storage": "fp32 deviation", "gamma": 2.7, "steps_in_config": 500},
+        # achieved: the algorithmic bytes of one step over the summed average
+        # durations of the step's two launches (kernel time, HIP events on
+        # the library stream); frac_step_wall: the same bytes over the whole
+        # step's wall time (ms_per_step)
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "frac_basis": "kernel time",
+                     "frac_step_wall": round(bytes_site * N / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
                      "measured_gbs_per_sweep": measured_gbs,
                      "kernel": "split_lb + split_q (the two launches of one step)",
                      "bytes_per_site": bytes_site, "sites_per_launch": N,
@@ -410,9 +456,16 @@ def main():
                                         / HBM_PEAK_GBS, 4)},
         "fp32_over_fp64": round(mlups32 / mlups64, 3),
         "fp32_max_abs_dS_vs_fp64": dS,
-        "fp32_steps_compared": args.warmup + args.steps,
+        "fp32_steps_compared": r32["steps_total"],
+        # float storage with the molecular field summed in double and
+        # stochastic rounding of the Q update (within 1e-5 on the droplets)
+        "fp32sr": {"mlups": round(mlups_sr, 2), "ms_per_step": round(rsr["ms"], 5),
+                   "kernel_ms": [round(v, 5) for v in rsr["kernel_ms"]],
+                   "roofline_frac": round(bytes_site * N / (sum(rsr["kernel_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "over_fp64": round(mlups_sr / mlups64, 3), "max_abs_dS_vs_fp64": dS_sr},
     }
     if not args.quick:
+        out["fused"] = fused_leg(torch, lc, w, args, dev, stream, N, bytes_site, r32["ms"], r64["ms"])
         out["mixed"] = mixed
         out["mrt_fp32"] = mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)
         out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)

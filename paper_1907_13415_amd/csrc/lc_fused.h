@@ -146,6 +146,41 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     ip[n].ym = (gy == 0) ? uint32_t(g.ny - 1) * sy : 0u - sy;
   }
 
+  // Register staging of the next plane's global loads (float forms in 3D,
+  // where registers allow): the Q rectangle of plane p+1 and the populations
+  // of the next moment plane are in flight while the stages of plane p run.
+  constexpr bool PF = DIM == 3 && sizeof(QT) == 4;
+  struct QRegs {
+    QT v[PF ? P4 : 1][5];
+  };
+  struct FRegs {
+    S v[PF ? P2 : 1][L::q];
+  };
+  auto fetch_q = [&](int gz, QRegs& r) {
+    if constexpr (PF) {
+      const uint32_t plane = sz * uint32_t(gz);
+#pragma unroll
+      for (int n = 0; n < P4; n++) {
+        const int k = tid + n * NTHR;
+        if (n == P4 - 1 && k >= R4::N) break;
+        const uint32_t s = plane + q_off[n];
+#pragma unroll
+        for (int q = 0; q < 5; q++) r.v[n][q] = Qin[size_t(q) * size_t(N) + s];
+      }
+    }
+  };
+  auto store_q = [&](int m, const QRegs& r) {
+    if constexpr (PF) {
+#pragma unroll
+      for (int n = 0; n < P4; n++) {
+        const int k = tid + n * NTHR;
+        if (n == P4 - 1 && k >= R4::N) break;
+#pragma unroll
+        for (int q = 0; q < 5; q++) sQ[m][q][k] = r.v[n][q];
+      }
+    }
+  };
+
   // (a) Q of plane gz on the radius-4 rectangle into slot m
   auto load_q = [&](int m, int gz) {
     const uint32_t plane = sz * uint32_t(gz);
@@ -194,11 +229,45 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   // (c) body force, moments and velocity of plane z on the radius-2
   // rectangle; the tile's own sites also collide and store (write: plane in
   // the block's chunk)
-  auto lb_plane = [&](int z, int ts, int zsp, int zsm, int us, bool write) {
+  // pull the populations of plane z at the thread's radius-2 points
+  // f_i(x) = buf_i(x - c_i)
+  auto pull = [&](int n, uint32_t plane, uint32_t zpo, uint32_t zmo, S (&f)[L::q]) {
+    const uint32_t site = plane + ip[n].s;
+#pragma unroll
+    for (int i = 0; i < L::q; i++) {
+      uint32_t d = site;
+      if (L::cx(i) == 1) d += ip[n].xm;
+      if (L::cx(i) == -1) d += ip[n].xp;
+      if (L::cy(i) == 1) d += ip[n].ym;
+      if (L::cy(i) == -1) d += ip[n].yp;
+      if (L::cz(i) == 1) d += zmo;
+      if (L::cz(i) == -1) d += zpo;
+      f[i] = fin[size_t(i) * size_t(N) + d];
+    }
+  };
+  auto zoffsets = [&](int gz, uint32_t& zpo, uint32_t& zmo) {
+    zpo = (gz + 1 == g.nz) ? 0u - uint32_t(g.nz - 1) * sz : sz;
+    zmo = (gz == 0) ? uint32_t(g.nz - 1) * sz : 0u - sz;
+  };
+  auto fetch_f = [&](int z, FRegs& r) {
+    if constexpr (PF) {
+      const int gz = wrapi(z, g.nz);
+      uint32_t zpo, zmo;
+      zoffsets(gz, zpo, zmo);
+#pragma unroll
+      for (int n = 0; n < P2; n++) {
+        const int k = tid + n * NTHR;
+        if (n == P2 - 1 && k >= R2::N) break;
+        pull(n, sz * uint32_t(gz), zpo, zmo, r.v[n]);
+      }
+    }
+  };
+
+  auto lb_plane = [&](int z, int ts, int zsp, int zsm, int us, bool write, const FRegs* pre) {
     const int gz = wrapi(z, g.nz);
     const uint32_t plane = sz * uint32_t(gz);
-    const uint32_t zpo = (gz + 1 == g.nz) ? 0u - uint32_t(g.nz - 1) * sz : sz;
-    const uint32_t zmo = (gz == 0) ? uint32_t(g.nz - 1) * sz : 0u - sz;
+    uint32_t zpo, zmo;
+    zoffsets(gz, zpo, zmo);
 #pragma unroll
     for (int n = 0; n < P2; n++) {
       const int k = tid + n * NTHR;
@@ -216,16 +285,11 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
       }
       const uint32_t site = plane + ip[n].s;
       S f[L::q];
+      if (PF && pre) {
 #pragma unroll
-      for (int i = 0; i < L::q; i++) {
-        uint32_t d = site;
-        if (L::cx(i) == 1) d += ip[n].xm;
-        if (L::cx(i) == -1) d += ip[n].xp;
-        if (L::cy(i) == 1) d += ip[n].ym;
-        if (L::cy(i) == -1) d += ip[n].yp;
-        if (L::cz(i) == 1) d += zmo;
-        if (L::cz(i) == -1) d += zpo;
-        f[i] = fin[size_t(i) * size_t(N) + d];
+        for (int i = 0; i < L::q; i++) f[i] = pre->v[PF ? n : 0][i];
+      } else {
+        pull(n, plane, zpo, zmo, f);
       }
       S rho, mass, u[3];
       moments<LAT, S, DEV>(f, F, rho, u, mass);
@@ -333,7 +397,7 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     __syncthreads();
     stress_plane(0, 0, 0, 0, 0);
     __syncthreads();
-    lb_plane(0, 0, 0, 0, 0, true);
+    lb_plane(0, 0, 0, 0, 0, true, nullptr);
     __syncthreads();
     Stash st;
     pred_plane(0, 0, 0, 0, 0, 0, 0, st);
@@ -348,16 +412,27 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     auto s3 = [](int p) { return (p + (1 << 30)) % 3; };
     auto s2 = [](int p) { return (p + (1 << 30)) & 1; };
     Sym<QT> pm = sym_zero<QT>();  // Q^P of plane p-5 at the tile site
+    QRegs qr;
+    FRegs fr;
+    fetch_q(wrapi(zb - 4, g.nz), qr);
     // one iteration of the march (Q plane p newest); `prev` holds the stash
     // of plane p-4, `cur` receives that of plane p-3
     auto iteration = [&](int p, Stash& prev, Stash& cur) {
       // slot s5(p) = s5(p-5) was last read by the predictor of iteration p-1
       __syncthreads();
-      load_q(s5(p), wrapi(p, g.nz));
+      if constexpr (PF) {
+        store_q(s5(p), qr);
+        if (p + 1 <= ze + 3) fetch_q(wrapi(p + 1, g.nz), qr);
+      } else {
+        load_q(s5(p), wrapi(p, g.nz));
+      }
       __syncthreads();
       if (p - 1 >= zb - 3) stress_plane(s5(p - 1), s5(p), s5(p - 2), s2(p - 1), s3(p - 1));
       __syncthreads();
-      if (p - 2 >= zb - 2) lb_plane(p - 2, s2(p - 2), s3(p - 1), s3(p - 3), s3(p - 2), p - 2 >= zb && p - 2 < ze);
+      if (p - 2 >= zb - 2)
+        lb_plane(p - 2, s2(p - 2), s3(p - 1), s3(p - 3), s3(p - 2), p - 2 >= zb && p - 2 < ze, PF ? &fr : nullptr);
+      // populations of the next moment plane, p - 1
+      if (PF && p - 1 >= zb - 2 && p - 1 <= ze + 1) fetch_f(p - 1, fr);
       __syncthreads();
       if (p - 3 >= zb - 1)
         pred_plane(s5(p - 3), s5(p - 2), s5(p - 4), s3(p - 3), s3(p - 2), s3(p - 4), s2(p - 3), cur);
