@@ -198,11 +198,12 @@ LC_HD Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>& L, const Coef<T>& c)
 }
 
 // The molecular field of the float form with stochastic rounding: the bulk
-// terms nearly cancel near the nematic minimum and at an interface (they
-// balance K L there), and their float rounding, the same at a site from one
-// step to the next while the state there is unchanged, acts as a small
-// systematic force.  The sum is formed in double from the float Q and L
-// with the unrounded coefficients and rounded once.
+// terms nearly cancel near the nematic minimum (and balance K L at an
+// interface), and their float rounding, the same at a site from one step to
+// the next while the state there is unchanged, acts as a small systematic
+// force; so does the rounding of the bulk coefficients, which shifts the
+// coexistence temperature.  The sum is formed in double from the float Q and
+// L with the unrounded coefficients and rounded once.
 template <typename T>
 LC_HD Sym<T> molecular_field_exact(const Sym<T>& Q, const Sym<T>& L, const Coef<T>& c) {
   return molecular_field_in<double, T>(Q, L, c.lin_d, c.quad_d, c.K_d);
@@ -217,30 +218,35 @@ LC_HD Sym<T> molecular_field_exact(const Sym<T>& Q, const Sym<T>& L, const Coef<
 // value equal to the exact one.
 //
 // Counter-based uniform numbers: the PCG hash (the RXS-M-XS output
-// permutation of a one-step LCG, O'Neill 2014, as a hash: Jarzynski and
-// Olano, "Hash Functions for GPU Rendering", JCGT 2020) of the site index
-// xor a per-step key.
+// permutation of a one-step LCG, O'Neill 2014, used as a hash: Jarzynski
+// and Olano, "Hash Functions for GPU Rendering", JCGT 2020) of the site
+// index xor a per-step key (itself the hash of the step count).
 LC_HD uint32_t pcg_hash(uint32_t v) {
   const uint32_t state = v * 747796405u + 2891336453u;
   const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
   return (word >> 22u) ^ word;
 }
 
-// u in (0, 1] from 24 bits of a hash.
-LC_HD float unit_of(uint32_t h) { return float((h >> 8) + 1u) * (1.0f / 16777216.0f); }
+// u * 2^-24, u uniform in (0, 1] from 24 bits of the hash, for site s
+// under the step key.
+LC_HD float site_uniform(uint32_t s, uint32_t key) {
+  const uint32_t h = pcg_hash(s ^ key);
+  return float((h >> 8) + 1u) * (1.0f / 281474976710656.0f);
+}
 
-// q + inc rounded to float with probability of rounding away from the
-// nearest value equal to the distance to it in units in the last place (u
-// uniform in (0, 1]).  The remainder of the nearest sum is exact when
-// |q| >= |inc| (Fast2Sum); where Q is smaller than its increment it is
-// near zero and so is its unit in the last place.
-LC_HD float add_stochastic(float q, float inc, float u) {
+// q + inc rounded to float, away from the nearest value with probability
+// equal to the distance to it in units in the last place (u24 = u 2^-24,
+// u uniform in (0, 1]).  The remainder of the nearest sum is exact when
+// |q| >= |inc| (Fast2Sum); where Q is smaller than its increment it is near
+// zero and so is its unit in the last place.  For |s| in [2^(ex-1), 2^ex)
+// the unit in the last place is 2^(ex-24).
+LC_HD float add_stochastic(float q, float inc, float u24) {
   const float s = q + inc;
   const float e = inc - (s - q);
   int ex = 0;
   (void)frexpf(s, &ex);
-  const float ulp = ldexpf(1.0f, ex - 24);
-  return fabsf(e) > u * ulp ? s + copysignf(ulp, e) : s;
+  const float ulp = ldexpf(1.0f / 16777216.0f, ex);
+  return fabsf(e) > ldexpf(u24, ex) ? s + copysignf(ulp, e) : s;
 }
 LC_HD double add_stochastic(double q, double inc, float) { return q + inc; }
 
@@ -272,6 +278,28 @@ LC_HD void stress(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3],
       const T E = ddot(dQ[a], dQ[b]);
       tau[a][b] = two_xi_qh * qp - xi23 * Hm[a][b] - c.K * E - ap * M[a][b] - am * M[b][a];
     }
+  }
+}
+
+// Column b of the same stress (tau_ab for a = x, y, z), each entry by the
+// same expression as in stress(), so bit for bit the same values: what a
+// site outside a tile contributes to one derivative of the body force.
+template <typename T>
+LC_HD void stress_col(const Sym<T>& Q, const Sym<T>& H, const Sym<T> (&dQ)[3], const Coef<T>& c, int b,
+                      T (&col)[3]) {
+  const T Qm[3][3] = {{Q.xx, Q.xy, Q.xz}, {Q.xy, Q.yy, Q.yz}, {Q.xz, Q.yz, Q.zz()}};
+  const T Hm[3][3] = {{H.xx, H.xy, H.xz}, {H.xy, H.yy, H.yz}, {H.xz, H.yz, H.zz()}};
+  const T qh = ddot(Q, H);
+  const T two_xi_qh = T(2) * c.xi * qh;
+  const T xi23 = c.xi * T(2.0 / 3.0);
+  const T ap = c.xi + T(1), am = c.xi - T(1);
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    const T Mab = Hm[a][0] * Qm[0][b] + Hm[a][1] * Qm[1][b] + Hm[a][2] * Qm[2][b];
+    const T Mba = Hm[b][0] * Qm[0][a] + Hm[b][1] * Qm[1][a] + Hm[b][2] * Qm[2][a];
+    const T qp = Qm[a][b] + (a == b ? T(1.0 / 3.0) : T(0));
+    const T E = ddot(dQ[a], dQ[b]);
+    col[a] = two_xi_qh * qp - xi23 * Hm[a][b] - c.K * E - ap * Mab - am * Mba;
   }
 }
 

@@ -171,7 +171,7 @@ template <typename S, bool SR>
 __device__ __forceinline__ void store_q_update(S* __restrict__ Qout, int64_t N, int64_t s, const Sym<S>& q,
                                                const Sym<S>& r, const Sym<S>& rp, uint32_t srkey) {
   if constexpr (SR) {
-    const float u = unit_of(pcg_hash(uint32_t(s) ^ srkey));
+    const float u = site_uniform(uint32_t(s), srkey);
     __builtin_nontemporal_store(add_stochastic(q.xx, S(0.5) * (r.xx + rp.xx), u), &Qout[s]);
     __builtin_nontemporal_store(add_stochastic(q.xy, S(0.5) * (r.xy + rp.xy), u), &Qout[N + s]);
     __builtin_nontemporal_store(add_stochastic(q.xz, S(0.5) * (r.xz + rp.xz), u), &Qout[2 * N + s]);
@@ -235,34 +235,62 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
     const Sym<QT> H = molecular_field(q, Lq, cq);
     stress(q, H, d, cq, t);
   };
+  // column b of the stress at the R1 point (i, j)
+  auto tau_col = [&](int m, int zp, int zm, int i, int j, int b, QT (&col)[3]) {
+    Sym<QT> q, Lq, d[3];
+    stencil_lds<QT, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
+    const Sym<QT> H = molecular_field(q, Lq, cq);
+    stress_col(q, H, d, cq, b, col);
+  };
+  // Ring sites in the rows above and below the tile need only tau_{a y},
+  // those in the columns beside it only tau_{a x}.  With rows of 32 or 64
+  // sites the two kinds fall in different waves and each wave computes just
+  // its column; otherwise every ring site computes the whole stress.  All
+  // entries round alike either way.
+  constexpr bool COLS = TX % 32 == 0 && (TX * TY) % 64 == 0 && (2 * TX) % 64 == 0;
   // stress of the whole region of plane slot m into sT[ts]; returns the
   // owner's tau_{a z}
   auto tau_plane = [&](int m, int zp, int zm, int ts, QT (&tz)[3]) {
-    // pass 0: the owner's site; pass 1: a ring site (threads tid < RING).
-    // Both passes run the same code, so every site's stress is rounded the
-    // same way wherever it falls in a tile.
-#pragma unroll 1
-    for (int pass = 0; pass < 2; pass++) {
-      if (pass == 1 && tid >= T::RING) break;
-      int i = tx + 1, j = ty + 1;
-      if (pass == 1) T::ring(tid, i, j);
+    {  // the owner's site
       QT t[3][3];
-      tau_point(m, zp, zm, i, j, t);
-      const bool row_ring = pass == 1 && (j == 0 || j == TY + 1);
-      const bool col_ring = pass == 1 && !row_ring;
-      if (!row_ring) {
-        const int kx = i + T::W1 * (j - 1);
+      tau_point(m, zp, zm, tx + 1, ty + 1, t);
+      const int kx = (tx + 1) + T::W1 * ty, ky = tx + TX * (ty + 1);
 #pragma unroll
-        for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = t[a][0];
+      for (int a = 0; a < DIM; a++) {
+        sTx[ts][a][kx] = t[a][0];
+        sTy[ts][a][ky] = t[a][1];
       }
-      if (!col_ring) {
-        const int ky = (i - 1) + TX * j;
 #pragma unroll
-        for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
-      }
-      if (pass == 0) {
+      for (int a = 0; a < 3; a++) tz[a] = t[a][2];
+    }
+    if (tid < T::RING) {  // a ring site
+      int i, j;
+      T::ring(tid, i, j);
+      const bool row_ring = j == 0 || j == TY + 1;
+      if constexpr (COLS) {
+        QT col[3];
+        tau_col(m, zp, zm, i, j, row_ring ? 1 : 0, col);
+        if (row_ring) {
+          const int ky = (i - 1) + TX * j;
 #pragma unroll
-        for (int a = 0; a < 3; a++) tz[a] = t[a][2];
+          for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = col[a];
+        } else {
+          const int kx = i + T::W1 * (j - 1);
+#pragma unroll
+          for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = col[a];
+        }
+      } else {
+        QT t[3][3];
+        tau_point(m, zp, zm, i, j, t);
+        if (row_ring) {
+          const int ky = (i - 1) + TX * j;
+#pragma unroll
+          for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
+        } else {
+          const int kx = i + T::W1 * (j - 1);
+#pragma unroll
+          for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = t[a][0];
+        }
       }
     }
   };
