@@ -17,7 +17,7 @@ Prints one JSON line.  Inputs are resident in HBM before the timed region;
 timings use HIP events recorded on the stream the library launches on.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--no-cpu]
-                  [--quick] [--only batch|adjoint|mrt] [--calibrate]
+                  [--quick] [--only batch|adjoint|mrt|fused] [--calibrate]
 """
 import argparse
 import hashlib
@@ -158,7 +158,7 @@ def fused_leg(torch, lc, w, args, dev, stream, N, bytes_site, ms_split32, ms_spl
     sweeps timed above."""
     out = {}
     for prec, es, ref in (("fp32dev", 4, ms_split32), ("fp64", 8, ms_split64)):
-        r = run_slab(torch, lc, w, prec, args.steps, args.warmup, dev, stream, repeats=3,
+        r = run_slab(torch, lc, w, prec, args.steps, args.warmup, dev, stream, repeats=min(3, args.repeats),
                      variant=lc.LC_VARIANT_FUSED)
         del r["S"]
         b = alg_bytes_per_site(19, es)
@@ -363,7 +363,7 @@ def main():
     ap.add_argument("--batch-tiles", help="LB,Q tile shapes of the batched leg instead of tuning (0..6)")
     ap.add_argument("--no-physics", action="store_true",
                     help="with --only batch: skip the 5000-step front-speed window (for counter runs)")
-    ap.add_argument("--only", choices=["batch", "adjoint", "mrt"],
+    ap.add_argument("--only", choices=["batch", "adjoint", "mrt", "fused"],
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -399,6 +399,9 @@ def main():
     bytes_site = alg_bytes_per_site(19, 4)
     if args.only == "mrt":
         print(json.dumps({"mrt_fp32": mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)}), flush=True)
+        return
+    if args.only == "fused":
+        print(json.dumps({"fused": fused_leg(torch, lc, w, args, dev, stream, N, bytes_site, 1.0, 1.0)}), flush=True)
         return
     rep = args.repeats
     r32 = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream, repeats=rep)
