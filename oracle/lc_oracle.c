@@ -485,7 +485,11 @@ int lco_stress(int nx, int ny, int nz, const double *p, const double *q5,
  *   m* = m - S (m - M f_eq) + (I - S/2) M G,   f* = M^-1 m*,
  * where S = diag(s_k) and G is the forcing term of Sec. 1.2.1 without its
  * factor (1 - 1/(2 tau)).  With every s_k = 1/tau this is the BGK step
- * above. */
+ * above.  The rows of M are orthogonal, so M^-1 = M^T diag(1/|m_k|^2):
+ * f*_i = sum_k M_ki (m*_k / |m_k|^2), with the integer entries of M as they
+ * are (a numerically computed inverse rounds its entries independently, and
+ * its momentum columns then pick up a fixed fraction of the density at every
+ * site and step). */
 static double basis_row(int lattice, int k, const int c[3]) {
   const double cx = c[0], cy = c[1], cz = c[2];
   const double c2 = cx * cx + cy * cy + cz * cz;
@@ -536,38 +540,8 @@ int lco_mrt_basis(int lattice, double *M) {
   return L.q;
 }
 
-/* Inverse of a q x q matrix by Gauss-Jordan elimination with partial
- * pivoting.  Returns 0, or -1 if singular. */
-static int invert(int q, const double *A, double *Ainv) {
-  double a[19 * 38];
-  for (int r = 0; r < q; r++)
-    for (int k = 0; k < 2 * q; k++) a[r * 2 * q + k] = k < q ? A[r * q + k] : (k - q == r ? 1.0 : 0.0);
-  for (int col = 0; col < q; col++) {
-    int piv = col;
-    for (int r = col + 1; r < q; r++)
-      if (fabs(a[r * 2 * q + col]) > fabs(a[piv * 2 * q + col])) piv = r;
-    if (a[piv * 2 * q + col] == 0.0) return -1;
-    if (piv != col)
-      for (int k = 0; k < 2 * q; k++) {
-        double t = a[col * 2 * q + k];
-        a[col * 2 * q + k] = a[piv * 2 * q + k];
-        a[piv * 2 * q + k] = t;
-      }
-    double d = a[col * 2 * q + col];
-    for (int k = 0; k < 2 * q; k++) a[col * 2 * q + k] /= d;
-    for (int r = 0; r < q; r++) {
-      if (r == col) continue;
-      double m = a[r * 2 * q + col];
-      for (int k = 0; k < 2 * q; k++) a[r * 2 * q + k] -= m * a[col * 2 * q + k];
-    }
-  }
-  for (int r = 0; r < q; r++)
-    for (int k = 0; k < q; k++) Ainv[r * q + k] = a[r * 2 * q + q + k];
-  return 0;
-}
-
 typedef struct {
-  double M[19 * 19], Minv[19 * 19], s[19];
+  double M[19 * 19], norm2[19], s[19]; /* basis, |m_k|^2, rates */
 } mrt_t;
 
 /* Post-collision populations at one site with the MRT operator. */
@@ -591,9 +565,10 @@ static void collide_mrt(const lattice_t *L, const mrt_t *op, const double *fin, 
     }
     ms[k] = mk - op->s[k] * (mk - mek) + (1.0 - op->s[k] / 2.0) * mgk;
   }
+  for (int k = 0; k < q; k++) ms[k] /= op->norm2[k];
   for (int i = 0; i < q; i++) {
     double v = 0.0;
-    for (int k = 0; k < q; k++) v += op->Minv[i * q + k] * ms[k];
+    for (int k = 0; k < q; k++) v += op->M[k * q + i] * ms[k];
     out[i] = v;
   }
 }
@@ -650,8 +625,13 @@ int lco_run_coll(int lattice, int nx, int ny, int nz, const double *p, const dou
   mrt_t op, *opp = NULL;
   if (rates) {
     lco_mrt_basis(lattice, op.M);
-    if (invert(L.q, op.M, op.Minv)) return -1;
-    for (int k = 0; k < L.q; k++) op.s[k] = rates[k];
+    for (int k = 0; k < L.q; k++) {
+      double n2 = 0.0;
+      for (int i = 0; i < L.q; i++) n2 += op.M[k * L.q + i] * op.M[k * L.q + i];
+      if (n2 == 0.0) return -1;
+      op.norm2[k] = n2;
+      op.s[k] = rates[k];
+    }
     opp = &op;
   }
   const size_t N = g.N;

@@ -81,8 +81,10 @@ MUTANTS = {
     "observe_mom_sign": ("mom[a] += L.c[i][a] * fi;", "mom[a] -= L.c[i][a] * fi;"),
     "observe_umax_squared": ("if (sqrt(uu) > umax) umax = sqrt(uu);", "if (uu > umax) umax = uu;"),
     "observe_s_factor": ("double S = sqrt(1.5 * qq);", "double S = sqrt(qq);"),
-    # MRT: forcing relaxed with (1 - s) instead of (1 - s/2)
+    # MRT: forcing relaxed with (1 - s) instead of (1 - s/2); the back-transform
+    # without the 1/|m_k|^2 of the orthogonal inverse
     "mrt_forcing": ("(1.0 - op->s[k] / 2.0) * mgk", "(1.0 - op->s[k]) * mgk"),
+    "mrt_inverse_norm": ("for (int k = 0; k < q; k++) ms[k] /= op->norm2[k];", ";"),
 }
 
 
