@@ -10,9 +10,15 @@ Array conventions (numpy, float64, C order):
   f  : (q, nz, ny, nx)  populations in the oracle's velocity order;
   q5 : (5, nz, ny, nx)  order tensor (xx, xy, xz, yy, yz), Qzz = -Qxx - Qyy;
   params: (A0, gamma, K, Gamma, xi, tau).
+
+Stencils: ``stencil="compact"`` (the default) takes the central differences
+and compact Laplacian of Sec. 1.2.2; ``stencil="isotropic"`` takes every
+derivative of the step from the lattice's own velocity set and weights (the
+option Sec. 2.2 closes on for reducing spurious currents).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -82,6 +88,10 @@ def _load():
         lib.lco_set_threads.restype = None
         lib.lco_threads.argtypes = []
         lib.lco_threads.restype = ctypes.c_int
+        lib.lco_set_stencil.argtypes = [ctypes.c_int]
+        lib.lco_set_stencil.restype = ctypes.c_int
+        lib.lco_stencil.argtypes = []
+        lib.lco_stencil.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -109,6 +119,24 @@ def set_threads(n: int) -> None:
     _load().lco_set_threads(int(n))
 
 
+STENCILS = {"compact": 0, "isotropic": 1}
+
+
+@contextlib.contextmanager
+def _stencil(name):
+    """Select the difference stencil for the duration of one call."""
+    if name not in STENCILS:
+        raise ValueError("stencil must be one of %s" % sorted(STENCILS))
+    lib = _load()
+    old = lib.lco_stencil()
+    if lib.lco_set_stencil(STENCILS[name]) != 0:
+        raise ValueError("lco_set_stencil failed")
+    try:
+        yield lib
+    finally:
+        lib.lco_set_stencil(old)
+
+
 def lattice(lat: int):
     """Velocity table c (q, 3) and weights w (q,) of the oracle."""
     c = np.zeros(19 * 3, dtype=np.int32)
@@ -125,20 +153,23 @@ def _dims(q5):
     return nx, ny, nz
 
 
-def run(lat, f, q5, params, nsteps, rates=None):
+def run(lat, f, q5, params, nsteps, rates=None, stencil="compact"):
     """Advance (f, q5) by nsteps; returns new arrays.  With rates (q values,
     one per moment of the MRT basis, see mrt_basis) the collision is MRT,
-    else BGK."""
+    else BGK; `stencil` as in the module notes."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     q5 = np.array(q5, dtype=np.float64, order="C", copy=True)
     nx, ny, nz = _dims(q5)
     p = _params(params)
-    if rates is None:
-        rc = _load().lco_run(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(nsteps))
-    else:
+    r = None
+    if rates is not None:
         r = np.ascontiguousarray(np.asarray(rates, dtype=np.float64))
         assert r.shape == (f.shape[0],), "one rate per moment"
-        rc = _load().lco_run_coll(lat, nx, ny, nz, _ptr(p), _ptr(r), _ptr(f), _ptr(q5), int(nsteps))
+    with _stencil(stencil) as lib:
+        if r is None:
+            rc = lib.lco_run(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(nsteps))
+        else:
+            rc = lib.lco_run_coll(lat, nx, ny, nz, _ptr(p), _ptr(r), _ptr(f), _ptr(q5), int(nsteps))
     if rc != 0:
         raise ValueError("lco_run failed: %d" % rc)
     return f, q5
@@ -176,7 +207,7 @@ def mrt_rates(lat, tau, ghost_rates):
     return r
 
 
-def fields(lat, f, q5, params):
+def fields(lat, f, q5, params, stencil="compact"):
     """Intermediates of one step at state (f, q5)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     q5 = np.ascontiguousarray(q5, dtype=np.float64)
@@ -186,7 +217,8 @@ def fields(lat, f, q5, params):
                H=np.zeros((3, 3) + sh), tau=np.zeros((3, 3) + sh), G=np.zeros((3, 3) + sh),
                R=np.zeros((5,) + sh), Rp=np.zeros((5,) + sh), S=np.zeros((3, 3) + sh))
     p = _params(params)
-    rc = _load().lco_fields(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5),
+    with _stencil(stencil) as lib:
+        rc = lib.lco_fields(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5),
                             *[_ptr(out[k]) for k in ("rho", "u", "F", "H", "tau", "G", "R", "Rp", "S")])
     if rc != 0:
         raise ValueError("lco_fields failed: %d" % rc)
@@ -241,14 +273,15 @@ def source(lat, tau, u, F):
     return out
 
 
-def observe(lat, f, q5, params, half_axis=0):
+def observe(lat, f, q5, params, half_axis=0, stencil="compact"):
     """mass, lattice momentum (3), max |u|, sum S, half-domain sum S."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     q5 = np.ascontiguousarray(q5, dtype=np.float64)
     nx, ny, nz = _dims(q5)
     out = np.zeros(7)
     p = _params(params)
-    rc = _load().lco_observe(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(half_axis), _ptr(out))
+    with _stencil(stencil) as lib:
+        rc = lib.lco_observe(lat, nx, ny, nz, _ptr(p), _ptr(f), _ptr(q5), int(half_axis), _ptr(out))
     if rc != 0:
         raise ValueError("lco_observe failed")
     return dict(mass=out[0], mom=out[1:4].copy(), umax=out[4], ssum=out[5], ssum_half=out[6])

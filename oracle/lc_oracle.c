@@ -136,6 +136,35 @@ static size_t shift(const grid_t *g, size_t s, int a, int d) {
   return site(g, x, y, z);
 }
 
+/* Site s displaced by the lattice vector c (periodic). */
+static size_t displaced(const grid_t *g, size_t s, const int c[3]) {
+  long x, y, z;
+  coords(g, s, &x, &y, &z);
+  return site(g, x + c[0], y + c[1], z + c[2]);
+}
+
+/* ---- finite-difference stencils ---------------------------------------------
+ * Compact (the default): the central first differences and the (2d+1)-point
+ * second difference of Sec. 1.2.2.  Isotropic (lco_set_stencil(1)), the
+ * alternative the closing remarks of Sec. 2.2 point to for cutting spurious
+ * currents: derivatives from the lattice's own velocity set and weights,
+ *   d_g V = (1/cs2) sum_i w_i c_ig V(x + c_i),
+ *   lap V = (2/cs2) sum_i w_i [V(x + c_i) - V(x)],
+ * exact on linear and quadratic fields, with leading errors that do not
+ * depend on the direction.  The mode applies to grad Q, lap Q, the body
+ * force and grad u of lco_run_coll, lco_fields and lco_observe (the velocity
+ * set is that of the lattice argument); lco_rate and lco_stress are always
+ * compact.  `iso` below is that velocity set, or NULL for compact. */
+static int g_stencil = 0;
+
+int lco_set_stencil(int mode) {
+  if (mode != 0 && mode != 1) return -1;
+  g_stencil = mode;
+  return 0;
+}
+
+int lco_stencil(void) { return g_stencil; }
+
 /* Full symmetric traceless tensor from the five stored components
  * (uniaxial definition and symmetry of Q, Sec. 1.1). */
 static void full_Q(const double *q5, size_t N, size_t s, double Q[3][3]) {
@@ -146,8 +175,22 @@ static void full_Q(const double *q5, size_t N, size_t s, double Q[3][3]) {
   Q[2][0] = xz; Q[2][1] = yz; Q[2][2] = -xx - yy;
 }
 
-/* Central first differences, Sec. 1.2.2:  dQ[g][a][b] = d_g Q_ab. */
-static void grad_Q(const grid_t *g, const double *q5, size_t s, double dQ[3][3][3]) {
+/* First differences:  dQ[g][a][b] = d_g Q_ab; central (Sec. 1.2.2) or
+ * isotropic. */
+static void grad_Q(const grid_t *g, const lattice_t *iso, const double *q5, size_t s, double dQ[3][3][3]) {
+  if (iso) {
+    for (int gg = 0; gg < 3; gg++)
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) dQ[gg][a][b] = 0.0;
+    for (int i = 1; i < iso->q; i++) {
+      double Qi[3][3];
+      full_Q(q5, g->N, displaced(g, s, iso->c[i]), Qi);
+      for (int gg = 0; gg < 3; gg++)
+        for (int a = 0; a < 3; a++)
+          for (int b = 0; b < 3; b++) dQ[gg][a][b] += iso->w[i] * iso->c[i][gg] * Qi[a][b] / CS2;
+    }
+    return;
+  }
   for (int gg = 0; gg < 3; gg++) {
     double Qp[3][3], Qm[3][3];
     full_Q(q5, g->N, shift(g, s, gg, +1), Qp);
@@ -157,12 +200,22 @@ static void grad_Q(const grid_t *g, const double *q5, size_t s, double dQ[3][3][
   }
 }
 
-/* Compact second-order Laplacian: sum over axes of V(x+e) - 2V(x) + V(x-e). */
-static void lap_Q(const grid_t *g, const double *q5, size_t s, double L[3][3]) {
+/* Laplacian: compact, the sum over axes of V(x+e) - 2V(x) + V(x-e); or
+ * isotropic. */
+static void lap_Q(const grid_t *g, const lattice_t *iso, const double *q5, size_t s, double L[3][3]) {
   double Q0[3][3];
   full_Q(q5, g->N, s, Q0);
   for (int a = 0; a < 3; a++)
     for (int b = 0; b < 3; b++) L[a][b] = 0.0;
+  if (iso) {
+    for (int i = 1; i < iso->q; i++) {
+      double Qi[3][3];
+      full_Q(q5, g->N, displaced(g, s, iso->c[i]), Qi);
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) L[a][b] += 2.0 * iso->w[i] * (Qi[a][b] - Q0[a][b]) / CS2;
+    }
+    return;
+  }
   for (int gg = 0; gg < 3; gg++) {
     double Qp[3][3], Qm[3][3];
     full_Q(q5, g->N, shift(g, s, gg, +1), Qp);
@@ -295,16 +348,16 @@ void lco_source(int lattice, double tau, const double *u, const double *F, doubl
 /* ---- whole-grid stages --------------------------------------------------- */
 
 /* H (9 per site) and tau (9 per site) from Q. */
-static void stage_H_tau(const grid_t *g, const double *p, const double *q5,
+static void stage_H_tau(const grid_t *g, const lattice_t *iso, const double *p, const double *q5,
                         double *H9, double *tau9) {
   const size_t N = g->N;
 #pragma omp parallel for schedule(static)
   for (size_t s = 0; s < N; s++) {
     double Q[3][3], L[3][3], H[3][3], dQ[3][3][3], tau[3][3];
     full_Q(q5, N, s, Q);
-    lap_Q(g, q5, s, L);
+    lap_Q(g, iso, q5, s, L);
     molecular_field(Q, L, p, H);
-    grad_Q(g, q5, s, dQ);
+    grad_Q(g, iso, q5, s, dQ);
     stress(Q, H, dQ, p, tau);
     for (int a = 0; a < 3; a++)
       for (int b = 0; b < 3; b++) {
@@ -314,9 +367,9 @@ static void stage_H_tau(const grid_t *g, const double *p, const double *q5,
   }
 }
 
-/* Body force F_a = d_b tau_ab (central differences), then rho and the
- * force-corrected velocity of Eq. (9). */
-static void stage_force_moments(const grid_t *g, const lattice_t *L, const double *tau9,
+/* Body force F_a = d_b tau_ab (central or isotropic differences), then rho
+ * and the force-corrected velocity of Eq. (9). */
+static void stage_force_moments(const grid_t *g, const lattice_t *L, const lattice_t *iso, const double *tau9,
                                 const double *f, double *F3, double *rho1, double *u3) {
   const size_t N = g->N;
 #pragma omp parallel for schedule(static)
@@ -324,6 +377,13 @@ static void stage_force_moments(const grid_t *g, const lattice_t *L, const doubl
     double F[3];
     for (int a = 0; a < 3; a++) {
       F[a] = 0.0;
+      if (iso) {
+        for (int i = 1; i < iso->q; i++) {
+          const size_t si = displaced(g, s, iso->c[i]);
+          for (int b = 0; b < 3; b++) F[a] += iso->w[i] * iso->c[i][b] * tau9[(a * 3 + b) * N + si] / CS2;
+        }
+        continue;
+      }
       for (int b = 0; b < 3; b++) {
         size_t sp = shift(g, s, b, +1), sm = shift(g, s, b, -1);
         F[a] += (tau9[(a * 3 + b) * N + sp] - tau9[(a * 3 + b) * N + sm]) / 2.0;
@@ -344,9 +404,19 @@ static void stage_force_moments(const grid_t *g, const lattice_t *L, const doubl
   }
 }
 
-/* Velocity gradient G[a][b] = d_b u_a at site s. */
-static void velocity_gradient(const grid_t *g, const double *u3, size_t s, double G[3][3]) {
+/* Velocity gradient G[a][b] = d_b u_a at site s (central or isotropic). */
+static void velocity_gradient(const grid_t *g, const lattice_t *iso, const double *u3, size_t s, double G[3][3]) {
   const size_t N = g->N;
+  if (iso) {
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) G[a][b] = 0.0;
+    for (int i = 1; i < iso->q; i++) {
+      const size_t si = displaced(g, s, iso->c[i]);
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) G[a][b] += iso->w[i] * iso->c[i][b] * u3[a * N + si] / CS2;
+    }
+    return;
+  }
   for (int a = 0; a < 3; a++)
     for (int b = 0; b < 3; b++) {
       size_t sp = shift(g, s, b, +1), sm = shift(g, s, b, -1);
@@ -356,17 +426,17 @@ static void velocity_gradient(const grid_t *g, const double *u3, size_t s, doubl
 
 /* Rate of the five stored components for the tensor field q5, with a given
  * velocity field u3 (3 per site).  Optional full outputs S9, H9. */
-static void stage_rate(const grid_t *g, const double *p, const double *q5, const double *u3,
+static void stage_rate(const grid_t *g, const lattice_t *iso, const double *p, const double *q5, const double *u3,
                        double *R5, double *S9, double *H9) {
   const size_t N = g->N;
 #pragma omp parallel for schedule(static)
   for (size_t s = 0; s < N; s++) {
     double Q[3][3], L[3][3], H[3][3], dQ[3][3][3], G[3][3], R[3][3], S[3][3], u[3];
     full_Q(q5, N, s, Q);
-    lap_Q(g, q5, s, L);
+    lap_Q(g, iso, q5, s, L);
     molecular_field(Q, L, p, H);
-    grad_Q(g, q5, s, dQ);
-    velocity_gradient(g, u3, s, G);
+    grad_Q(g, iso, q5, s, dQ);
+    velocity_gradient(g, iso, u3, s, G);
     for (int a = 0; a < 3; a++) u[a] = u3[a * N + s];
     be_rate(Q, H, dQ, u, G, p, R, S);
     store5(R, R5, N, s);
@@ -409,11 +479,12 @@ int lco_fields(int lattice, int nx, int ny, int nz, const double *p,
   double *qp = malloc(5 * N * sizeof(double));
   double *Rp5 = malloc(5 * N * sizeof(double));
   if (!tau9 || !H9 || !F3 || !u3 || !rho || !R5 || !qp || !Rp5) return -2;
-  stage_H_tau(&g, p, q5, H9, tau9);
-  stage_force_moments(&g, &L, tau9, f, F3, rho, u3);
-  stage_rate(&g, p, q5, u3, R5, S_o, NULL);
+  const lattice_t *iso = g_stencil ? &L : NULL;
+  stage_H_tau(&g, iso, p, q5, H9, tau9);
+  stage_force_moments(&g, &L, iso, tau9, f, F3, rho, u3);
+  stage_rate(&g, iso, p, q5, u3, R5, S_o, NULL);
   for (size_t k = 0; k < 5 * N; k++) qp[k] = q5[k] + R5[k];
-  stage_rate(&g, p, qp, u3, Rp5, NULL, NULL);
+  stage_rate(&g, iso, p, qp, u3, Rp5, NULL, NULL);
   if (rho_o) memcpy(rho_o, rho, N * sizeof(double));
   if (u_o) memcpy(u_o, u3, 3 * N * sizeof(double));
   if (F_o) memcpy(F_o, F3, 3 * N * sizeof(double));
@@ -424,7 +495,7 @@ int lco_fields(int lattice, int nx, int ny, int nz, const double *p,
   if (G_o) {
     for (size_t s = 0; s < N; s++) {
       double G[3][3];
-      velocity_gradient(&g, u3, s, G);
+      velocity_gradient(&g, iso, u3, s, G);
       for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) G_o[(a * 3 + b) * N + s] = G[a][b];
     }
@@ -442,7 +513,7 @@ int lco_rate(int nx, int ny, int nz, const double *p, const double *q5, const do
   if (nx < 1 || ny < 1 || nz < 1) return -1;
   g.nx = nx; g.ny = ny; g.nz = nz;
   g.N = (size_t)nx * (size_t)ny * (size_t)nz;
-  stage_rate(&g, p, q5, u3, R5, S9, H9);
+  stage_rate(&g, NULL, p, q5, u3, R5, S9, H9);
   return 0;
 }
 
@@ -455,7 +526,7 @@ int lco_stress(int nx, int ny, int nz, const double *p, const double *q5,
   g.N = (size_t)nx * (size_t)ny * (size_t)nz;
   const size_t N = g.N;
   double *tau9 = tau_o ? tau_o : malloc(9 * N * sizeof(double));
-  stage_H_tau(&g, p, q5, H_o, tau9);
+  stage_H_tau(&g, NULL, p, q5, H_o, tau9);
   if (F_o) {
     for (size_t s = 0; s < N; s++)
       for (int a = 0; a < 3; a++) {
@@ -583,11 +654,12 @@ static void one_step(const grid_t *g, const lattice_t *L, const double *p, const
                      double *R5, double *qp, double *Rp5) {
   const size_t N = g->N;
   const double tau = p[5];
-  stage_H_tau(g, p, q5, NULL, tau9);
-  stage_force_moments(g, L, tau9, f, F3, rho, u3);
-  stage_rate(g, p, q5, u3, R5, NULL, NULL);          /* step 1 */
+  const lattice_t *iso = g_stencil ? L : NULL;
+  stage_H_tau(g, iso, p, q5, NULL, tau9);
+  stage_force_moments(g, L, iso, tau9, f, F3, rho, u3);
+  stage_rate(g, iso, p, q5, u3, R5, NULL, NULL);          /* step 1 */
   for (size_t k = 0; k < 5 * N; k++) qp[k] = q5[k] + R5[k]; /* step 2 */
-  stage_rate(g, p, qp, u3, Rp5, NULL, NULL);         /* step 3 */
+  stage_rate(g, iso, p, qp, u3, Rp5, NULL, NULL);         /* step 3 */
   for (size_t k = 0; k < 5 * N; k++)                 /* steps 4-5 */
     q5_out[k] = q5[k] + (R5[k] + Rp5[k]) / 2.0;
 #pragma omp parallel for schedule(static)

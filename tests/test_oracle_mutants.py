@@ -2,8 +2,8 @@
 
 Each case below plants one mistake in a copy of the oracle's C source (a
 dropped term, a wrong sign, factor or index, a transposed operand), builds
-it, and runs the pin suites (tests/test_oracle_pins.py and
-tests/test_oracle_mrt.py, without the long runs) against that build in a
+it, and runs the pin suites (tests/test_oracle_pins.py, tests/test_oracle_mrt.py
+and tests/test_oracle_stencil.py, without the long runs) against that build in a
 child process.  A mistake passes this test only if at least one pin fails on
 it.  The unmodified source passing the same pins is the ordinary suite.
 Everything runs on the CPU.
@@ -19,7 +19,7 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lc_oracle.c")
-PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_mrt.py"]
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_mrt.py", "tests/test_oracle_stencil.py"]
 
 # name -> (text of the correct source, the same text with the mistake);
 # each original text occurs exactly once in the source
@@ -85,6 +85,19 @@ MUTANTS = {
     # without the 1/|m_k|^2 of the orthogonal inverse
     "mrt_forcing": ("(1.0 - op->s[k] / 2.0) * mgk", "(1.0 - op->s[k]) * mgk"),
     "mrt_inverse_norm": ("for (int k = 0; k < q; k++) ms[k] /= op->norm2[k];", ";"),
+    # isotropic stencils: Laplacian without its factor 2, gradient without
+    # 1/cs2, neighbours taken against the velocity, divergence on the first
+    # index of the stress, velocity gradient along the wrong axis
+    "iso_lap_factor": ("L[a][b] += 2.0 * iso->w[i] * (Qi[a][b] - Q0[a][b]) / CS2;",
+                       "L[a][b] += iso->w[i] * (Qi[a][b] - Q0[a][b]) / CS2;"),
+    "iso_grad_cs2": ("dQ[gg][a][b] += iso->w[i] * iso->c[i][gg] * Qi[a][b] / CS2;",
+                     "dQ[gg][a][b] += iso->w[i] * iso->c[i][gg] * Qi[a][b];"),
+    "iso_displaced_sign": ("return site(g, x + c[0], y + c[1], z + c[2]);",
+                           "return site(g, x - c[0], y - c[1], z - c[2]);"),
+    "iso_force_first_index": ("F[a] += iso->w[i] * iso->c[i][b] * tau9[(a * 3 + b) * N + si] / CS2;",
+                              "F[a] += iso->w[i] * iso->c[i][b] * tau9[(b * 3 + a) * N + si] / CS2;"),
+    "iso_grad_u_axis": ("G[a][b] += iso->w[i] * iso->c[i][b] * u3[a * N + si] / CS2;",
+                        "G[a][b] += iso->w[i] * iso->c[i][a] * u3[a * N + si] / CS2;"),
 }
 
 

@@ -1,0 +1,261 @@
+"""Pins of the oracle's isotropic difference stencils (CPU).
+
+The isotropic option takes every derivative of the step from the lattice's
+velocity set and weights (Sec. 2.2 closes on such stencils as the way to cut
+spurious currents):
+  d_g V = (1/cs2) sum_i w_i c_ig V(x + c_i),  lap V = (2/cs2) sum_i w_i [V(x + c_i) - V(x)].
+Each pin checks it against something the mathematics fixes:
+  - on a field that varies along one lattice axis only, both stencils reduce
+    to the three-point central differences, so a whole isotropic run equals
+    the compact one to rounding;
+  - both are exact on linear and quadratic fields (second-order lattice
+    isotropy), checked against the polynomials' analytic derivatives;
+  - their leading errors do not depend on the direction: on plane waves of
+    equal |k| the Laplacian's eigenvalue is -k^2 + cs2 k^4 / 4 and the
+    gradient's k (1 - cs2 k^2 / 2), up to O(k^6) and O(k^5) (fourth-order
+    lattice isotropy), where the compact stencils differ at O(k^4) and O(k^3);
+  - the discrete divergence of the stress sums to zero over a periodic grid,
+    so a run conserves mass and lattice momentum.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_13415_amd import inputs
+
+D2, D3 = oracle.D2Q9, oracle.D3Q19
+BASE = inputs.WORKLOAD_PARAMS
+CS2 = 1.0 / 3.0
+
+
+def _feq_populations(lat, rho, u):
+    """Second-order equilibrium populations of a velocity field u (3, nz, ny,
+    nx) at density rho (the tests check that the oracle recovers u)."""
+    c, w = oracle.lattice(lat)
+    cu = np.einsum("ia,a...->i...", c.astype(np.float64), u) / CS2
+    uu = (u * u).sum(axis=0) / CS2
+    return rho * w.reshape(-1, 1, 1, 1) * (1 + cu + cu * cu / 2 - uu / 2)
+
+
+# ------------------------------------------------ reduction on 1D fields
+@pytest.mark.parametrize("lat,axis", [(D3, 0), (D3, 1), (D3, 2), (D2, 0), (D2, 1)])
+def test_isotropic_equals_compact_on_fields_varying_along_one_axis(lat, axis):
+    """Fields that vary along one lattice axis only: the isotropic sums
+    collapse onto the central differences, for grad Q, lap Q, the body force
+    and grad u alike.  Five steps and every intermediate of a step agree."""
+    rng = np.random.default_rng(40 + axis + 3 * lat)
+    n = 14
+    shape = [3, 3, 3] if lat == D3 else [1, 3, 3]  # (nz, ny, nx)
+    shape[2 - axis] = n
+    line = [1] * 3
+    line[2 - axis] = n
+    q5 = np.broadcast_to(inputs.random_q5(tuple(line), rng, amp=0.2), (5,) + tuple(shape)).copy()
+    q = 19 if lat == D3 else 9
+    rel = np.broadcast_to(inputs.random_rel(q, tuple(line), rng, amp=5e-3), (q,) + tuple(shape))
+    f = oracle.rest_populations(lat, shape, rel=rel)
+    fc = oracle.fields(lat, f, q5, BASE, stencil="compact")
+    fi = oracle.fields(lat, f, q5, BASE, stencil="isotropic")
+    for k in fc:
+        scale = max(1.0, float(np.abs(fc[k]).max()))
+        assert np.abs(fi[k] - fc[k]).max() < 1e-13 * scale, k
+    assert np.abs(fc["F"]).max() > 1e-4  # the field does drive a flow
+    a_c, q_c = oracle.run(lat, f, q5, BASE, 5, stencil="compact")
+    a_i, q_i = oracle.run(lat, f, q5, BASE, 5, stencil="isotropic")
+    assert np.abs(a_i - a_c).max() < 1e-13 and np.abs(q_i - q_c).max() < 1e-13
+
+
+def test_compact_stencil_is_default_and_restored():
+    assert oracle._load().lco_stencil() == 0
+    with pytest.raises(ValueError):
+        oracle.fields(D2, oracle.rest_populations(D2, (1, 4, 4)), np.zeros((5, 1, 4, 4)), BASE, stencil="wide")
+    assert oracle._load().lco_stencil() == 0
+
+
+# ------------------------------------------------ exactness on polynomials
+def _coords(shape):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.stack([x, y, z]).astype(np.float64)
+
+
+def _interior(shape, r, dim):
+    nz, ny, nx = shape
+    zs = slice(r, nz - r) if dim == 3 else slice(0, 1)
+    return (zs, slice(r, ny - r), slice(r, nx - r))
+
+
+def _quadratic(X, rng, dim, amp, harmonic=False):
+    """p(x) = x.A.x + b.x + c with random A (symmetric, zero outside the
+    active dimensions; traceless when harmonic) and its gradient/Laplacian."""
+    A = np.zeros((3, 3))
+    A[:dim, :dim] = rng.standard_normal((dim, dim))
+    A = amp * (A + A.T) / 2
+    if harmonic:
+        A[np.arange(dim), np.arange(dim)] -= np.trace(A) / dim
+    b = np.zeros(3)
+    b[:dim] = amp * rng.standard_normal(dim)
+    c0 = amp * rng.standard_normal()
+    p = np.einsum("ab,a...,b...->...", A, X, X) + np.einsum("a,a...->...", b, X) + c0
+    grad = 2 * np.einsum("ab,b...->a...", A, X) + b.reshape((3,) + (1,) * (X.ndim - 1))
+    return p, grad, 2 * np.trace(A), 2 * A
+
+
+@pytest.mark.parametrize("lat,dim", [(D2, 2), (D3, 3)])
+def test_isotropic_laplacian_exact_on_quadratic_fields(lat, dim):
+    """A0 = 0 leaves H = K lap Q; on quadratic components the Laplacian is a
+    constant, reproduced exactly away from the periodic wrap."""
+    rng = np.random.default_rng(50 + lat)
+    shape = (8, 8, 8) if dim == 3 else (1, 10, 10)
+    X = _coords(shape)
+    q5 = np.zeros((5,) + shape)
+    lap5 = np.zeros(5)
+    for k in range(5):
+        q5[k], _, lap5[k], _ = _quadratic(X, rng, dim, 0.01)
+    K = 0.7
+    p = (0.0, 2.7, K, 0.3, 0.7, 1.0)
+    fl = oracle.fields(lat, oracle.rest_populations(lat, shape), q5, p, stencil="isotropic")
+    H = fl["H"]
+    sl = _interior(shape, 1, dim)
+    want = {(0, 0): lap5[0], (0, 1): lap5[1], (0, 2): lap5[2], (1, 1): lap5[3], (1, 2): lap5[4],
+            (2, 2): -lap5[0] - lap5[3]}
+    for (a, b), v in want.items():
+        assert np.abs(H[a, b][sl] - K * v).max() < 1e-13, (a, b)
+        assert np.abs(H[b, a][sl] - K * v).max() < 1e-13, (b, a)
+    # the compact stencil agrees on quadratics too (both are second order)
+    Hc = oracle.fields(lat, oracle.rest_populations(lat, shape), q5, p)["H"]
+    assert np.abs(Hc[0, 1][sl] - K * lap5[1]).max() < 1e-13
+
+
+@pytest.mark.parametrize("lat,dim", [(D2, 2), (D3, 3)])
+def test_isotropic_gradients_exact_on_quadratic_fields(lat, dim):
+    """Harmonic quadratic Q (lap Q = 0) with A0 = 0, xi = 0: H = 0 and the
+    stress is -K d_a Q_gn d_b Q_gn, built from the isotropic gradient of Q;
+    its isotropic divergence (the body force) is exact too, two sites away
+    from the wrap.  Then Q = 0 with a quadratic velocity: grad u exact."""
+    rng = np.random.default_rng(60 + lat)
+    shape = (9, 9, 9) if dim == 3 else (1, 12, 12)
+    X = _coords(shape)
+    q5 = np.zeros((5,) + shape)
+    g5 = np.zeros((5, 3) + shape)
+    h5 = np.zeros((5, 3, 3))
+    for k in range(5):
+        q5[k], g5[k], _, h5[k] = _quadratic(X, rng, dim, 0.01, harmonic=True)
+    # Qzz = -Qxx - Qyy is harmonic too; the full tensor's derivatives
+    idx = {(0, 0): 0, (0, 1): 1, (0, 2): 2, (1, 1): 3, (1, 2): 4}
+    dQ = np.zeros((3, 3, 3) + shape)  # dQ[g, a, b] = d_g Q_ab
+    d2Q = np.zeros((3, 3, 3, 3))  # d2Q[g, d, a, b] = d_g d_d Q_ab
+    for (a, b), k in idx.items():
+        dQ[:, a, b] = dQ[:, b, a] = g5[k]
+        d2Q[:, :, a, b] = d2Q[:, :, b, a] = h5[k]
+    dQ[:, 2, 2] = -g5[0] - g5[3]
+    d2Q[:, :, 2, 2] = -h5[0] - h5[3]
+    K = 0.9
+    p = (0.0, 2.7, K, 0.3, 0.0, 1.0)
+    fl = oracle.fields(lat, oracle.rest_populations(lat, shape), q5, p, stencil="isotropic")
+    tau_want = -K * np.einsum("agn...,bgn...->ab...", dQ, dQ)
+    # F_a = d_b tau_ab = -K sum (d_a d_b Q_gn d_b Q_gn + d_a Q_gn lap Q_gn), the second term zero
+    F_want = -K * np.einsum("abgn,bgn...->a...", d2Q, dQ)
+    s1, s2 = _interior(shape, 1, dim), _interior(shape, 2, dim)
+    assert np.abs(fl["H"][(slice(None), slice(None)) + s1]).max() < 1e-14
+    assert np.abs(fl["tau"][(slice(None), slice(None)) + s1] - tau_want[(slice(None), slice(None)) + s1]).max() < 1e-14
+    assert np.abs(fl["F"][(slice(None),) + s2] - F_want[(slice(None),) + s2]).max() < 1e-14
+    assert np.abs(F_want).max() > 1e-5
+
+    # grad u: Q = 0 (no stress, no force), populations at equilibrium with a
+    # quadratic velocity field
+    u = np.zeros((3,) + shape)
+    G_want = np.zeros((3, 3) + shape)
+    for a in range(dim):
+        u[a], G_want[a], _, _ = _quadratic(X, rng, dim, 2e-4)
+    f = _feq_populations(lat, 1.0, u)
+    fl = oracle.fields(lat, f, np.zeros((5,) + shape), BASE, stencil="isotropic")
+    assert np.abs(fl["u"] - u).max() < 1e-15
+    assert np.abs(fl["G"][(slice(None), slice(None)) + s1] - G_want[(slice(None), slice(None)) + s1]).max() < 1e-15
+
+
+# ------------------------------------------------ isotropy of the leading error
+def _waves(n, ms):
+    """Plane waves cos(k.x) on an n-periodic grid for integer wave vectors m."""
+    return [(2 * np.pi * np.asarray(m, dtype=np.float64) / n) for m in ms]
+
+
+def _laplacian_eigenvalue(lat, shape, k, stencil):
+    X = _coords(shape)
+    phase = np.einsum("a,a...->...", k, X)
+    q5 = np.zeros((5,) + shape)
+    q5[1] = 1e-3 * np.cos(phase)  # Q_xy
+    p = (0.0, 2.7, 1.0, 0.3, 0.7, 1.0)
+    H = oracle.fields(lat, oracle.rest_populations(lat, shape), q5, p, stencil=stencil)["H"][0, 1]
+    return float((H * q5[1]).sum() / (q5[1] ** 2).sum())
+
+
+def _gradient_eigenvalue(lat, shape, k, stencil):
+    X = _coords(shape)
+    phase = np.einsum("a,a...->...", k, X)
+    u = np.zeros((3,) + shape)
+    u[0] = 1e-4 * np.sin(phase)
+    f = _feq_populations(lat, 1.0, u)
+    G = oracle.fields(lat, f, np.zeros((5,) + shape), BASE, stencil=stencil)["G"][0]
+    c = 1e-4 * np.cos(phase)
+    return np.array([float((G[b] * c).sum() / (c * c).sum()) for b in range(3)])
+
+
+@pytest.mark.parametrize("lat,n,ms", [
+    (D2, 60, [(5, 0, 0), (3, 4, 0), (4, 3, 0)]),
+    (D3, 30, [(5, 0, 0), (0, 3, 4), (4, 0, 3)]),
+])
+def test_isotropic_laplacian_error_does_not_depend_on_direction(lat, n, ms):
+    shape = (n, n, n) if lat == D3 else (1, n, n)
+    ks = _waves(n, ms)
+    kk = float(ks[0] @ ks[0])
+    iso = [_laplacian_eigenvalue(lat, shape, k, "isotropic") for k in ks]
+    cmp_ = [_laplacian_eigenvalue(lat, shape, k, "compact") for k in ks]
+    # the compact eigenvalue is the textbook sum of 2 cos k_a - 2
+    for k, lam in zip(ks, cmp_):
+        assert abs(lam - float(np.sum(2 * np.cos(k) - 2))) < 1e-12
+    # isotropic: -k^2 + cs2 k^4 / 4 + O(k^6), in every direction
+    for lam in iso:
+        assert abs(lam - (-kk + CS2 * kk * kk / 4)) < kk ** 3 / 100
+    spread_iso = max(iso) - min(iso)
+    spread_cmp = max(cmp_) - min(cmp_)
+    assert spread_cmp > 0.1 * kk * kk / 12
+    assert spread_iso < 0.05 * spread_cmp
+
+
+@pytest.mark.parametrize("lat,n,ms", [
+    (D2, 40, [(5, 0, 0), (3, 4, 0), (4, 3, 0)]),
+    (D3, 40, [(5, 0, 0), (0, 3, 4), (4, 0, 3)]),
+])
+def test_isotropic_gradient_error_does_not_depend_on_direction(lat, n, ms):
+    shape = (n, n, n) if lat == D3 else (1, n, n)
+    ks = _waves(n, ms)
+    kk = float(ks[0] @ ks[0])
+    for k in ks:
+        g_iso = _gradient_eigenvalue(lat, shape, k, "isotropic")
+        g_cmp = _gradient_eigenvalue(lat, shape, k, "compact")
+        assert np.abs(g_cmp - np.sin(k)).max() < 1e-12  # central difference: sin k_a
+        # isotropic: k (1 - cs2 k^2 / 2) + O(k^5): parallel to k, with a
+        # magnitude that depends on |k| only
+        assert np.abs(g_iso - k * (1 - CS2 * kk / 2)).max() < kk ** 2.5 / 20
+    mags_iso = [np.linalg.norm(_gradient_eigenvalue(lat, shape, k, "isotropic")) for k in ks]
+    mags_cmp = [np.linalg.norm(np.sin(k)) for k in ks]
+    assert max(mags_iso) - min(mags_iso) < 0.1 * (max(mags_cmp) - min(mags_cmp))
+
+
+# ------------------------------------------------ conservation
+@pytest.mark.parametrize("lat,shape", [(D2, (1, 24, 20)), (D3, (6, 8, 10))])
+def test_isotropic_run_conserves_mass_and_momentum(lat, shape):
+    rng = np.random.default_rng(70 + lat)
+    q5 = inputs.random_q5(shape, rng, amp=0.2)
+    q = 19 if lat == D3 else 9
+    f = oracle.rest_populations(lat, shape, rel=inputs.random_rel(q, shape, rng, amp=5e-3))
+    o0 = oracle.observe(lat, f, q5, BASE, stencil="isotropic")
+    f1, q1 = oracle.run(lat, f, q5, BASE, 40, stencil="isotropic")
+    o1 = oracle.observe(lat, f1, q1, BASE, stencil="isotropic")
+    assert abs(o1["mass"] - o0["mass"]) < 1e-11 * o0["mass"]
+    assert np.abs(o1["mom"] - o0["mom"]).max() < 1e-12
+    assert o1["umax"] > 1e-5  # the run does move the fluid
+    # the isotropic body force differs from the compact one on such fields
+    fc = oracle.fields(lat, f, q5, BASE)["F"]
+    fi = oracle.fields(lat, f, q5, BASE, stencil="isotropic")["F"]
+    assert np.abs(fi - fc).max() > 1e-3 * np.abs(fc).max()
