@@ -85,6 +85,10 @@ typedef int32_t lc_status;
 #define LC_COLL_BGK 0 /* single relaxation time (default) */
 #define LC_COLL_MRT 1 /* multiple relaxation times, standard orthogonal moment bases */
 
+/* Difference stencils for lc_set_stencil. */
+#define LC_STENCIL_COMPACT 0   /* central differences, (2d+1)-point Laplacian (default) */
+#define LC_STENCIL_ISOTROPIC 1 /* from the lattice velocities and weights */
+
 /* Kernel variants for lc_set_variant. */
 #define LC_VARIANT_AUTO 0
 #define LC_VARIANT_STAGED 1 /* one kernel per stage, intermediates in scratch */
@@ -185,8 +189,9 @@ lc_status lc_init(const lc_grid *grid, const lc_params *params, const lc_buffers
 lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 
 /* Choose the kernel variant (LC_VARIANT_*) of the step of Sec. 1.2 (the
- * same arithmetic in each; SPLIT and FUSED agree bit for bit).  AUTO picks
- * the fastest the build provides (the two-sweep variant).  FUSED runs every
+ * same arithmetic in each; SPLIT and FUSED agree bit for bit).  AUTO (the
+ * default) picks the fastest the build provides for the context's stencil:
+ * the two-sweep variant, or the staged one for LC_STENCIL_ISOTROPIC.  FUSED runs every
  * stage of a step in one pass over the grid: a block recomputes the
  * stress, moments and predictor on shrinking rings around its tile instead
  * of reading them back from HBM.  LC_EUNSUPPORTED for the staged variant in
@@ -208,6 +213,23 @@ lc_status lc_set_variant(lc_ctx *ctx, int32_t variant);
  * wrong count or a rate outside (0, 2).  The reverse step supports BGK
  * only (LC_EUNSUPPORTED otherwise). */
 lc_status lc_set_collision(lc_ctx *ctx, int32_t kind, const double *rates, int32_t nrates);
+
+/* Difference stencil of every derivative in the step: grad Q and lap Q
+ * (Eqs. 2, 4, 6), the divergence of the stress (the body force of Sec.
+ * 1.2.1) and grad u (Eq. 2).  LC_STENCIL_COMPACT (the default): the
+ * second-order central differences and compact Laplacian of Sec. 1.2.2.
+ * LC_STENCIL_ISOTROPIC: the option the closing remarks of Sec. 2.2 point to
+ * for reducing spurious currents, derivatives from the lattice's own
+ * velocities c_i and weights w_i (c_s^2 = 1/3):
+ *   d_g V = 3 sum_i w_i c_ig V(x + c_i),  lap V = 6 sum_i w_i [V(x + c_i) - V(x)],
+ * second order as well, with leading errors independent of direction.
+ * Applies to the steps, exports and observables after the call.  The
+ * isotropic stencils run in the staged variant (lc_step returns
+ * LC_EUNSUPPORTED with LC_VARIANT_SPLIT or LC_VARIANT_FUSED set explicitly),
+ * in LC_FP64 and LC_FP32_DEV (LC_EUNSUPPORTED otherwise), with either
+ * collision; the reverse step and the batched form use the compact
+ * stencils only.  LC_EINVAL for an unknown stencil. */
+lc_status lc_set_stencil(lc_ctx *ctx, int32_t stencil);
 
 /* Planes each block marches through along z in the two-sweep kernels
  * (>= 1; larger chunks recompute fewer boundary planes, smaller chunks give

@@ -63,8 +63,8 @@ __global__ void __launch_bounds__(256) export_fq(const S* __restrict__ fb, const
 }
 
 // Derived fields: 0 rho, 1 u (3), 2 force (3), 3 S.  Needs tau (QT) in
-// scratch.
-template <int LAT, typename S, bool DEV, typename QT = S>
+// scratch; ST: the difference stencil of the body force.
+template <int LAT, typename S, bool DEV, typename QT = S, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(256) export_derived(const S* __restrict__ fin, const QT* __restrict__ Q,
                                                       const QT* __restrict__ tau, double* __restrict__ out,
                                                       int which, GridDims g) {
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) export_derived(const S* __restrict__ fin,
   }
   const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
   QT FQ[3];
-  body_force<LAT, QT>(tau, N, s, nb, FQ);
+  body_force<LAT, QT, ST>(tau, N, s, nb, FQ);
   const S F[3] = {S(FQ[0]), S(FQ[1]), S(FQ[2])};
   S f[L::q];
   gather_f<LAT, S>(fin, N, s, nb, f);
@@ -138,7 +138,7 @@ __device__ __forceinline__ void block_reduce_obs(double (&v)[OBS_W], double* __r
   }
 }
 
-template <int LAT, typename S, bool DEV, typename QT = S>
+template <int LAT, typename S, bool DEV, typename QT = S, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(256) observe_partial(const S* __restrict__ fin, const QT* __restrict__ Q,
                                                        const QT* __restrict__ tau, double* __restrict__ partial,
                                                        GridDims g, int half_axis, int want_u) {
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) observe_partial(const S* __restrict__ fin
     v[3] = jz;
     if (want_u) {
       QT FQ[3];
-      body_force<LAT, QT>(tau, N, s, nb, FQ);
+      body_force<LAT, QT, ST>(tau, N, s, nb, FQ);
       const S F[3] = {S(FQ[0]), S(FQ[1]), S(FQ[2])};
       S rho, u[3];
       moments<LAT, S, DEV>(f, F, rho, u);

@@ -152,7 +152,8 @@ struct lc_ctx {
   int parity;
   int64_t step;
   bool loaded;
-  int variant;
+  int variant;     // LC_VARIANT_* as requested (AUTO resolved at each step)
+  int stencil = LC_STENCIL_COMPACT;  // LC_STENCIL_*
   int zchunk;  // 0: default
   int coll;        // LC_COLL_*
   double mrt[5];   // MRT rates of the ghost groups
@@ -246,13 +247,8 @@ static void ctx_end(lc_ctx* c, hipStream_t st, hipEvent_t a, int kind) {
 // ---------------------------------------------------------------------------
 // Dispatch helpers.  Each is instantiated for (lattice, S = population and
 // collision type, DEV = deviation storage, QT = order-tensor type).
-template <int LAT, typename S, bool DEV, typename QT = S>
-static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
-  if constexpr (!std::is_same<S, QT>::value) {
-    return fail(LC_EUNSUPPORTED, "the staged variant has no mixed-precision form");
-  } else {
-  if (c->g.precision == LC_FP32_SR)
-    return fail(LC_EUNSUPPORTED, "the staged variant has no stochastic-rounding form");
+template <int LAT, typename S, bool DEV, int ST>
+static lc_status run_steps_staged_st(lc_ctx* c, int64_t n) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = ctx_coef<S>(c);
   char* scr = static_cast<char*>(c->b.scratch);
@@ -266,17 +262,28 @@ static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
     S* f1 = static_cast<S*>(c->b.f[c->parity ^ 1]);
     const S* q0 = static_cast<const S*>(c->b.Q[c->parity]);
     S* q1 = static_cast<S*>(c->b.Q[c->parity ^ 1]);
-    hipLaunchKernelGGL((stage_tau<LAT, S>), grid, block, 0, c->stream, q0, tau, gd, k);
+    hipLaunchKernelGGL((stage_tau<LAT, S, ST>), grid, block, 0, c->stream, q0, tau, gd, k);
     if (c->coll == LC_COLL_MRT)
-      hipLaunchKernelGGL((stage_lb<LAT, S, DEV, true>), grid, block, 0, c->stream, f0, tau, f1, u, gd, k);
+      hipLaunchKernelGGL((stage_lb<LAT, S, DEV, true, ST>), grid, block, 0, c->stream, f0, tau, f1, u, gd, k);
     else
-      hipLaunchKernelGGL((stage_lb<LAT, S, DEV>), grid, block, 0, c->stream, f0, tau, f1, u, gd, k);
-    hipLaunchKernelGGL((stage_pred<LAT, S>), grid, block, 0, c->stream, q0, u, qp, rq, gd, k);
-    hipLaunchKernelGGL((stage_corr<LAT, S>), grid, block, 0, c->stream, q0, qp, rq, u, q1, gd, k);
+      hipLaunchKernelGGL((stage_lb<LAT, S, DEV, false, ST>), grid, block, 0, c->stream, f0, tau, f1, u, gd, k);
+    hipLaunchKernelGGL((stage_pred<LAT, S, ST>), grid, block, 0, c->stream, q0, u, qp, rq, gd, k);
+    hipLaunchKernelGGL((stage_corr<LAT, S, ST>), grid, block, 0, c->stream, q0, qp, rq, u, q1, gd, k);
     c->parity ^= 1;
     c->step++;
   }
   return hip_check(hipGetLastError(), "step launch");
+}
+
+template <int LAT, typename S, bool DEV, typename QT = S>
+static lc_status run_steps_staged(lc_ctx* c, int64_t n) {
+  if constexpr (!std::is_same<S, QT>::value) {
+    return fail(LC_EUNSUPPORTED, "the staged variant has no mixed-precision form");
+  } else {
+    if (c->g.precision == LC_FP32_SR)
+      return fail(LC_EUNSUPPORTED, "the staged variant has no stochastic-rounding form");
+    if (c->stencil == LC_STENCIL_ISOTROPIC) return run_steps_staged_st<LAT, S, DEV, STENCIL_ISO>(c, n);
+    return run_steps_staged_st<LAT, S, DEV, STENCIL_COMPACT>(c, n);
   }
 }
 
@@ -374,10 +381,20 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
   return hip_check(hipGetLastError(), "step launch");
 }
 
+// The variant a step runs: AUTO is the two-sweep variant, or the staged one
+// where only it provides the context's stencil.
+static int resolved_variant(const lc_ctx* c) {
+  if (c->variant != LC_VARIANT_AUTO) return c->variant;
+  return c->stencil == LC_STENCIL_ISOTROPIC ? LC_VARIANT_STAGED : LC_VARIANT_SPLIT;
+}
+
 template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps(lc_ctx* c, int64_t n) {
-  if (c->variant == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV, QT>(c, n);
-  if (c->variant == LC_VARIANT_FUSED) return run_steps_fused<LAT, S, DEV, QT>(c, n);
+  const int v = resolved_variant(c);
+  if (c->stencil == LC_STENCIL_ISOTROPIC && v != LC_VARIANT_STAGED)
+    return fail(LC_EUNSUPPORTED, "the isotropic stencils are provided by the staged variant");
+  if (v == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV, QT>(c, n);
+  if (v == LC_VARIANT_FUSED) return run_steps_fused<LAT, S, DEV, QT>(c, n);
   return run_steps_staged<LAT, S, DEV, QT>(c, n);
 }
 
@@ -386,8 +403,11 @@ static lc_status compute_tau(lc_ctx* c) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<QT> k = make_coef<QT>(c->p);
   QT* tau = reinterpret_cast<QT*>(static_cast<char*>(c->b.scratch) + c->L.off_tau);
-  hipLaunchKernelGGL((stage_tau<LAT, QT>), site_grid(c->g), site_block(), 0, c->stream,
-                     static_cast<const QT*>(c->b.Q[c->parity]), tau, gd, k);
+  const QT* q = static_cast<const QT*>(c->b.Q[c->parity]);
+  if (c->stencil == LC_STENCIL_ISOTROPIC)
+    hipLaunchKernelGGL((stage_tau<LAT, QT, STENCIL_ISO>), site_grid(c->g), site_block(), 0, c->stream, q, tau, gd, k);
+  else
+    hipLaunchKernelGGL((stage_tau<LAT, QT>), site_grid(c->g), site_block(), 0, c->stream, q, tau, gd, k);
   return hip_check(hipGetLastError(), "stress launch");
 }
 
@@ -417,8 +437,12 @@ static lc_status do_export(lc_ctx* c, int field, double* dst) {
   }
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, N};
   const QT* tau = reinterpret_cast<const QT*>(static_cast<char*>(c->b.scratch) + c->L.off_tau);
-  hipLaunchKernelGGL((export_derived<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream, f, q, tau,
-                     dst, which, gd);
+  if (c->stencil == LC_STENCIL_ISOTROPIC)
+    hipLaunchKernelGGL((export_derived<LAT, S, DEV, QT, STENCIL_ISO>), site_grid(c->g), site_block(), 0, c->stream, f,
+                       q, tau, dst, which, gd);
+  else
+    hipLaunchKernelGGL((export_derived<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream, f, q, tau,
+                       dst, which, gd);
   return hip_check(hipGetLastError(), "export launch");
 }
 
@@ -435,9 +459,14 @@ static lc_status do_observe_async(lc_ctx* c, uint32_t mask, int half_axis, doubl
   char* scr = static_cast<char*>(c->b.scratch);
   const QT* tau = reinterpret_cast<const QT*>(scr + c->L.off_tau);
   double* partial = reinterpret_cast<double*>(scr + c->L.off_partial);
-  hipLaunchKernelGGL((observe_partial<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream,
-                     static_cast<const S*>(c->b.f[c->parity]), static_cast<const QT*>(c->b.Q[c->parity]), tau,
-                     partial, gd, half_axis, want_u);
+  const S* f = static_cast<const S*>(c->b.f[c->parity]);
+  const QT* q = static_cast<const QT*>(c->b.Q[c->parity]);
+  if (c->stencil == LC_STENCIL_ISOTROPIC)
+    hipLaunchKernelGGL((observe_partial<LAT, S, DEV, QT, STENCIL_ISO>), site_grid(c->g), site_block(), 0, c->stream,
+                       f, q, tau, partial, gd, half_axis, want_u);
+  else
+    hipLaunchKernelGGL((observe_partial<LAT, S, DEV, QT>), site_grid(c->g), site_block(), 0, c->stream, f, q, tau,
+                       partial, gd, half_axis, want_u);
   hipLaunchKernelGGL(observe_final, dim3(1), dim3(256), 0, c->stream, partial, c->L.nblocks, res);
   return hip_check(hipGetLastError(), "observe launch");
 }
@@ -552,7 +581,8 @@ lc_status lc_init(const lc_grid* grid, const lc_params* params, const lc_buffers
   c->parity = 0;
   c->step = 0;
   c->loaded = false;
-  c->variant = LC_VARIANT_SPLIT;
+  c->variant = LC_VARIANT_AUTO;
+  c->stencil = LC_STENCIL_COMPACT;
   c->coll = LC_COLL_BGK;
   for (double& r : c->mrt) r = 0.0;
   c->zchunk = 0;
@@ -574,7 +604,7 @@ lc_status lc_set_variant(lc_ctx* c, int32_t variant) {
   clear_error();
   if (!c) return fail(LC_EINVAL, "ctx is NULL");
   if (variant == LC_VARIANT_AUTO || variant == LC_VARIANT_SPLIT) {
-    c->variant = LC_VARIANT_SPLIT;
+    c->variant = variant;
     return LC_OK;
   }
   if (variant == LC_VARIANT_STAGED) {
@@ -606,6 +636,20 @@ lc_status lc_set_collision(lc_ctx* c, int32_t kind, const double* rates, int32_t
     if (!(rates[g] > 0.0 && rates[g] < 2.0)) return fail(LC_EINVAL, "MRT rate %d = %g outside (0, 2)", g, rates[g]);
   for (int g = 0; g < 5; g++) c->mrt[g] = g < ng ? rates[g] : 0.0;
   c->coll = LC_COLL_MRT;
+  return LC_OK;
+}
+
+lc_status lc_set_stencil(lc_ctx* c, int32_t stencil) {
+  clear_error();
+  if (!c) return fail(LC_EINVAL, "ctx is NULL");
+  if (stencil == LC_STENCIL_COMPACT) {
+    c->stencil = stencil;
+    return LC_OK;
+  }
+  if (stencil != LC_STENCIL_ISOTROPIC) return fail(LC_EINVAL, "unknown stencil %d", stencil);
+  if (c->g.precision != LC_FP64 && c->g.precision != LC_FP32_DEV)
+    return fail(LC_EUNSUPPORTED, "the isotropic stencils are provided in LC_FP64 and LC_FP32_DEV");
+  c->stencil = stencil;
   return LC_OK;
 }
 
@@ -744,6 +788,8 @@ static lc_status vjp_check(lc_ctx* c) {
   if (c->g.lattice != LC_D2Q9 || c->g.precision != LC_FP64)
     return fail(LC_EUNSUPPORTED, "the reverse step is provided for D2Q9 in double precision");
   if (c->coll != LC_COLL_BGK) return fail(LC_EUNSUPPORTED, "the reverse step is provided for the BGK collision");
+  if (c->stencil != LC_STENCIL_COMPACT)
+    return fail(LC_EUNSUPPORTED, "the reverse step is provided for the compact stencils");
   return LC_OK;
 }
 

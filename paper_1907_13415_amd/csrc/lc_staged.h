@@ -8,7 +8,8 @@
 //   stage_corr : Q, Q^P, R, u -> Q_next = Q + (R(Q) + R(Q^P))/2.
 // This is the plainest correct mapping of the method onto the GPU; the
 // fused and split kernels compute the same per-site arithmetic with fewer
-// HBM round trips.
+// HBM round trips.  The stage kernels alone also offer the isotropic
+// difference stencils (template argument ST, see below).
 #pragma once
 
 #include "lc_device.h"
@@ -20,6 +21,83 @@ struct GridDims {
   int64_t N;
 };
 
+// Difference stencils.  STENCIL_COMPACT: the central first differences and
+// the (2d+1)-point Laplacian of Sec. 1.2.2.  STENCIL_ISO: every derivative
+// of the step (grad Q, lap Q, the divergence of the stress, grad u) taken
+// from the lattice's own velocities and weights, with c_s^2 = 1/3,
+//   d_g V = 3 sum_i w_i c_ig V(x + c_i),   lap V = 6 sum_i w_i [V(x + c_i) - V(x)],
+// exact on quadratic fields like the compact ones but with leading errors
+// that do not depend on the direction (the remedy for spurious currents
+// the closing remarks of Sec. 2.2 point to).  The sums run over pairs of
+// opposite velocities: 3 w c_g [V(+c) - V(-c)] and 6 w [(V(+c) - V(x)) +
+// (V(-c) - V(x))], the latter differences taken first so that a smooth
+// field does not lose its low bits to the sum.
+constexpr int STENCIL_COMPACT = 0;
+constexpr int STENCIL_ISO = 1;
+
+// Index offset from a site to its neighbour along lattice velocity i.
+template <int LAT>
+__device__ __forceinline__ int64_t nbr_offset(const Nbr& nb, int i) {
+  using L = Lattice<LAT>;
+  int64_t d = 0;
+  if (L::cx(i) == 1) d += nb.xp;
+  if (L::cx(i) == -1) d += nb.xm;
+  if (L::cy(i) == 1) d += nb.yp;
+  if (L::cy(i) == -1) d += nb.ym;
+  if (L::cz(i) == 1) d += nb.zp;
+  if (L::cz(i) == -1) d += nb.zm;
+  return d;
+}
+
+template <int LAT>
+__host__ __device__ constexpr int lat_c(int i, int a) {
+  return a == 0 ? Lattice<LAT>::cx(i) : (a == 1 ? Lattice<LAT>::cy(i) : Lattice<LAT>::cz(i));
+}
+
+// Isotropic gradient and Laplacian of a symmetric tensor field at site s.
+template <int LAT, typename S>
+__device__ __forceinline__ void stencil_iso(const S* __restrict__ q, int64_t N, int64_t s, const Nbr& nb,
+                                            Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
+  using Lt = Lattice<LAT>;
+  c = load_sym(q, N, s);
+  const S cv[5] = {c.xx, c.xy, c.xz, c.yy, c.yz};
+  S dv[3][5], lv[5];
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    lv[k] = S(0);
+#pragma unroll
+    for (int g = 0; g < 3; g++) dv[g][k] = S(0);
+  }
+#pragma unroll
+  for (int i = 1; i < Lt::q; i++) {
+    if (Lt::opp(i) < i) continue;
+    const Sym<S> P = load_sym(q, N, s + nbr_offset<LAT>(nb, i));
+    const Sym<S> M = load_sym(q, N, s + nbr_offset<LAT>(nb, Lt::opp(i)));
+    const S pv[5] = {P.xx, P.xy, P.xz, P.yy, P.yz}, mv[5] = {M.xx, M.xy, M.xz, M.yy, M.yz};
+    const S w3 = S(3.0 * Lt::w(i)), w6 = S(6.0 * Lt::w(i));
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+      const S diff = pv[k] - mv[k];
+#pragma unroll
+      for (int g = 0; g < 3; g++)
+        if (lat_c<LAT>(i, g) != 0) dv[g][k] += (lat_c<LAT>(i, g) > 0 ? w3 : -w3) * diff;
+      lv[k] += w6 * ((pv[k] - cv[k]) + (mv[k] - cv[k]));
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < 3; g++) d[g] = Sym<S>{dv[g][0], dv[g][1], dv[g][2], dv[g][3], dv[g][4]};
+  L = Sym<S>{lv[0], lv[1], lv[2], lv[3], lv[4]};
+}
+
+template <int LAT, typename S, int ST>
+__device__ __forceinline__ void stencil_st(const S* __restrict__ q, int64_t N, int64_t s, const Nbr& nb,
+                                           Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
+  if constexpr (ST == STENCIL_ISO)
+    stencil_iso<LAT, S>(q, N, s, nb, c, d, L);
+  else
+    stencil<S, Lattice<LAT>::dim>(q, N, s, nb, c, d, L);
+}
+
 // Number of stress components kept: D2Q9 needs tau_xx, tau_xy, tau_yx,
 // tau_yy (the z row of F is not carried); D3Q19 needs all nine.
 template <int LAT>
@@ -30,7 +108,7 @@ struct TauLayout {
   }
 };
 
-template <int LAT, typename S>
+template <int LAT, typename S, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(256) stage_tau(const S* __restrict__ Q, S* __restrict__ tau,
                                                  GridDims g, Coef<S> c) {
   constexpr int DIM = Lattice<LAT>::dim;
@@ -41,7 +119,7 @@ __global__ void __launch_bounds__(256) stage_tau(const S* __restrict__ Q, S* __r
   const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
   const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
   Sym<S> q, L, d[3];
-  stencil<S, DIM>(Q, g.N, s, nb, q, d, L);
+  stencil_st<LAT, S, ST>(Q, g.N, s, nb, q, d, L);
   const Sym<S> H = molecular_field(q, L, c);
   S t[3][3];
   stress(q, H, d, c, t);
@@ -52,14 +130,37 @@ __global__ void __launch_bounds__(256) stage_tau(const S* __restrict__ Q, S* __r
     for (int b = 0; b < D; b++) tau[TauLayout<LAT>::idx(a, b) * g.N + s] = t[a][b];
 }
 
-// Body force F_a = sum_b [tau_ab(x+e_b) - tau_ab(x-e_b)]/2 (Sec. 1.2.1).
-template <int LAT, typename S>
+// Body force F_a = sum_b [tau_ab(x+e_b) - tau_ab(x-e_b)]/2 (Sec. 1.2.1),
+// or with ST = STENCIL_ISO  F_a = 3 sum_i w_i sum_b c_ib tau_ab(x + c_i).
+template <int LAT, typename S, int ST = STENCIL_COMPACT>
 __device__ __forceinline__ void body_force(const S* __restrict__ tau, int64_t N, int64_t s, const Nbr& nb,
                                            S (&F)[3]) {
   constexpr int DIM = Lattice<LAT>::dim;
   const int64_t off[3][2] = {{nb.xp, nb.xm}, {nb.yp, nb.ym}, {nb.zp, nb.zm}};
 #pragma unroll
   for (int a = 0; a < 3; a++) F[a] = S(0);
+  if constexpr (ST == STENCIL_ISO) {
+    using Lt = Lattice<LAT>;
+#pragma unroll
+    for (int i = 1; i < Lt::q; i++) {
+      if (Lt::opp(i) < i) continue;
+      const int64_t sp = s + nbr_offset<LAT>(nb, i), sm = s + nbr_offset<LAT>(nb, Lt::opp(i));
+      const S w3 = S(3.0 * Lt::w(i));
+#pragma unroll
+      for (int a = 0; a < DIM; a++) {
+        S acc = S(0);
+#pragma unroll
+        for (int b = 0; b < DIM; b++) {
+          if (lat_c<LAT>(i, b) == 0) continue;
+          const S* t = tau + TauLayout<LAT>::idx(a, b) * N;
+          const S dt = t[sp] - t[sm];
+          acc += lat_c<LAT>(i, b) > 0 ? dt : -dt;
+        }
+        F[a] += w3 * acc;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < DIM; a++) {
     S acc = S(0);
@@ -266,7 +367,7 @@ __device__ __forceinline__ void gather_f(const S* __restrict__ buf, int64_t N, i
   }
 }
 
-template <int LAT, typename S, bool DEV, bool MRT = false>
+template <int LAT, typename S, bool DEV, bool MRT = false, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const S* __restrict__ tau,
                                                 S* __restrict__ fout, S* __restrict__ uout,
                                                 GridDims g, Coef<S> c) {
@@ -279,7 +380,7 @@ __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const
   const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
   const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
   S F[3];
-  body_force<LAT, S>(tau, N, s, nb, F);
+  body_force<LAT, S, ST>(tau, N, s, nb, F);
   S f[L::q];
   gather_f<LAT, S>(fin, N, s, nb, f);
   S rho, mass, u[3];
@@ -294,10 +395,35 @@ __global__ void __launch_bounds__(256) stage_lb(const S* __restrict__ fin, const
   for (int i = 0; i < L::q; i++) fout[i * N + s] = f[i];
 }
 
-// Velocity gradient G[a][b] = d_b u_a (central differences).
-template <int DIM, typename S>
+// Velocity gradient G[a][b] = d_b u_a (central differences, or with ST =
+// STENCIL_ISO 3 sum_i w_i c_ib u_a(x + c_i)).
+template <int LAT, typename S, int ST = STENCIL_COMPACT>
 __device__ __forceinline__ void velocity_gradient(const S* __restrict__ u, int64_t N, int64_t s, const Nbr& nb,
                                                   S (&G)[3][3], S (&uc)[3]) {
+  constexpr int DIM = Lattice<LAT>::dim;
+  if constexpr (ST == STENCIL_ISO) {
+    using Lt = Lattice<LAT>;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      uc[a] = a < DIM ? u[a * N + s] : S(0);
+#pragma unroll
+      for (int b = 0; b < 3; b++) G[a][b] = S(0);
+    }
+#pragma unroll
+    for (int i = 1; i < Lt::q; i++) {
+      if (Lt::opp(i) < i) continue;
+      const int64_t sp = s + nbr_offset<LAT>(nb, i), sm = s + nbr_offset<LAT>(nb, Lt::opp(i));
+      const S w3 = S(3.0 * Lt::w(i));
+#pragma unroll
+      for (int a = 0; a < DIM; a++) {
+        const S du = w3 * (u[a * N + sp] - u[a * N + sm]);
+#pragma unroll
+        for (int b = 0; b < DIM; b++)
+          if (lat_c<LAT>(i, b) != 0) G[a][b] += lat_c<LAT>(i, b) > 0 ? du : -du;
+      }
+    }
+    return;
+  }
   const int64_t off[3][2] = {{nb.xp, nb.xm}, {nb.yp, nb.ym}, {nb.zp, nb.zm}};
 #pragma unroll
   for (int a = 0; a < 3; a++) {
@@ -308,11 +434,10 @@ __device__ __forceinline__ void velocity_gradient(const S* __restrict__ u, int64
   }
 }
 
-template <int LAT, typename S>
+template <int LAT, typename S, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(256) stage_pred(const S* __restrict__ Q, const S* __restrict__ u,
                                                   S* __restrict__ qp, S* __restrict__ rq, GridDims g,
                                                   Coef<S> c) {
-  constexpr int DIM = Lattice<LAT>::dim;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -320,20 +445,19 @@ __global__ void __launch_bounds__(256) stage_pred(const S* __restrict__ Q, const
   const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
   const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
   Sym<S> q, L, d[3];
-  stencil<S, DIM>(Q, g.N, s, nb, q, d, L);
+  stencil_st<LAT, S, ST>(Q, g.N, s, nb, q, d, L);
   const Sym<S> H = molecular_field(q, L, c);
   S G[3][3], uc[3];
-  velocity_gradient<DIM, S>(u, g.N, s, nb, G, uc);
+  velocity_gradient<LAT, S, ST>(u, g.N, s, nb, G, uc);
   const Sym<S> R = be_rate(q, H, d, uc, G, c);
   store_sym(rq, g.N, s, R);
   store_sym(qp, g.N, s, Sym<S>{q.xx + R.xx, q.xy + R.xy, q.xz + R.xz, q.yy + R.yy, q.yz + R.yz});
 }
 
-template <int LAT, typename S>
+template <int LAT, typename S, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(256) stage_corr(const S* __restrict__ Q, const S* __restrict__ qp,
                                                   const S* __restrict__ rq, const S* __restrict__ u,
                                                   S* __restrict__ Qout, GridDims g, Coef<S> c) {
-  constexpr int DIM = Lattice<LAT>::dim;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -341,10 +465,10 @@ __global__ void __launch_bounds__(256) stage_corr(const S* __restrict__ Q, const
   const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
   const Nbr nb = neighbours(x, y, z, g.nx, g.ny, g.nz);
   Sym<S> p, L, d[3];
-  stencil<S, DIM>(qp, g.N, s, nb, p, d, L);
+  stencil_st<LAT, S, ST>(qp, g.N, s, nb, p, d, L);
   const Sym<S> H = molecular_field(p, L, c);
   S G[3][3], uc[3];
-  velocity_gradient<DIM, S>(u, g.N, s, nb, G, uc);
+  velocity_gradient<LAT, S, ST>(u, g.N, s, nb, G, uc);
   const Sym<S> Rp = be_rate(p, H, d, uc, G, c);
   const Sym<S> q = load_sym(Q, g.N, s);
   const Sym<S> R = load_sym(rq, g.N, s);

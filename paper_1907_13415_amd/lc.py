@@ -22,6 +22,7 @@ LC_D2Q9, LC_D3Q19 = 0, 1
 LC_FP64, LC_FP32_DEV, LC_MIXED, LC_FP32_SR = 0, 1, 2, 3
 LC_VARIANT_AUTO, LC_VARIANT_STAGED, LC_VARIANT_SPLIT, LC_VARIANT_FUSED = 0, 1, 2, 3
 LC_COLL_BGK, LC_COLL_MRT = 0, 1
+LC_STENCIL_COMPACT, LC_STENCIL_ISOTROPIC = 0, 1
 LC_OBS_MASS, LC_OBS_MOM, LC_OBS_UMAX, LC_OBS_S, LC_OBS_ALL = 1, 2, 4, 8, 15
 LC_FIELD_F, LC_FIELD_Q, LC_FIELD_RHO, LC_FIELD_U, LC_FIELD_FORCE, LC_FIELD_S = range(6)
 
@@ -76,6 +77,7 @@ def _load():
         "lc_set_params": ([ctypes.c_void_p, P(lc_params)], ctypes.c_int32),
         "lc_set_variant": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
         "lc_set_chunk": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+        "lc_set_stencil": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
         "lc_load_state": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
         "lc_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
         "lc_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
@@ -172,6 +174,10 @@ def lc_set_variant(ctx, variant):
 
 def lc_set_chunk(ctx, planes):
     _check(_lib.lc_set_chunk(ctx, int(planes)))
+
+
+def lc_set_stencil(ctx, stencil):
+    _check(_lib.lc_set_stencil(ctx, int(stencil)))
 
 
 def lc_load_state(ctx, f_ptr, q_ptr):
@@ -323,6 +329,9 @@ class Solver:
 
     def set_chunk(self, planes):
         lc_set_chunk(self.ctx, planes)
+
+    def set_stencil(self, stencil):
+        lc_set_stencil(self.ctx, stencil)
 
     def set_params(self, params):
         self.params = make_params(*params)

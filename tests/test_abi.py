@@ -181,6 +181,35 @@ def test_host_side_validation_of_settings_and_reverse_calls():
         lc.lc_free(ctx2)
 
 
+def test_stencil_setting_validated_on_the_host():
+    """lc_set_stencil: unknown stencils are LC_EINVAL; the isotropic
+    stencils exist in LC_FP64 and LC_FP32_DEV only; the reverse step refuses
+    them."""
+    from paper_1907_13415_amd import lc
+    params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
+    ctxs = {prec: lc.lc_init(lc.make_grid(lc.LC_D2Q9, prec, 16, 16, 1), params, _fake_bufs(lc), 0)
+            for prec in (lc.LC_FP64, lc.LC_FP32_DEV, lc.LC_MIXED, lc.LC_FP32_SR)}
+    try:
+        for prec, ctx in ctxs.items():
+            with pytest.raises(lc.LCError) as e:
+                lc.lc_set_stencil(ctx, 2)
+            assert e.value.code == lc.LC_EINVAL
+            lc.lc_set_stencil(ctx, lc.LC_STENCIL_COMPACT)
+            if prec in (lc.LC_FP64, lc.LC_FP32_DEV):
+                lc.lc_set_stencil(ctx, lc.LC_STENCIL_ISOTROPIC)
+            else:
+                with pytest.raises(lc.LCError) as e:
+                    lc.lc_set_stencil(ctx, lc.LC_STENCIL_ISOTROPIC)
+                assert e.value.code == lc.LC_EUNSUPPORTED
+        dummy = 1 << 40
+        with pytest.raises(lc.LCError) as e:
+            lc.lc_vjp_step(ctxs[lc.LC_FP64], dummy, dummy, dummy, dummy, dummy)
+        assert e.value.code == lc.LC_EUNSUPPORTED and "stencil" in str(e.value)
+    finally:
+        for ctx in ctxs.values():
+            lc.lc_free(ctx)
+
+
 def test_static_step_validates_before_touching_the_device():
     """lc_step_static rejects a grid whose velocity field exceeds its fixed
     scratch array (LC_ENOMEM) and bad arguments (LC_EINVAL) on the host."""

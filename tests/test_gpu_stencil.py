@@ -1,0 +1,160 @@
+"""GPU parity of the isotropic difference stencils (lc_set_stencil) against
+the oracle's isotropic option (oracle.run(..., stencil="isotropic")).
+
+The library's staged kernels take every derivative of the step (grad Q,
+lap Q, the divergence of the stress, grad u) from the lattice's velocities
+and weights when LC_STENCIL_ISOTROPIC is set.  Double precision must agree
+with the oracle to 1e-12 in the normwise metric of gpu_util.rel_err, for the
+state, the derived fields and the observables, with BGK and MRT collisions;
+the FP32 deviation form must keep S within 1e-5.  The calls the stencils do
+not support fail with LC_EUNSUPPORTED.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_13415_amd import inputs
+from gpu_util import SCALES, lattice_name, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+GHOSTS = {0: (1.19, 1.4, 1.1), 1: (1.19, 1.4, 1.2, 1.4, 1.98)}
+ISO = "isotropic"
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def _lc():
+    require_gpu()
+    from paper_1907_13415_amd import lc
+    return lc
+
+
+def _state(lc, lat, shape, seed):
+    rng = np.random.default_rng(seed)
+    q = 9 if lat == 0 else 19
+    q5 = inputs.random_q5(shape, rng, amp=0.12)
+    rel = inputs.random_rel(q, shape, rng, amp=2e-3)
+    _, w = lc.lc_lattice_info(lat)
+    return q5, rel, w.reshape((q, 1, 1, 1)) * (1.0 + rel)
+
+
+@pytest.mark.parametrize("coll", ["bgk", "mrt"])
+@pytest.mark.parametrize("lat,shape", [(0, (1, 23, 37)), (0, (1, 70, 130)), (1, (9, 11, 13)), (1, (17, 6, 67))])
+def test_isotropic_parity_random_state_ragged(lat, shape, coll):
+    """Random Q and perturbed populations on ragged grids spanning several
+    site tiles, 12 steps: state, rho, u and the body force, and the
+    observables, against the oracle with the same stencils."""
+    lc = _lc()
+    _say("isotropic parity lat %d shape %s %s" % (lat, shape, coll))
+    q5, rel, f_gpu = _state(lc, lat, shape, 500 + lat)
+    p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
+    s = lc.Solver(lattice_name(lat), "fp64", shape, p)
+    s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+    rates = None
+    if coll == "mrt":
+        s.set_collision(lc.LC_COLL_MRT, GHOSTS[lat])
+        rates = oracle.mrt_rates(lat, p[5], GHOSTS[lat])
+    s.load(q5, f_gpu)
+    s.step(12)
+    f_ref, q_ref = oracle.run(lat, oracle.rest_populations(lat, shape, rel=rel), q5, p, 12, rates=rates,
+                              stencil=ISO)
+    ef = rel_err(s.export(lc.LC_FIELD_F), f_ref, SCALES["f"])
+    eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
+    _say("  err f %.3e  Q %.3e" % (ef, eq))
+    assert ef < TOL64 and eq < TOL64
+    fl = oracle.fields(lat, f_ref, q_ref, p, stencil=ISO)
+    for field, key, sc in ((lc.LC_FIELD_RHO, "rho", 1.0), (lc.LC_FIELD_U, "u", SCALES["u"]),
+                           (lc.LC_FIELD_FORCE, "F", SCALES["F"])):
+        got = s.export(field)
+        want = fl[key] if key != "rho" else fl[key][None]
+        e = rel_err(got, want, sc)
+        assert e < TOL64, (key, e)
+    # the isotropic force differs from the compact one on this state (the
+    # comparison above is not passing on a shared stencil)
+    fc = oracle.fields(lat, f_ref, q_ref, p)["F"]
+    assert rel_err(fl["F"], fc, SCALES["F"]) > 1e-4
+    for ax in range(2 if lat == 0 else 3):
+        o = s.observe(half_axis=ax)
+        r = oracle.observe(lat, f_ref, q_ref, p, half_axis=ax, stencil=ISO)
+        assert abs(o["mass"] - r["mass"]) < 1e-12 * r["mass"]
+        np.testing.assert_allclose(o["mom"], r["mom"], rtol=0, atol=1e-13)
+        assert abs(o["umax"] - r["umax"]) < 1e-12 * SCALES["u"]
+        assert abs(o["ssum_half"] - r["ssum_half"]) < 1e-12 * r["ssum"]
+
+
+def test_isotropic_flat_interface_1000_steps_fp64_and_fp32():
+    """The flat-interface workload (128 x 16, paper parameters) for 1000
+    steps with isotropic stencils: FP64 to 1e-12, the FP32 deviation form
+    within 1e-5 on S."""
+    lc = _lc()
+    w = inputs.config0()
+    p = inputs.PAPER_PARAMS
+    f_ref, q_ref = oracle.run(0, oracle.rest_populations(0, w.shape), w.q5, p, 1000, stencil=ISO)
+    S_ref = np.sqrt(1.5 * (q_ref[0] ** 2 + q_ref[3] ** 2 + (q_ref[0] + q_ref[3]) ** 2
+                           + 2 * (q_ref[1] ** 2 + q_ref[2] ** 2 + q_ref[4] ** 2)))
+    for prec in ("fp64", "fp32dev"):
+        s = lc.Solver("D2Q9", prec, w.shape, p)
+        s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+        s.load(w.q5)
+        s.step(1000)
+        if prec == "fp64":
+            ef = rel_err(s.export(lc.LC_FIELD_F), f_ref, SCALES["f"])
+            eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
+            _say("isotropic flat fp64: err f %.3e  Q %.3e" % (ef, eq))
+            assert ef < TOL64 and eq < TOL64
+        else:
+            err = np.abs(s.export(lc.LC_FIELD_S)[0] - S_ref).max()
+            _say("isotropic flat fp32dev: max |dS| %.3e" % err)
+            assert err < 1e-5
+
+
+def test_isotropic_slab_32cubed_d3q19_500_steps():
+    """The slab recipe on a 32^3 D3Q19 grid with isotropic stencils, 500
+    steps, against the oracle to 1e-12; lattice momentum conserved."""
+    lc = _lc()
+    w = inputs.config2(32)
+    s = lc.Solver("D3Q19", "fp64", w.shape, w.params)
+    s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+    s.load(w.q5)
+    j0 = s.observe()["mom"]
+    s.step(500)
+    f_ref, q_ref = oracle.run(1, oracle.rest_populations(1, w.shape), w.q5, w.params, 500, stencil=ISO)
+    ef = rel_err(s.export(lc.LC_FIELD_F), f_ref, SCALES["f"])
+    eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
+    dj = np.abs(s.observe()["mom"] - j0).max()
+    _say("isotropic slab 32^3 step 500: err f %.3e  Q %.3e  momentum drift %.2e" % (ef, eq, dj))
+    assert ef < TOL64 and eq < TOL64
+    assert dj < 1e-10
+
+
+def test_isotropic_stencil_unsupported_combinations():
+    """Explicit split or fused variants with the isotropic stencils, and the
+    reverse step, fail with LC_EUNSUPPORTED; compact again runs the split
+    sweeps bit for bit as a fresh context does."""
+    lc = _lc()
+    shape = (1, 16, 24)
+    q5, rel, f_gpu = _state(lc, 0, shape, 7)
+    p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
+    s = lc.Solver("D2Q9", "fp64", shape, p)
+    s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+    s.load(q5, f_gpu)
+    for v in (lc.LC_VARIANT_SPLIT, lc.LC_VARIANT_FUSED):
+        s.set_variant(v)
+        with pytest.raises(lc.LCError) as e:
+            s.step(1)
+        assert e.value.code == lc.LC_EUNSUPPORTED
+    s.set_variant(lc.LC_VARIANT_AUTO)
+    s.set_stencil(lc.LC_STENCIL_COMPACT)
+    s.step(3)
+    ref = lc.Solver("D2Q9", "fp64", shape, p)
+    ref.load(q5, f_gpu)
+    ref.step(3)
+    assert np.array_equal(s.export(lc.LC_FIELD_F), ref.export(lc.LC_FIELD_F))
+    assert np.array_equal(s.export(lc.LC_FIELD_Q), ref.export(lc.LC_FIELD_Q))
