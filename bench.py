@@ -10,8 +10,9 @@ stochastic rounding.  Each of these legs runs W untimed steps and then
 `--repeats` timed runs of exactly K steps; ms_per_step is the median run.
 Also reported: the single-pass variant, the mixed form, the 64-grid
 temperature sweep in the batched form, the same slab with the MRT
-collision, the 256^2 droplets over 20000 steps, and the cost of the
-checkpointed reverse sweep on the 256^2 droplet.
+collision, the isotropic difference stencils (staged kernels), the 256^2
+droplets over 20000 steps, and the cost of the checkpointed reverse sweep on
+the 256^2 droplet.
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region;
 timings use HIP events recorded on the stream the library launches on.
@@ -116,7 +117,7 @@ def cpu_baseline(n=128, min_s=10.0, max_steps=200):
 MRT_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
 
 
-def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False, repeats=1, variant=None):
+def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False, repeats=1, variant=None, stencil=None):
     """The slab for `warmup` untimed steps, then `repeats` timed runs of
     exactly `steps` steps each (HIP events on the library stream around each
     run, and around each kernel launch): the median run's ms per step and
@@ -125,6 +126,8 @@ def run_slab(torch, lc, w, prec, steps, warmup, dev, stream, mrt=False, repeats=
         s = lc.Solver("D3Q19", prec, w.shape, w.params, device=dev, stream=stream)
         if variant is not None:
             s.set_variant(variant)
+        if stencil is not None:
+            s.set_stencil(stencil)
         if mrt:
             s.set_collision(lc.LC_COLL_MRT, MRT_RATES)
         s.load(w.q5)
@@ -187,6 +190,19 @@ def mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site):
     return {"mlups": round(N / (rm["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(rm["ms"], 5),
             "kernel_ms": [round(v, 5) for v in rm["kernel_ms"]], "rates": list(MRT_RATES),
             "roofline_frac": round(bytes_site * N / (sum(rm["kernel_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def stencil_leg(torch, lc, w, args, dev, stream, N):
+    """The isotropic difference stencils (staged kernels) on the slab in
+    FP32, beside the staged kernels with the compact stencils."""
+    out = {}
+    for name, st in (("compact", lc.LC_STENCIL_COMPACT), ("isotropic", lc.LC_STENCIL_ISOTROPIC)):
+        r = run_slab(torch, lc, w, "fp32dev", min(args.steps, 100), min(args.warmup, 10), dev, stream,
+                     variant=lc.LC_VARIANT_STAGED, stencil=st)
+        del r["S"]
+        out[name] = {"mlups": round(N / (r["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(r["ms"], 5)}
+        torch.cuda.empty_cache()
+    return {"variant": "staged", "precision": "fp32dev", **out}
 
 
 def s_nematic(g):
@@ -471,6 +487,7 @@ def main():
         out["fused"] = fused_leg(torch, lc, w, args, dev, stream, N, bytes_site, r32["ms"], r64["ms"])
         out["mixed"] = mixed
         out["mrt_fp32"] = mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)
+        out["stencil_iso"] = stencil_leg(torch, lc, w, args, dev, stream, N)
         out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)
         out["droplets"] = run_droplets(torch, lc, dev, stream)
         out["adjoint"] = run_adjoint(torch)
