@@ -41,6 +41,11 @@ COUNTERS = os.path.join(ROOT, "profiles", "split_sweeps_slab256_d3q19_fp32dev_co
 KERNEL_SOURCES = ["csrc/lc_device.h", "csrc/lc_staged.h", "csrc/lc_split.h", "build.py"]
 
 
+def note(msg):
+    """Progress line on stderr (the JSON record alone goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def alg_bytes_per_site(q, es):
     """Compulsory traffic of one site update: read and write f (q values)
     and Q (5 values)."""
@@ -421,8 +426,11 @@ def main():
         return
     rep = args.repeats
     r32 = run_slab(torch, lc, w, "fp32dev", args.steps, args.warmup, dev, stream, repeats=rep)
+    note("slab fp32dev %.4f ms/step" % r32["ms"])
     r64 = run_slab(torch, lc, w, "fp64", args.steps, args.warmup, dev, stream, repeats=rep)
+    note("slab fp64 %.4f ms/step" % r64["ms"])
     rsr = run_slab(torch, lc, w, "fp32sr", args.steps, args.warmup, dev, stream, repeats=rep)
+    note("slab fp32sr %.4f ms/step" % rsr["ms"])
     dS = float((r32["S"] - r64["S"]).abs().max().item())
     dS_sr = float((rsr["S"] - r64["S"]).abs().max().item())
     mixed = None if args.quick else mixed_leg(torch, lc, w, args, dev, stream, N, r64["S"])
@@ -485,14 +493,21 @@ def main():
     }
     if not args.quick:
         out["fused"] = fused_leg(torch, lc, w, args, dev, stream, N, bytes_site, r32["ms"], r64["ms"])
+        note("fused leg done")
         out["mixed"] = mixed
         out["mrt_fp32"] = mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)
+        note("mrt leg done")
         out["stencil_iso"] = stencil_leg(torch, lc, w, args, dev, stream, N)
+        note("stencil leg done")
         out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)
+        note("batch leg done")
         out["droplets"] = run_droplets(torch, lc, dev, stream)
+        note("droplets done")
         out["adjoint"] = run_adjoint(torch)
+        note("adjoint done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        note("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -167,25 +167,36 @@ typedef struct {
 typedef struct lc_ctx lc_ctx;
 typedef struct lc_batch lc_batch;
 
-/* Message of the last failing call on this thread ("" if none). */
+/* Message of the last failing call on this thread ("" if none).  Library
+ * plumbing: implements no passage of the paper. */
 const char *lc_last_error(void);
 
 /* Velocity set of a lattice: *q, c[i*3 + a] (q*3 ints) and w[i] (q doubles).
- * c and w may be NULL to query q only. */
+ * c and w may be NULL to query q only.  The D2Q9 and D3Q19 velocity sets and
+ * weights of Sec. 1.2.1 (Eq. 8 uses the weights, c_s^2 = 1/3), in the order
+ * of the preamble.  LC_EINVAL for an unknown lattice or NULL q. */
 lc_status lc_lattice_info(int32_t lattice, int32_t *q, int32_t *c, double *w);
 
 /* Bytes of one f buffer, one Q buffer and the scratch buffer for a grid
- * (any output pointer may be NULL). */
+ * (any output pointer may be NULL): f holds the q populations of Eq. (7) per
+ * site, Q the five independent components of the traceless symmetric order
+ * tensor of Sec. 1.1, in the storage precision of the grid.  LC_EINVAL for
+ * a bad grid. */
 lc_status lc_buffer_bytes(const lc_grid *grid, size_t *f_bytes, size_t *q_bytes,
                           size_t *scratch_bytes);
 
-/* Create a context over caller-owned buffers.  `stream` is a hipStream_t
- * (NULL = default stream).  Validates the grid, the parameters and the
- * buffers (LC_EINVAL).  The state is undefined until lc_load_state. */
+/* Create a context over caller-owned buffers for the time step of Sec. 1.2
+ * (Eqs. 1-9) on `grid` with the parameters of Eqs. (1)-(5).  `stream` is a
+ * hipStream_t (NULL = default stream).  Validates the grid, the parameters
+ * and the buffers (LC_EINVAL); host allocation failure is LC_ENOMEM.  The
+ * state is undefined until lc_load_state.  Defaults: variant AUTO, BGK
+ * collision, compact stencils. */
 lc_status lc_init(const lc_grid *grid, const lc_params *params, const lc_buffers *bufs,
                   void *stream, lc_ctx **out);
 
-/* Replace the parameters (same validation as lc_init); for sweeps. */
+/* Replace the parameters of Eqs. (1)-(5) (same validation as lc_init); for
+ * the temperature sweeps of Sec. 2.1.  Applies to the steps enqueued after
+ * the call. */
 lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 
 /* Choose the kernel variant (LC_VARIANT_*) of the step of Sec. 1.2 (the
@@ -231,28 +242,46 @@ lc_status lc_set_collision(lc_ctx *ctx, int32_t kind, const double *rates, int32
  * stencils only.  LC_EINVAL for an unknown stencil. */
 lc_status lc_set_stencil(lc_ctx *ctx, int32_t stencil);
 
-/* Planes each block marches through along z in the two-sweep kernels
- * (>= 1; larger chunks recompute fewer boundary planes, smaller chunks give
- * more blocks).  0 restores the built-in default.  Ignored by 2D grids. */
+/* Planes each block marches through along z in the two-sweep and fused
+ * kernels (>= 1; larger chunks recompute fewer boundary planes, smaller
+ * chunks give more blocks).  0 restores the built-in default.  Ignored by
+ * 2D grids.  A launch-shape setting: implements no passage of the paper and
+ * does not change results.  LC_EINVAL for planes < 0. */
 lc_status lc_set_chunk(lc_ctx *ctx, int32_t planes);
 
 /* Load the state from device arrays of double logical values: f_dev (q*N)
- * and Q_dev (5*N).  f_dev == NULL loads the fluid at rest with rho = 1,
- * f_i = w_i (the initial condition of Sec. 2).  Resets the step counter.
- * Asynchronous on the context stream. */
+ * and Q_dev (5*N), the populations of Eq. (7) and the order tensor of
+ * Sec. 1.1 (layout of the preamble).  f_dev == NULL loads the fluid at rest
+ * with rho = 1, f_i = w_i (the initial condition of Sec. 2).  Resets the
+ * step counter.  Asynchronous on the context stream.  LC_EINVAL for a NULL
+ * context or Q_dev. */
 lc_status lc_load_state(lc_ctx *ctx, const double *f_dev, const double *Q_dev);
 
-/* Enqueue n >= 0 time steps (asynchronous). */
+/* Enqueue n >= 0 time steps of Sec. 1.2 (asynchronous on the context
+ * stream): the molecular field (Eq. 4), stress (Eq. 6) and its divergence
+ * as the body force (Sec. 1.2.1), density and force-corrected velocity
+ * (Eq. 9), the predictor-corrector update of Q by Eqs. (1)-(2) (Sec. 1.2.2
+ * steps 1-5), and the forced collision (Eq. 8 and the forcing term of
+ * Sec. 1.2.1) with periodic streaming (Eq. 7).  LC_EINVAL for n < 0,
+ * LC_ESTATE before lc_load_state, LC_EUNSUPPORTED for a variant, precision
+ * and stencil that do not go together. */
 lc_status lc_step(lc_ctx *ctx, int64_t n);
 
 /* Reduce the current state to observables (mask of LC_OBS_*; fields not
- * requested are 0) with half-domain axis half_axis (0, 1, 2).  Synchronises
- * the stream.  Returns LC_ENONFINITE (with *out filled) if the state holds a
- * NaN or Inf. */
+ * requested are 0) with half-domain axis half_axis (0, 1, 2): mass and
+ * momentum of Eq. (9), the force-corrected velocity of Eq. (9), the scalar
+ * order S of Sec. 1.1 and the half-domain sum that locates the interface
+ * of Sec. 2.1.  Synchronises the stream.  Returns LC_ENONFINITE (with *out
+ * filled) if the state holds a NaN or Inf; LC_EINVAL for a bad axis or
+ * NULL argument; LC_ESTATE before lc_load_state. */
 lc_status lc_observe(lc_ctx *ctx, uint32_t mask, int32_t half_axis, lc_observables *out);
 
 /* Write a field of the current state as double to dst_dev (device memory,
- * size given by the field, N = nx*ny*nz).  Asynchronous. */
+ * size given by the field, N = nx*ny*nz, component-major): the populations
+ * of Eq. (7), the order tensor of Sec. 1.1, the density and force-corrected
+ * velocity of Eq. (9), the body force of Sec. 1.2.1 or S.  Asynchronous.
+ * LC_EINVAL for an unknown field or NULL argument; LC_ESTATE before
+ * lc_load_state. */
 lc_status lc_export(lc_ctx *ctx, int32_t field, double *dst_dev);
 
 /* Reverse-mode step (adjoint) for gradients of a loss of the final state
@@ -309,7 +338,8 @@ size_t lc_vjp_backward_bytes(const lc_grid *grid, int32_t n);
 lc_status lc_vjp_backward(lc_ctx *ctx, int32_t nseg, const double *const *f_cks, const double *const *Q_cks,
                           const int32_t *ns, void *hist, double *adj_f, double *adj_Q, double *dparams);
 
-/* Wait for the context stream and report any pending device error. */
+/* Wait for the context stream and report any pending device error
+ * (LC_EDEVICE).  Library plumbing: implements no passage of the paper. */
 lc_status lc_sync(lc_ctx *ctx);
 
 /* Per-launch timing of the step kernels.  While enabled, lc_step records
@@ -319,14 +349,17 @@ lc_status lc_sync(lc_ctx *ctx);
  * stays bounded).  lc_get_timing synchronises, returns the summed
  * durations in milliseconds and the number of launches of kind 0 (the
  * stress/LB sweep, or the single pass of the fused variant) and kind 1 (the
- * Q sweep) since the last call, and resets the record. */
+ * Q sweep) since the last call, and resets the record.  Measurement plumbing:
+ * implements no passage of the paper.  LC_EINVAL for a NULL context. */
 lc_status lc_set_timing(lc_ctx *ctx, int32_t enable);
 lc_status lc_get_timing(lc_ctx *ctx, double *ms /*[2]*/, int64_t *launches /*[2]*/);
 
-/* Steps taken since the last load. */
+/* Steps taken since the last load (-1 for a NULL context).  Library
+ * plumbing. */
 int64_t lc_step_count(const lc_ctx *ctx);
 
-/* Destroy the context (device buffers stay with the caller). */
+/* Destroy the context (device buffers stay with the caller).  Library
+ * plumbing. */
 lc_status lc_free(lc_ctx *ctx);
 
 /* Size of the library's own device scratch used by lc_step_static. */
@@ -368,7 +401,8 @@ lc_status lc_step_static(const lc_grid *grid, const lc_params *params, void *con
  * ------------------------------------------------------------------------- */
 
 /* Arena sizes and per-grid byte offsets (f_offsets, q_offsets: ngrids
- * entries each, may be NULL). */
+ * entries each, may be NULL) for the many grids of a temperature sweep
+ * (Sec. 2.1).  LC_EINVAL for a bad grid, LC_EUNSUPPORTED as above. */
 lc_status lc_batch_layout(int32_t ngrids, const lc_grid *grids, size_t *f_bytes, size_t *q_bytes,
                           size_t *scratch_bytes, size_t *f_offsets, size_t *q_offsets);
 
@@ -379,38 +413,45 @@ lc_status lc_batch_layout(int32_t ngrids, const lc_grid *grids, size_t *f_bytes,
 lc_status lc_batch_init(int32_t ngrids, const lc_grid *grids, const lc_params *params,
                         const lc_buffers *arena, void *stream, lc_batch **out);
 
-/* Load grid k (same conventions as lc_load_state).  Every grid must be
+/* Load grid k (same conventions as lc_load_state: Eq. (7) populations,
+ * Sec. 1.1 order tensor).  Every grid must be
  * loaded before the batch steps; loading after steps were taken resets the
  * batch, and every grid must then be loaded again. */
 lc_status lc_batch_load_state(lc_batch *b, int32_t k, const double *f_dev, const double *Q_dev);
 
-/* Enqueue n >= 0 steps of every grid (asynchronous; graph replays for
- * whole runs of 64 steps, direct launches for the rest). */
+/* Enqueue n >= 0 steps of Sec. 1.2 on every grid, each with its own
+ * parameters (asynchronous; graph replays for whole runs of 64 steps,
+ * direct launches for the rest).  LC_ESTATE until every grid is loaded. */
 lc_status lc_batch_step(lc_batch *b, int64_t n);
 
 /* Select the tile shape of each sweep: v_lb for the stress / LB sweep, v_q
  * for the Q sweep (0: 32x8, 1: 64x4, 2: 16x16, 3: 32x16, 4: 64x8, 5: 64x16,
- * 6: 128x8 sites per block).  Results do not depend on the tile shapes.
- * LC_EINVAL outside 0..6. */
+ * 6: 128x8 sites per block).  Results do not depend on the tile shapes (a
+ * launch shape: implements no passage of the paper).  LC_EINVAL outside
+ * 0..6. */
 lc_status lc_batch_set_tiles(lc_batch *b, int32_t v_lb, int32_t v_q);
 
-/* lc_batch_set_tiles(b, variant, variant). */
+/* lc_batch_set_tiles(b, variant, variant).  A launch shape: implements no
+ * passage of the paper and does not change results. */
 lc_status lc_batch_set_tile(lc_batch *b, int32_t variant);
 
 /* Time every pair of tile shapes for trial_steps steps (after one untimed
  * step) with HIP events and keep the fastest; *chosen = v_lb + 7 * v_q.
  * The state advances by 49 * (trial_steps + 1) steps: tune before loading
- * the real state, or load it again afterwards.  Synchronises the stream. */
+ * the real state, or load it again afterwards.  Synchronises the stream.
+ * Measurement plumbing: implements no passage of the paper. */
 lc_status lc_batch_autotune(lc_batch *b, int32_t trial_steps, int32_t *chosen, double *ms_per_step);
 
-/* Observables of every grid: out has ngrids entries.  Synchronises. */
+/* Observables of every grid, as lc_observe (Eq. 9, Sec. 1.1, Sec. 2.1):
+ * out has ngrids entries.  Synchronises. */
 lc_status lc_batch_observe(lc_batch *b, uint32_t mask, int32_t half_axis, lc_observables *out);
 
-/* Export a field of grid k (as lc_export). */
+/* Export a field of grid k (as lc_export: Eq. 7, Sec. 1.1, Eq. 9,
+ * Sec. 1.2.1). */
 lc_status lc_batch_export(lc_batch *b, int32_t k, int32_t field, double *dst_dev);
 
 /* Destroy the batch (graphs and its capture stream; arenas stay with the
- * caller). */
+ * caller).  Library plumbing. */
 lc_status lc_batch_free(lc_batch *b);
 
 #ifdef __cplusplus

@@ -7,8 +7,12 @@
    checkpoint-and-recompute, against central finite differences of the GPU
    forward with h = 1e-6: |g_adj - g_fd| <= 1e-6 |g_fd| + floor / h, where
    the floor is the measured rounding noise of the loss (the second
-   difference L(+h) - 2 L(0) + L(-h), at least eps |L|); and against the
-   Richardson extrapolation of differences at h = 1e-4 and 2e-4.
+   difference L(+h) - 2 L(0) + L(-h), at least eps |L|), asserted where that
+   floor is below 1e-6 |g_fd|; and for every entry against the Richardson
+   extrapolation of differences at h = 1e-4 and 2e-4, to 1e-6 relative plus
+   1000 eps |L| / 1e-4.  On the 256^2 droplet the h = 1e-6 difference is
+   below its floor for every probe and scalar, so the Richardson check is
+   the one that decides there.
 3. The overlapped reverse sweep (lc_vjp_backward) against one
    lc_vjp_segment call per segment, on uneven segments.
 4. A dot-product test of lc_vjp_step against central differences of the GPU
@@ -181,14 +185,18 @@ def _fd_check(n, steps, every, nprobe):
         d1 = (Lp(H) - Lp(-H)) / (2 * H)
         d2 = (Lp(2 * H) - Lp(-2 * H)) / (4 * H)
         rich = (4 * d1 - d2) / 3
-        _say("  %-12s adj %.10e  fd(1e-6) %.10e (floor %.1e)  richardson %.10e" % (name, ga, fd, floor, rich))
+        # rounding allowance of the Richardson estimate: a fixed multiple of
+        # eps |L| / H (the trajectories' rounding, not a sampled value)
+        slack = 1000 * eps * abs(L0) / H
+        _say("  %-12s adj %.10e  fd(1e-6) %.10e (floor %.1e)  richardson %.10e (slack %.1e)"
+             % (name, ga, fd, floor, rich, slack))
         # The measured floor is one sample of the trajectories' rounding
         # noise, not a bound on it.  Where it exceeds the 1e-6 relative
         # target the difference at h = 1e-6 says nothing at that level, and
-        # the Richardson estimate (floor noise/H, 100x smaller) decides.
+        # the Richardson estimate at H = 1e-4 decides.
         if floor <= 1e-6 * abs(fd):
             assert abs(ga - fd) <= 1e-6 * abs(fd) + floor, (name, ga, fd, floor)
-        assert abs(ga - rich) <= 1e-6 * abs(rich) + 2 * noise / H, (name, ga, rich)
+        assert abs(ga - rich) <= 1e-6 * abs(rich) + slack, (name, ga, rich, slack)
         return abs(ga - rich) / max(abs(rich), 1e-300)
 
     worst = 0.0

@@ -269,38 +269,46 @@ def test_circle_with_mrt():
 
 
 def test_fp32_errors_on_interface_and_spurious_velocity():
-    """The FP32 deviation form and the mixed form against double precision
-    (which matches the oracle to 1e-12) on the observables of Sec. 2: S(x)
-    and the front speed of the flat interface at gamma = 2.701, and the
-    spurious currents of the circle near its static temperature.  These runs
-    are long and slow: the front position integrates every rounding of the
-    float Q update (front speed off by 4e-4 over 3e5 steps).  The 1e-5 bound
-    on S holds for the FP32 form on the short workloads (the 1000-step flat
-    interface, the 256^3 slab) and for the mixed form here; the FP32 errors
-    are bounded at about five times their observed size."""
+    """The float storage forms against double precision (which matches the
+    oracle to 1e-12) on the observables of Sec. 2: S(x) and the front speed
+    of the flat interface at gamma = 2.701 after 3e5 steps, and S and the
+    spurious currents of the circle near its static temperature after 35000
+    steps.  The front position integrates every rounding of the Q update.
+
+    Tolerances the forms are offered at: LC_FP32_SR (float storage,
+    molecular field summed in double, stochastically rounded Q update) and
+    LC_MIXED keep S within 1e-5 of double precision, asserted here.
+    LC_FP32_DEV (all-float arithmetic, round to nearest) is offered at 1e-5
+    on S for the short workloads only (the 1000-step flat interface, the
+    500-step slab; tests/test_gpu_parity.py); on these long runs it is not,
+    and its errors are printed and checked only against regression, at
+    five times the values measured on one MI355X (front speed 3.9e-4, S
+    3.5e-4 after 3e5 steps; circle max|u| 6.5e-3 and S 4.1e-5)."""
     require_gpu()
     from paper_1907_13415_amd import lc
     nx, ny, g = 256, 4, 2.701
+    forms = ("fp32dev", "fp32sr", "mixed")
     res = {}
-    for prec in ("fp64", "fp32dev", "mixed"):
+    for prec in ("fp64",) + forms:
         s = _solver(inputs.paper_flat(nx, ny), g, prec=prec)
         o0 = _run_to(s, 100000)
         o1 = _run_to(s, 300000)
         v = (o1["ssum_half"] - o0["ssum_half"]) / (s_nematic(g) * ny) / 200000
         res[prec] = (v, s.export(lc.LC_FIELD_S))
     err = {p: (abs(res[p][0] - res["fp64"][0]) / abs(res["fp64"][0]),
-               float(np.abs(res[p][1] - res["fp64"][1]).max())) for p in ("fp32dev", "mixed")}
+               float(np.abs(res[p][1] - res["fp64"][1]).max())) for p in forms}
     c64 = _circle(2.707628)
     circ = {}
-    for p in ("fp32dev", "mixed"):
+    for p in forms:
         c = _circle(2.707628, prec=p)
         circ[p] = (abs(c[2] - c64[2]) / c64[2], float(np.abs(c[3].export(lc.LC_FIELD_S) -
                                                               c64[3].export(lc.LC_FIELD_S)).max()))
-    for p in ("fp32dev", "mixed"):
+    for p in forms:
         _say("%s vs fp64: flat front speed rel err %.2e, max|dS| %.2e after 3e5 steps; circle max|u| rel err "
              "%.2e, max|dS| %.2e after 35000 steps" % (p, err[p][0], err[p][1], circ[p][0], circ[p][1]))
+    for p in ("fp32sr", "mixed"):
+        assert err[p][1] < 1e-5 and circ[p][1] < 1e-5, p
     dv, dS = err["fp32dev"]
     du, dSc = circ["fp32dev"]
-    assert dv < 2e-3 and dS < 2e-3   # observed 3.9e-4, 3.5e-4 (the front moved ~20 sites)
-    assert du < 3e-2 and dSc < 2e-4  # observed 6.5e-3, 4.1e-5
-    assert err["mixed"][1] < 1e-5 and circ["mixed"][1] < 1e-5
+    assert dv < 2e-3 and dS < 2e-3   # regression check only (see above)
+    assert du < 3e-2 and dSc < 2e-4
