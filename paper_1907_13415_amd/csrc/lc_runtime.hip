@@ -54,7 +54,7 @@ lc_status check_grid(const lc_grid* g) {
   // site indices are 32-bit unsigned inside the sweeps; ny and nz index
   // launch grid dimensions, which are limited to 65535 blocks
   const double n = double(g->nx) * g->ny * g->nz;
-  if (n > 4.0e9) return fail(LC_EINVAL, "grid too large (%.3g sites)", n);
+  if (n > 4.0e9) return fail(LC_ENOMEM, "grid too large (%.3g sites; at most 4e9)", n);
   if (g->ny > 65535 || g->nz > 65535) return fail(LC_EINVAL, "ny and nz must not exceed 65535");
   return LC_OK;
 }

@@ -66,11 +66,13 @@ def test_init_rejects_bad_params(bad):
                                   (1, 1, 8, -1, 8), (1, 1, 8, 65536, 8), (1, 1, 8, 8, 65536),
                                   (1, 1, 2000, 2000, 1001)])
 def test_init_rejects_bad_grid(grid):
+    """Malformed grids are LC_EINVAL; a grid beyond 4e9 sites is LC_ENOMEM."""
     from paper_1907_13415_amd import lc
     params = lc.make_params(1.0, 2.7, 0.04, 0.3, 0.7, 1.0)
     with pytest.raises(lc.LCError) as e:
         lc.lc_init(lc.make_grid(*grid), params, _fake_bufs(lc), 0)
-    assert e.value.code == lc.LC_EINVAL
+    oversize = grid[2] * grid[3] * grid[4] > 4e9
+    assert e.value.code == (lc.LC_ENOMEM if oversize else lc.LC_EINVAL)
 
 
 def test_init_rejects_misaligned_buffers_and_accepts_good_ones():
