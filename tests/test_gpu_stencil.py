@@ -158,3 +158,40 @@ def test_isotropic_stencil_unsupported_combinations():
     ref.step(3)
     assert np.array_equal(s.export(lc.LC_FIELD_F), ref.export(lc.LC_FIELD_F))
     assert np.array_equal(s.export(lc.LC_FIELD_Q), ref.export(lc.LC_FIELD_Q))
+
+
+@pytest.mark.parametrize("lat,shape", [(0, (1, 1, 5)), (0, (1, 2, 3)), (0, (1, 3, 1)), (1, (1, 2, 3)),
+                                       (1, (2, 1, 3)), (1, (3, 2, 1)), (1, (1, 1, 1))])
+def test_isotropic_parity_degenerate_grids(lat, shape):
+    """Axes of length one and two, where several lattice neighbours of a site
+    are the same site (the periodic wrap), against the oracle to 1e-12."""
+    lc = _lc()
+    _say("isotropic degenerate lat %d shape %s" % (lat, shape))
+    q5, rel, f_gpu = _state(lc, lat, shape, 600 + sum(shape))
+    p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
+    s = lc.Solver(lattice_name(lat), "fp64", shape, p)
+    s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+    s.load(q5, f_gpu)
+    s.step(6)
+    f_ref, q_ref = oracle.run(lat, oracle.rest_populations(lat, shape, rel=rel), q5, p, 6, stencil=ISO)
+    ef = rel_err(s.export(lc.LC_FIELD_F), f_ref, SCALES["f"])
+    eq = rel_err(s.export(lc.LC_FIELD_Q), q_ref, SCALES["q"])
+    assert ef < TOL64 and eq < TOL64, (ef, eq)
+
+
+def test_isotropic_d3q19_single_plane_equals_d2q9_on_gpu():
+    """D3Q19 on one plane with in-plane directors gives the D2Q9 run with
+    the isotropic stencils too (the projected weights coincide)."""
+    lc = _lc()
+    w = inputs.paper_circle(48, 12.0, 0.0)
+    p = inputs.with_gamma(inputs.PAPER_PARAMS, 2.7076)
+    S = {}
+    for lat in ("D2Q9", "D3Q19"):
+        s = lc.Solver(lat, "fp64", w.shape[1:], p)
+        s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+        s.load(w)
+        s.step(2000)
+        S[lat] = s.export(lc.LC_FIELD_S)
+    d = float(np.abs(S["D2Q9"] - S["D3Q19"]).max())
+    _say("isotropic, D3Q19 on one plane vs D2Q9 after 2000 steps: max|dS| %.2e" % d)
+    assert d < 1e-12
