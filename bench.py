@@ -18,7 +18,7 @@ Prints one JSON line.  Inputs are resident in HBM before the timed region;
 timings use HIP events recorded on the stream the library launches on.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--no-cpu]
-                  [--quick] [--only batch|adjoint|mrt|fused] [--calibrate]
+                  [--quick] [--only batch|adjoint|mrt|fused|stencil] [--calibrate]
 """
 import argparse
 import hashlib
@@ -197,17 +197,51 @@ def mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site):
             "roofline_frac": round(bytes_site * N / (sum(rm["kernel_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def stencil_leg(torch, lc, w, args, dev, stream, N):
-    """The isotropic difference stencils (staged kernels) on the slab in
-    FP32, beside the staged kernels with the compact stencils."""
-    out = {}
+def _time_2d(torch, lc, q5, params, prec, variant, stencil, steps, dev, stream):
+    """ms per step of a D2Q9 grid (HIP events on the library stream)."""
+    with torch.cuda.stream(stream):
+        s = lc.Solver("D2Q9", prec, q5.shape[1:], params, device=dev, stream=stream)
+        s.set_variant(variant)
+        s.set_stencil(stencil)
+        s.load(q5)
+        s.step(20)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        s.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        del s
+    return t0.elapsed_time(t1) / steps
+
+
+def stencil_leg(torch, lc, inputs, w, args, dev, stream, N):
+    """The isotropic difference stencils: on the slab in FP32 (staged
+    kernels, the only ones that take them in 3D) beside the staged kernels
+    with the compact stencils; on a 2048^2 D2Q9 grid (the circle recipe
+    scaled up) in the two-sweep and staged kernels beside the compact
+    two-sweep step."""
+    out = {"slab_staged_fp32dev": {}}
     for name, st in (("compact", lc.LC_STENCIL_COMPACT), ("isotropic", lc.LC_STENCIL_ISOTROPIC)):
         r = run_slab(torch, lc, w, "fp32dev", min(args.steps, 100), min(args.warmup, 10), dev, stream,
                      variant=lc.LC_VARIANT_STAGED, stencil=st)
         del r["S"]
-        out[name] = {"mlups": round(N / (r["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(r["ms"], 5)}
+        out["slab_staged_fp32dev"][name] = {"mlups": round(N / (r["ms"] * 1e-3) / 1e6, 2),
+                                            "ms_per_step": round(r["ms"], 5)}
         torch.cuda.empty_cache()
-    return {"variant": "staged", "precision": "fp32dev", **out}
+    n2 = 2048
+    q5 = inputs.paper_circle(n2, n2 / 4.0)
+    params = inputs.with_gamma(inputs.PAPER_PARAMS, 2.7076)
+    d2 = {}
+    for name, variant, st in (("split_compact", lc.LC_VARIANT_SPLIT, lc.LC_STENCIL_COMPACT),
+                              ("split_isotropic", lc.LC_VARIANT_SPLIT, lc.LC_STENCIL_ISOTROPIC),
+                              ("staged_isotropic", lc.LC_VARIANT_STAGED, lc.LC_STENCIL_ISOTROPIC)):
+        ms = _time_2d(torch, lc, q5, params, "fp32dev", variant, st, 200, dev, stream)
+        d2[name] = {"mlups": round(n2 * n2 / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 5)}
+        torch.cuda.empty_cache()
+    out["circle2048_d2q9_fp32dev"] = d2
+    return out
 
 
 def s_nematic(g):
@@ -384,7 +418,7 @@ def main():
     ap.add_argument("--batch-tiles", help="LB,Q tile shapes of the batched leg instead of tuning (0..6)")
     ap.add_argument("--no-physics", action="store_true",
                     help="with --only batch: skip the 5000-step front-speed window (for counter runs)")
-    ap.add_argument("--only", choices=["batch", "adjoint", "mrt", "fused"],
+    ap.add_argument("--only", choices=["batch", "adjoint", "mrt", "fused", "stencil"],
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -420,6 +454,9 @@ def main():
     bytes_site = alg_bytes_per_site(19, 4)
     if args.only == "mrt":
         print(json.dumps({"mrt_fp32": mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)}), flush=True)
+        return
+    if args.only == "stencil":
+        print(json.dumps({"stencil_iso": stencil_leg(torch, lc, inputs, w, args, dev, stream, N)}), flush=True)
         return
     if args.only == "fused":
         print(json.dumps({"fused": fused_leg(torch, lc, w, args, dev, stream, N, bytes_site, 1.0, 1.0)}), flush=True)
@@ -497,7 +534,7 @@ def main():
         out["mixed"] = mixed
         out["mrt_fp32"] = mrt_leg(torch, lc, w, args, dev, stream, N, bytes_site)
         note("mrt leg done")
-        out["stencil_iso"] = stencil_leg(torch, lc, w, args, dev, stream, N)
+        out["stencil_iso"] = stencil_leg(torch, lc, inputs, w, args, dev, stream, N)
         note("stencil leg done")
         out["batch_sweep"] = run_batch(torch, lc, stream, dev, 128)
         note("batch leg done")

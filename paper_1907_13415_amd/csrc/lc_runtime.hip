@@ -307,6 +307,22 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY,
                 unsigned((c->g.nz + zc2 - 1) / zc2));
   hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
+  if constexpr (LAT == 0 && std::is_same<S, QT>::value) {
+    if (c->stencil == LC_STENCIL_ISOTROPIC) {  // two-dimensional sweeps with the isotropic stencils
+      if (c->coll == LC_COLL_MRT)
+        hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, true, QT, STENCIL_ISO>), g1,
+                           dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
+      else
+        hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, false, QT, STENCIL_ISO>), g1,
+                           dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
+      ctx_end(c, st, e, 0);
+      e = mark ? ctx_begin(c, st) : nullptr;
+      hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE, false, STENCIL_ISO>), g2,
+                         dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1, gd, kq, zc2, rec_q, 0u);
+      ctx_end(c, st, e, 1);
+      return;
+    }
+  }
   if (c->coll == LC_COLL_MRT)
     hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, true, QT>), g1,
                        dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
@@ -382,17 +398,20 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
 }
 
 // The variant a step runs: AUTO is the two-sweep variant, or the staged one
-// where only it provides the context's stencil.
+// where only it provides the context's stencil (the isotropic stencils on
+// D3Q19).
 static int resolved_variant(const lc_ctx* c) {
   if (c->variant != LC_VARIANT_AUTO) return c->variant;
-  return c->stencil == LC_STENCIL_ISOTROPIC ? LC_VARIANT_STAGED : LC_VARIANT_SPLIT;
+  return (c->stencil == LC_STENCIL_ISOTROPIC && c->g.lattice != LC_D2Q9) ? LC_VARIANT_STAGED : LC_VARIANT_SPLIT;
 }
 
 template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps(lc_ctx* c, int64_t n) {
   const int v = resolved_variant(c);
-  if (c->stencil == LC_STENCIL_ISOTROPIC && v != LC_VARIANT_STAGED)
-    return fail(LC_EUNSUPPORTED, "the isotropic stencils are provided by the staged variant");
+  if (c->stencil == LC_STENCIL_ISOTROPIC && v != LC_VARIANT_STAGED &&
+      !(v == LC_VARIANT_SPLIT && c->g.lattice == LC_D2Q9))
+    return fail(LC_EUNSUPPORTED,
+                "the isotropic stencils are provided by the staged variant and, on D2Q9, the two-sweep one");
   if (v == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV, QT>(c, n);
   if (v == LC_VARIANT_FUSED) return run_steps_fused<LAT, S, DEV, QT>(c, n);
   return run_steps_staged<LAT, S, DEV, QT>(c, n);

@@ -13,7 +13,11 @@
 // the owning thread (a three-plane window), so nothing is recomputed along
 // z.  Every index is taken modulo the grid (periodic), so any grid size,
 // including sizes smaller than the tile, is handled.  On two-dimensional
-// lattices the block treats its single plane without the z pipeline.
+// lattices the block treats its single plane without the z pipeline, and
+// there the sweeps also take the isotropic stencils of lc_staged.h
+// (template argument ST): their in-plane diagonal neighbours are in the LDS
+// regions, and the rings of stress and predictor values gain the four
+// corner sites.
 #pragma once
 
 #include "lc_staged.h"
@@ -92,6 +96,53 @@ __device__ __forceinline__ void stencil_lds(const S (*m)[R2], const S (*zp)[R2],
   d[1] = Sym<S>{dy[0], dy[1], dy[2], dy[3], dy[4]};
   d[2] = Sym<S>{dz[0], dz[1], dz[2], dz[3], dz[4]};
   L = Sym<S>{lap[0], lap[1], lap[2], lap[3], lap[4]};
+}
+
+// Isotropic stencil (D2Q9) of a symmetric tensor from an LDS plane with row
+// stride W: the centre value, the gradients (times two with HALF unset)
+// and the Laplacian, each from the pairs of opposite velocities.
+template <typename S, int W, int RN, bool HALF = true>
+__device__ __forceinline__ void stencil_lds_iso2(const S (*m)[RN], int k, Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
+  using Lt = Lattice<0>;
+  S v[5], lap[5], dx[5], dy[5];
+#pragma unroll
+  for (int q = 0; q < 5; q++) {
+    const S cc = m[q][k];
+    S gx = S(0), gy = S(0), l = S(0);
+#pragma unroll
+    for (int i = 1; i < Lt::q; i++) {
+      if (Lt::opp(i) < i) continue;
+      const int o = Lt::cx(i) + W * Lt::cy(i);
+      const S vp = m[q][k + o], vm = m[q][k - o];
+      const S wg = S((HALF ? 3.0 : 6.0) * Lt::w(i)), wl = S(6.0 * Lt::w(i));
+      const S df = wg * (vp - vm);
+      if (Lt::cx(i) != 0) gx += Lt::cx(i) > 0 ? df : -df;
+      if (Lt::cy(i) != 0) gy += Lt::cy(i) > 0 ? df : -df;
+      l += wl * ((vp - cc) + (vm - cc));
+    }
+    v[q] = cc;
+    dx[q] = gx;
+    dy[q] = gy;
+    lap[q] = l;
+  }
+  c = Sym<S>{v[0], v[1], v[2], v[3], v[4]};
+  d[0] = Sym<S>{dx[0], dx[1], dx[2], dx[3], dx[4]};
+  d[1] = Sym<S>{dy[0], dy[1], dy[2], dy[3], dy[4]};
+  d[2] = sym_zero<S>();
+  L = Sym<S>{lap[0], lap[1], lap[2], lap[3], lap[4]};
+}
+
+// R1 coordinates of ring point k of a TX x TY tile: the one-site ring of
+// Tile::ring for k < RING, then its four corners.
+template <int TX, int TY>
+__device__ __forceinline__ void ring_point(int k, int& i, int& j) {
+  if (k < Tile<TX, TY>::RING) {
+    Tile<TX, TY>::ring(k, i, j);
+  } else {
+    const int cn = k - Tile<TX, TY>::RING;
+    i = (cn & 1) ? TX + 1 : 0;
+    j = (cn & 2) ? TY + 1 : 0;
+  }
 }
 
 // The NC component arrays of an LDS region: the first NA of type A, the
@@ -204,7 +255,8 @@ __device__ __forceinline__ void store_out(S* p, S v) {
 // and of the molecular field, stress and body force (S, or double in the
 // mixed-precision form, whose populations and collision stay in S), and of
 // the velocity handed to sweep 2; cq holds the constants in that type.
-template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false, bool STREAM_F = false, typename QT = S>
+template <int LAT, typename S, bool DEV, int TX, int TY, bool MRT = false, bool STREAM_F = false, typename QT = S,
+          int ST = STENCIL_COMPACT>
 __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const S* __restrict__ fin,
                                               S* __restrict__ fout, QT* __restrict__ uout, const GridDims& g,
                                               const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz,
@@ -217,9 +269,17 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
   // tau_{a x} is needed at x +- 1 (rows 1..TY of the R1 region, all
   // columns) and tau_{a y} at y +- 1 (columns 1..TX, all rows)
   constexpr int NXA = T::W1 * TY, NYA = TX * T::H1;
+  // isotropic stencils (2D): the body force needs tau_{a x} and tau_{a y}
+  // at the eight neighbours, so the whole stress of the tile, its ring and
+  // the ring's corners goes to LDS (sTi[a][b][R1 index])
+  constexpr bool ISO = ST == STENCIL_ISO;
+  static_assert(!ISO || DIM == 2, "the sweeps take the isotropic stencils on two-dimensional lattices only");
+  static_assert(!ISO || T::RING + 4 <= T::NT, "tile too thin for its ring and corners");
+  constexpr int NI = ISO ? 2 : 1, RI = ISO ? T::R1 : 1;
   __shared__ QT sQ[NQP][5][T::R2];
-  __shared__ QT sTx[NTP][DIM][NXA];
-  __shared__ QT sTy[NTP][DIM][NYA];
+  __shared__ QT sTx[NTP][DIM][ISO ? 1 : NXA];
+  __shared__ QT sTy[NTP][DIM][ISO ? 1 : NYA];
+  __shared__ QT sTi[NI][NI][RI];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   const int x0 = bx * TX, y0 = by * TY;
@@ -231,7 +291,10 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
   // stress at the R1 point (i, j) of plane slot m with z neighbours zp/zm
   auto tau_point = [&](int m, int zp, int zm, int i, int j, QT (&t)[3][3]) {
     Sym<QT> q, Lq, d[3];
-    stencil_lds<QT, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
+    if constexpr (ISO)
+      stencil_lds_iso2<QT, T::W2, T::R2>(sQ[m], T::r2(i, j), q, d, Lq);
+    else
+      stencil_lds<QT, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
     const Sym<QT> H = molecular_field(q, Lq, cq);
     stress(q, H, d, cq, t);
   };
@@ -251,49 +314,70 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
   // stress of the whole region of plane slot m into sT[ts]; returns the
   // owner's tau_{a z}
   auto tau_plane = [&](int m, int zp, int zm, int ts, QT (&tz)[3]) {
-    {  // the owner's site
-      QT t[3][3];
-      tau_point(m, zp, zm, tx + 1, ty + 1, t);
-      const int kx = (tx + 1) + T::W1 * ty, ky = tx + TX * (ty + 1);
-#pragma unroll
-      for (int a = 0; a < DIM; a++) {
-        sTx[ts][a][kx] = t[a][0];
-        sTy[ts][a][ky] = t[a][1];
-      }
-#pragma unroll
-      for (int a = 0; a < 3; a++) tz[a] = t[a][2];
-    }
-    if (tid < T::RING) {  // a ring site
-      int i, j;
-      T::ring(tid, i, j);
-      const bool row_ring = j == 0 || j == TY + 1;
-      if constexpr (COLS) {
-        QT col[3];
-        tau_col(m, zp, zm, i, j, row_ring ? 1 : 0, col);
-        if (row_ring) {
-          const int ky = (i - 1) + TX * j;
-#pragma unroll
-          for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = col[a];
-        } else {
-          const int kx = i + T::W1 * (j - 1);
-#pragma unroll
-          for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = col[a];
-        }
-      } else {
+    if constexpr (ISO) {  // every site of the R1 region, corners included
+      auto put = [&](int i, int j) {
         QT t[3][3];
         tau_point(m, zp, zm, i, j, t);
-        if (row_ring) {
-          const int ky = (i - 1) + TX * j;
+        const int k = i + T::W1 * j;
 #pragma unroll
-          for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+          for (int b = 0; b < 2; b++) sTi[a][b][k] = t[a][b];
+      };
+      put(tx + 1, ty + 1);
+      if (tid < T::RING + 4) {
+        int i, j;
+        ring_point<TX, TY>(tid, i, j);
+        put(i, j);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; a++) tz[a] = QT(0);
+    } else {
+      {  // the owner's site
+        QT t[3][3];
+        tau_point(m, zp, zm, tx + 1, ty + 1, t);
+        const int kx = (tx + 1) + T::W1 * ty, ky = tx + TX * (ty + 1);
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+          sTx[ts][a][kx] = t[a][0];
+          sTy[ts][a][ky] = t[a][1];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) tz[a] = t[a][2];
+      }
+      if (tid < T::RING) {  // a ring site
+        int i, j;
+        T::ring(tid, i, j);
+        const bool row_ring = j == 0 || j == TY + 1;
+        if constexpr (COLS) {
+          QT col[3];
+          tau_col(m, zp, zm, i, j, row_ring ? 1 : 0, col);
+          if (row_ring) {
+            const int ky = (i - 1) + TX * j;
+#pragma unroll
+            for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = col[a];
+          } else {
+            const int kx = i + T::W1 * (j - 1);
+#pragma unroll
+            for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = col[a];
+          }
         } else {
-          const int kx = i + T::W1 * (j - 1);
+          QT t[3][3];
+          tau_point(m, zp, zm, i, j, t);
+          if (row_ring) {
+            const int ky = (i - 1) + TX * j;
 #pragma unroll
-          for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = t[a][0];
+            for (int a = 0; a < DIM; a++) sTy[ts][a][ky] = t[a][1];
+          } else {
+            const int kx = i + T::W1 * (j - 1);
+#pragma unroll
+            for (int a = 0; a < DIM; a++) sTx[ts][a][kx] = t[a][0];
+          }
         }
       }
-    }
+  }
   };
+
   // periodic neighbour offsets of the owner's site in plane z (unsigned
   // arithmetic modulo 2^32 on in-range indices)
   struct Off {
@@ -338,11 +422,36 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
     if (!own) return;
     const int kx = (tx + 1) + T::W1 * ty, ky = tx + TX * (ty + 1);
     S F[3] = {S(0), S(0), S(0)};
+    if constexpr (ISO) {  // F_a = 3 sum_i w_i sum_b c_ib tau_ab(x + c_i), over pairs
+      using Lt = Lattice<0>;
+      const int k1 = (tx + 1) + T::W1 * (ty + 1);
 #pragma unroll
-    for (int a = 0; a < DIM; a++) {
-      QT acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + TX] - sTy[ts][a][ky - TX]);
-      if constexpr (DIM == 3) acc += tzp[a] - tzm[a];
-      F[a] = S(QT(0.5) * acc);
+      for (int a = 0; a < 2; a++) {
+        QT acc = QT(0);
+#pragma unroll
+        for (int i = 1; i < Lt::q; i++) {
+          if (Lt::opp(i) < i) continue;
+          const int o = Lt::cx(i) + T::W1 * Lt::cy(i);
+          QT dsum = QT(0);
+          if (Lt::cx(i) != 0) {
+            const QT dt = sTi[a][0][k1 + o] - sTi[a][0][k1 - o];
+            dsum += Lt::cx(i) > 0 ? dt : -dt;
+          }
+          if (Lt::cy(i) != 0) {
+            const QT dt = sTi[a][1][k1 + o] - sTi[a][1][k1 - o];
+            dsum += Lt::cy(i) > 0 ? dt : -dt;
+          }
+          acc += QT(3.0 * Lt::w(i)) * dsum;
+        }
+        F[a] = S(acc);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < DIM; a++) {
+        QT acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + TX] - sTy[ts][a][ky - TX]);
+        if constexpr (DIM == 3) acc += tzp[a] - tzm[a];
+        F[a] = S(QT(0.5) * acc);
+      }
     }
     const uint32_t s = uint32_t(x) + uint32_t(g.nx) * (uint32_t(y) + uint32_t(g.ny) * uint32_t(z));
     S rho, mass, u[3];
@@ -400,13 +509,14 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
   }
 }
 
-template <int LAT, typename S, bool DEV, int TX, int TY, int WPE, bool MRT = false, typename QT = S>
+template <int LAT, typename S, bool DEV, int TX, int TY, int WPE, bool MRT = false, typename QT = S,
+          int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_lb(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, QT* __restrict__ uout,
              GridDims g, Coef<S> c, Coef<QT> cq, int zc, S* __restrict__ rec) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  split_lb_body<LAT, S, DEV, TX, TY, MRT, false, QT>(Qin, fin, fout, uout, g, c, cq, zc, t % gridDim.x,
+  split_lb_body<LAT, S, DEV, TX, TY, MRT, false, QT, ST>(Qin, fin, fout, uout, g, c, cq, zc, t % gridDim.x,
                                                      (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y), rec);
 }
 
@@ -415,7 +525,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE
 // type of Q, of the velocity and of the arithmetic.
 // SR: the float form with stochastic rounding (molecular field summed in
 // double, Q(n+1) rounded stochastically with the per-step key srkey).
-template <int LAT, typename S, int TX, int TY, bool SR = false>
+template <int LAT, typename S, int TX, int TY, bool SR = false, int ST = STENCIL_COMPACT>
 __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S* __restrict__ uin,
                                              S* __restrict__ Qout, const GridDims& g, const Coef<S>& c, int zc,
                                              int bx, int by, int bz, S* __restrict__ rec = nullptr,
@@ -433,6 +543,11 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   constexpr int NP = DIM == 3 ? 3 : 1;
   constexpr int NPS = (DIM == 3 && !ZREG) ? 3 : 1;
   constexpr int NC = 5 + DIM;  // Q components then u components
+  // isotropic stencils (2D): the predictor also runs at the ring's corners
+  constexpr bool ISO = ST == STENCIL_ISO;
+  static_assert(!ISO || DIM == 2, "the sweeps take the isotropic stencils on two-dimensional lattices only");
+  constexpr int NRING = ISO ? T::RING + 4 : T::RING;
+  static_assert(NRING <= T::NT, "tile too thin for its ring");
   __shared__ S sQ[NP][NC][T::R2];
   __shared__ S sP[NPS][5][T::R1];
 
@@ -464,12 +579,33 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   auto pred_point = [&](int m, int zp, int zm, int i, int j, Stash& st) {
     const int k = T::r2(i, j);
     Sym<S> q, Lq, d[3];
-    stencil_lds<S, DIM, T::W2, T::R2, false>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
+    if constexpr (ISO)
+      stencil_lds_iso2<S, T::W2, T::R2, false>(sQ[m], k, q, d, Lq);
+    else
+      stencil_lds<S, DIM, T::W2, T::R2, false>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
     const Sym<S> H = SR ? molecular_field_exact(q, Lq, c) : molecular_field(q, Lq, c);
     S u[3], G[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       u[a] = a < DIM ? sQ[m][5 + a][k] * S(0.5) : S(0);
+      if constexpr (ISO) {  // undivided: 6 sum_i w_i c_ib u_a(x + c_i), over pairs
+        using Lt = Lattice<0>;
+        S g0 = S(0), g1 = S(0);
+        if (a < DIM) {
+#pragma unroll
+          for (int n = 1; n < Lt::q; n++) {
+            if (Lt::opp(n) < n) continue;
+            const int o = Lt::cx(n) + T::W2 * Lt::cy(n);
+            const S du = S(6.0 * Lt::w(n)) * (sQ[m][5 + a][k + o] - sQ[m][5 + a][k - o]);
+            if (Lt::cx(n) != 0) g0 += Lt::cx(n) > 0 ? du : -du;
+            if (Lt::cy(n) != 0) g1 += Lt::cy(n) > 0 ? du : -du;
+          }
+        }
+        G[a][0] = g0;
+        G[a][1] = g1;
+        G[a][2] = S(0);
+        continue;
+      }
       G[a][0] = a < DIM ? sQ[m][5 + a][k + 1] - sQ[m][5 + a][k - 1] : S(0);
       G[a][1] = a < DIM ? sQ[m][5 + a][k + T::W2] - sQ[m][5 + a][k - T::W2] : S(0);
       if constexpr (DIM == 3)
@@ -496,6 +632,16 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   // from sP[b], the centre pc and the z neighbours pzp / pzm (3D)
   auto corr_site = [&](int z, int b, const Stash& st, const Sym<S>& pc, const Sym<S>& pzp, const Sym<S>& pzm) {
     if (!own) return;
+    if constexpr (ISO) {
+      Sym<S> pcc, Lp, d[3];
+      stencil_lds_iso2<S, T::W1, T::R1, false>(sP[b], k1, pcc, d, Lp);
+      const Sym<S> H = SR ? molecular_field_exact(pcc, Lp, c) : molecular_field(pcc, Lp, c);
+      const Sym<S> Rp = be_rate_flow<S, true>(pcc, H, d, st.fl, c);
+      const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      if (rec) store_sym(rec, N, s, pcc);
+      store_q_update<S, SR>(Qout, N, s, st.q, st.r, Rp, srkey);
+      return;
+    }
     const S vc[5] = {pc.xx, pc.xy, pc.xz, pc.yy, pc.yz};
     const S vzp[5] = {pzp.xx, pzp.xy, pzp.xz, pzp.yy, pzp.yz};
     const S vzm[5] = {pzm.xx, pzm.xy, pzm.xz, pzm.yy, pzm.yz};
@@ -533,9 +679,9 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     Stash st;
     const Sym<S> pc = pred_point(0, 0, 0, tx + 1, ty + 1, st);
     store_pred(0, tx + 1, ty + 1, pc);
-    if (tid < T::RING) {
+    if (tid < NRING) {
       int i, j;
-      T::ring(tid, i, j);
+      ring_point<TX, TY>(tid, i, j);
       Stash tmp;
       store_pred(0, i, j, pred_point(0, 0, 0, i, j, tmp));
     }
@@ -602,13 +748,13 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   }
 }
 
-template <int LAT, typename S, int TX, int TY, int WPE, bool SR = false>
+template <int LAT, typename S, int TX, int TY, int WPE, bool SR = false, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WPE)))
     split_q(const S* __restrict__ Qin, const S* __restrict__ uin, S* __restrict__ Qout, GridDims g, Coef<S> c,
             int zc, S* __restrict__ rec, uint32_t srkey) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  split_q_body<LAT, S, TX, TY, SR>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
+  split_q_body<LAT, S, TX, TY, SR, ST>(Qin, uin, Qout, g, c, zc, t % gridDim.x, (t / gridDim.x) % gridDim.y,
                                    t / (gridDim.x * gridDim.y), rec, srkey);
 }
 

@@ -1,9 +1,9 @@
 """GPU parity of the isotropic difference stencils (lc_set_stencil) against
 the oracle's isotropic option (oracle.run(..., stencil="isotropic")).
 
-The library's staged kernels take every derivative of the step (grad Q,
-lap Q, the divergence of the stress, grad u) from the lattice's velocities
-and weights when LC_STENCIL_ISOTROPIC is set.  Double precision must agree
+The library's staged kernels, and on D2Q9 its two-sweep kernels, take every
+derivative of the step (grad Q, lap Q, the divergence of the stress, grad u)
+from the lattice's velocities and weights when LC_STENCIL_ISOTROPIC is set.  Double precision must agree
 with the oracle to 1e-12 in the normwise metric of gpu_util.rel_err, for the
 state, the derived fields and the observables, with BGK and MRT collisions;
 the FP32 deviation form must keep S within 1e-5.  The calls the stencils do
@@ -45,17 +45,21 @@ def _state(lc, lat, shape, seed):
     return q5, rel, w.reshape((q, 1, 1, 1)) * (1.0 + rel)
 
 
+# variant 0 (AUTO): the two-sweep kernels on D2Q9, the staged ones on D3Q19;
+# variant 1: the staged kernels
 @pytest.mark.parametrize("coll", ["bgk", "mrt"])
-@pytest.mark.parametrize("lat,shape", [(0, (1, 23, 37)), (0, (1, 70, 130)), (1, (9, 11, 13)), (1, (17, 6, 67))])
-def test_isotropic_parity_random_state_ragged(lat, shape, coll):
+@pytest.mark.parametrize("lat,shape,variant", [(0, (1, 23, 37), 0), (0, (1, 70, 130), 0), (0, (1, 23, 37), 1),
+                                               (0, (1, 70, 130), 1), (1, (9, 11, 13), 0), (1, (17, 6, 67), 0)])
+def test_isotropic_parity_random_state_ragged(lat, shape, variant, coll):
     """Random Q and perturbed populations on ragged grids spanning several
     site tiles, 12 steps: state, rho, u and the body force, and the
     observables, against the oracle with the same stencils."""
     lc = _lc()
-    _say("isotropic parity lat %d shape %s %s" % (lat, shape, coll))
+    _say("isotropic parity lat %d shape %s variant %d %s" % (lat, shape, variant, coll))
     q5, rel, f_gpu = _state(lc, lat, shape, 500 + lat)
     p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
     s = lc.Solver(lattice_name(lat), "fp64", shape, p)
+    s.set_variant(variant)
     s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
     rates = None
     if coll == "mrt":
@@ -89,10 +93,11 @@ def test_isotropic_parity_random_state_ragged(lat, shape, coll):
         assert abs(o["ssum_half"] - r["ssum_half"]) < 1e-12 * r["ssum"]
 
 
-def test_isotropic_flat_interface_1000_steps_fp64_and_fp32():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_isotropic_flat_interface_1000_steps_fp64_and_fp32(variant):
     """The flat-interface workload (128 x 16, paper parameters) for 1000
-    steps with isotropic stencils: FP64 to 1e-12, the FP32 deviation form
-    within 1e-5 on S."""
+    steps with isotropic stencils, two-sweep (0) and staged (1) kernels:
+    FP64 to 1e-12, the FP32 deviation form within 1e-5 on S."""
     lc = _lc()
     w = inputs.config0()
     p = inputs.PAPER_PARAMS
@@ -101,6 +106,7 @@ def test_isotropic_flat_interface_1000_steps_fp64_and_fp32():
                            + 2 * (q_ref[1] ** 2 + q_ref[2] ** 2 + q_ref[4] ** 2)))
     for prec in ("fp64", "fp32dev"):
         s = lc.Solver("D2Q9", prec, w.shape, p)
+        s.set_variant(variant)
         s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
         s.load(w.q5)
         s.step(1000)
@@ -134,18 +140,20 @@ def test_isotropic_slab_32cubed_d3q19_500_steps():
     assert dj < 1e-10
 
 
-def test_isotropic_stencil_unsupported_combinations():
-    """Explicit split or fused variants with the isotropic stencils, and the
-    reverse step, fail with LC_EUNSUPPORTED; compact again runs the split
-    sweeps bit for bit as a fresh context does."""
+@pytest.mark.parametrize("lat", [0, 1])
+def test_isotropic_stencil_unsupported_combinations(lat):
+    """The fused variant with the isotropic stencils, and on D3Q19 the
+    explicit two-sweep variant, fail with LC_EUNSUPPORTED; compact again
+    runs the split sweeps bit for bit as a fresh context does."""
     lc = _lc()
-    shape = (1, 16, 24)
-    q5, rel, f_gpu = _state(lc, 0, shape, 7)
+    shape = (1, 16, 24) if lat == 0 else (6, 8, 10)
+    q5, rel, f_gpu = _state(lc, lat, shape, 7)
     p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
-    s = lc.Solver("D2Q9", "fp64", shape, p)
+    name = lattice_name(lat)
+    s = lc.Solver(name, "fp64", shape, p)
     s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
     s.load(q5, f_gpu)
-    for v in (lc.LC_VARIANT_SPLIT, lc.LC_VARIANT_FUSED):
+    for v in ((lc.LC_VARIANT_FUSED,) if lat == 0 else (lc.LC_VARIANT_SPLIT, lc.LC_VARIANT_FUSED)):
         s.set_variant(v)
         with pytest.raises(lc.LCError) as e:
             s.step(1)
@@ -153,7 +161,7 @@ def test_isotropic_stencil_unsupported_combinations():
     s.set_variant(lc.LC_VARIANT_AUTO)
     s.set_stencil(lc.LC_STENCIL_COMPACT)
     s.step(3)
-    ref = lc.Solver("D2Q9", "fp64", shape, p)
+    ref = lc.Solver(name, "fp64", shape, p)
     ref.load(q5, f_gpu)
     ref.step(3)
     assert np.array_equal(s.export(lc.LC_FIELD_F), ref.export(lc.LC_FIELD_F))
@@ -195,3 +203,24 @@ def test_isotropic_d3q19_single_plane_equals_d2q9_on_gpu():
     d = float(np.abs(S["D2Q9"] - S["D3Q19"]).max())
     _say("isotropic, D3Q19 on one plane vs D2Q9 after 2000 steps: max|dS| %.2e" % d)
     assert d < 1e-12
+
+
+def test_isotropic_two_sweep_and_staged_agree_on_d2q9():
+    """The two kernel variants evaluate the same isotropic sums in different
+    orders: on the paper's circle they agree to rounding after 3000 steps,
+    in double and in the FP32 deviation form."""
+    lc = _lc()
+    q5 = inputs.paper_circle(64, 16.0, 20.0)
+    p = inputs.with_gamma(inputs.PAPER_PARAMS, 2.7076)
+    for prec, tol in (("fp64", 1e-12), ("fp32dev", 1e-5)):
+        S = {}
+        for v in (0, 1):
+            s = lc.Solver("D2Q9", prec, q5.shape[1:], p)
+            s.set_variant(v)
+            s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+            s.load(q5)
+            s.step(3000)
+            S[v] = s.export(lc.LC_FIELD_S)
+        d = float(np.abs(S[0] - S[1]).max())
+        _say("isotropic %s, two-sweep vs staged after 3000 steps: max|dS| %.2e" % (prec, d))
+        assert d < tol
