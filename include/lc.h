@@ -202,9 +202,10 @@ lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 
 /* Choose the kernel variant (LC_VARIANT_*) of the step of Sec. 1.2 (the
  * same arithmetic in each; SPLIT and FUSED agree bit for bit).  AUTO (the
- * default) picks the fastest the build provides for the context's stencil:
- * the two-sweep variant, or the staged one for LC_STENCIL_ISOTROPIC on
- * D3Q19.  FUSED runs every
+ * default) picks the fastest the build provides for the context's stencil
+ * and grid: the two-sweep variant; the staged one for LC_STENCIL_ISOTROPIC
+ * on D3Q19; FUSED for compact stencils on D2Q9 grids of at most 65536
+ * sites, where launches are latency bound.  FUSED runs every
  * stage of a step in one pass over the grid: a block recomputes the
  * stress, moments and predictor on shrinking rings around its tile instead
  * of reading them back from HBM.  LC_EUNSUPPORTED for the staged variant in
