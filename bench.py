@@ -217,19 +217,23 @@ def _time_2d(torch, lc, q5, params, prec, variant, stencil, steps, dev, stream):
 
 
 def stencil_leg(torch, lc, inputs, w, args, dev, stream, N):
-    """The isotropic difference stencils: on the slab in FP32 (staged
-    kernels, the only ones that take them in 3D) beside the staged kernels
-    with the compact stencils; on a 2048^2 D2Q9 grid (the circle recipe
-    scaled up) in the two-sweep and staged kernels beside the compact
-    two-sweep step."""
-    out = {"slab_staged_fp32dev": {}}
-    for name, st in (("compact", lc.LC_STENCIL_COMPACT), ("isotropic", lc.LC_STENCIL_ISOTROPIC)):
-        r = run_slab(torch, lc, w, "fp32dev", min(args.steps, 100), min(args.warmup, 10), dev, stream,
-                     variant=lc.LC_VARIANT_STAGED, stencil=st)
-        del r["S"]
-        out["slab_staged_fp32dev"][name] = {"mlups": round(N / (r["ms"] * 1e-3) / 1e6, 2),
-                                            "ms_per_step": round(r["ms"], 5)}
-        torch.cuda.empty_cache()
+    """The isotropic difference stencils in the two-sweep and staged kernels,
+    beside the compact stencils: on the slab in FP32 and FP64, and on a
+    2048^2 D2Q9 grid (the circle recipe scaled up) in FP32."""
+    out = {}
+    for prec in ("fp32dev", "fp64"):
+        leg = {}
+        for name, variant, st in (("split_compact", lc.LC_VARIANT_SPLIT, lc.LC_STENCIL_COMPACT),
+                                  ("split_isotropic", lc.LC_VARIANT_SPLIT, lc.LC_STENCIL_ISOTROPIC),
+                                  ("staged_compact", lc.LC_VARIANT_STAGED, lc.LC_STENCIL_COMPACT),
+                                  ("staged_isotropic", lc.LC_VARIANT_STAGED, lc.LC_STENCIL_ISOTROPIC)):
+            r = run_slab(torch, lc, w, prec, min(args.steps, 100), min(args.warmup, 10), dev, stream,
+                         variant=variant, stencil=st)
+            del r["S"]
+            leg[name] = {"mlups": round(N / (r["ms"] * 1e-3) / 1e6, 2), "ms_per_step": round(r["ms"], 5),
+                         "kernel_ms": [round(v, 5) for v in r["kernel_ms"]]}
+            torch.cuda.empty_cache()
+        out["slab_%s" % prec] = leg
     n2 = 2048
     q5 = inputs.paper_circle(n2, n2 / 4.0)
     params = inputs.with_gamma(inputs.PAPER_PARAMS, 2.7076)

@@ -307,14 +307,18 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY,
                 unsigned((c->g.nz + zc2 - 1) / zc2));
   hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
-  if constexpr (LAT == 0 && std::is_same<S, QT>::value) {
-    if (c->stencil == LC_STENCIL_ISOTROPIC) {  // two-dimensional sweeps with the isotropic stencils
+  if constexpr (std::is_same<S, QT>::value) {
+    if (c->stencil == LC_STENCIL_ISOTROPIC) {  // the sweeps with the isotropic stencils
+      // stress/LB tiles whose stress ring of three planes (3D) leaves room
+      // for two blocks per CU: 32x8 (float), 16x8 (double in 3D)
+      constexpr int ITX = (C::d3 && sizeof(S) == 8) ? 16 : 32, ITY = 8;
+      const dim3 gi((c->g.nx + ITX - 1) / ITX, (c->g.ny + ITY - 1) / ITY, unsigned((c->g.nz + zc1 - 1) / zc1));
       if (c->coll == LC_COLL_MRT)
-        hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, true, QT, STENCIL_ISO>), g1,
-                           dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
+        hipLaunchKernelGGL((split_lb<LAT, S, DEV, ITX, ITY, 1, true, QT, STENCIL_ISO>), gi, dim3(ITX, ITY), 0, st, q0,
+                           f0, f1, u, gd, k, kq, zc1, rec_lb);
       else
-        hipLaunchKernelGGL((split_lb<LAT, S, DEV, C::LB_TX, C::LB_TY, C::LB_WPE, false, QT, STENCIL_ISO>), g1,
-                           dim3(C::LB_TX, C::LB_TY), 0, st, q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
+        hipLaunchKernelGGL((split_lb<LAT, S, DEV, ITX, ITY, 1, false, QT, STENCIL_ISO>), gi, dim3(ITX, ITY), 0, st,
+                           q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
       ctx_end(c, st, e, 0);
       e = mark ? ctx_begin(c, st) : nullptr;
       hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE, false, STENCIL_ISO>), g2,
@@ -397,17 +401,15 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
   return hip_check(hipGetLastError(), "step launch");
 }
 
-// The variant a step runs.  AUTO is the two-sweep variant, except: the
-// staged one where only it provides the context's stencil (the isotropic
-// stencils on D3Q19), and the single pass on two-dimensional grids of at
+// The variant a step runs.  AUTO is the two-sweep variant, except the
+// single pass (with the compact stencils) on two-dimensional grids of at
 // most 65536 sites, whose launches are latency bound (one wave per SIMD)
 // and where one launch per step instead of two measured 4-6% faster at
 // 128^2 and 256^2 (bit-identical results).
 constexpr int64_t AUTO_FUSED_MAX_SITES = 65536;
 static int resolved_variant(const lc_ctx* c) {
   if (c->variant != LC_VARIANT_AUTO) return c->variant;
-  if (c->stencil == LC_STENCIL_ISOTROPIC)
-    return c->g.lattice == LC_D2Q9 ? LC_VARIANT_SPLIT : LC_VARIANT_STAGED;
+  if (c->stencil == LC_STENCIL_ISOTROPIC) return LC_VARIANT_SPLIT;
   if (c->g.lattice == LC_D2Q9 && c->L.N <= AUTO_FUSED_MAX_SITES) return LC_VARIANT_FUSED;
   return LC_VARIANT_SPLIT;
 }
@@ -415,10 +417,8 @@ static int resolved_variant(const lc_ctx* c) {
 template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps(lc_ctx* c, int64_t n) {
   const int v = resolved_variant(c);
-  if (c->stencil == LC_STENCIL_ISOTROPIC && v != LC_VARIANT_STAGED &&
-      !(v == LC_VARIANT_SPLIT && c->g.lattice == LC_D2Q9))
-    return fail(LC_EUNSUPPORTED,
-                "the isotropic stencils are provided by the staged variant and, on D2Q9, the two-sweep one");
+  if (c->stencil == LC_STENCIL_ISOTROPIC && v == LC_VARIANT_FUSED)
+    return fail(LC_EUNSUPPORTED, "the isotropic stencils are provided by the two-sweep and staged variants");
   if (v == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV, QT>(c, n);
   if (v == LC_VARIANT_FUSED) return run_steps_fused<LAT, S, DEV, QT>(c, n);
   return run_steps_staged<LAT, S, DEV, QT>(c, n);

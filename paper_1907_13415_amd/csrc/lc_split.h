@@ -13,11 +13,12 @@
 // the owning thread (a three-plane window), so nothing is recomputed along
 // z.  Every index is taken modulo the grid (periodic), so any grid size,
 // including sizes smaller than the tile, is handled.  On two-dimensional
-// lattices the block treats its single plane without the z pipeline, and
-// there the sweeps also take the isotropic stencils of lc_staged.h
-// (template argument ST): their in-plane diagonal neighbours are in the LDS
-// regions, and the rings of stress and predictor values gain the four
-// corner sites.
+// lattices the block treats its single plane without the z pipeline.
+// Both sweeps also take the isotropic stencils of lc_staged.h (template
+// argument ST): the diagonal neighbours of Q and u are in the LDS regions,
+// the rings of stress and predictor values gain the four corner sites, and
+// in 3D the whole stress and the predictor are kept in three-plane LDS
+// rings for the neighbours in the planes above and below.
 #pragma once
 
 #include "lc_staged.h"
@@ -129,6 +130,43 @@ __device__ __forceinline__ void stencil_lds_iso2(const S (*m)[RN], int k, Sym<S>
   d[0] = Sym<S>{dx[0], dx[1], dx[2], dx[3], dx[4]};
   d[1] = Sym<S>{dy[0], dy[1], dy[2], dy[3], dy[4]};
   d[2] = sym_zero<S>();
+  L = Sym<S>{lap[0], lap[1], lap[2], lap[3], lap[4]};
+}
+
+// Isotropic stencil (D3Q19) of a symmetric tensor from three LDS planes
+// (centre m, above zp, below zm) with row stride W.
+template <typename S, int W, int RN, bool HALF = true>
+__device__ __forceinline__ void stencil_lds_iso3(const S (*m)[RN], const S (*zp)[RN], const S (*zm)[RN], int k,
+                                                 Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
+  using Lt = Lattice<1>;
+  S v[5], lap[5], g[3][5];
+#pragma unroll
+  for (int q = 0; q < 5; q++) {
+    const S cc = m[q][k];
+    S gx = S(0), gy = S(0), gz = S(0), l = S(0);
+#pragma unroll
+    for (int i = 1; i < Lt::q; i++) {
+      if (Lt::opp(i) < i) continue;
+      const int o = Lt::cx(i) + W * Lt::cy(i);
+      const S(*pp)[RN] = Lt::cz(i) > 0 ? zp : (Lt::cz(i) < 0 ? zm : m);
+      const S(*pm)[RN] = Lt::cz(i) > 0 ? zm : (Lt::cz(i) < 0 ? zp : m);
+      const S vp = pp[q][k + o], vm = pm[q][k - o];
+      const S wg = S((HALF ? 3.0 : 6.0) * Lt::w(i)), wl = S(6.0 * Lt::w(i));
+      const S df = wg * (vp - vm);
+      if (Lt::cx(i) != 0) gx += Lt::cx(i) > 0 ? df : -df;
+      if (Lt::cy(i) != 0) gy += Lt::cy(i) > 0 ? df : -df;
+      if (Lt::cz(i) != 0) gz += Lt::cz(i) > 0 ? df : -df;
+      l += wl * ((vp - cc) + (vm - cc));
+    }
+    v[q] = cc;
+    g[0][q] = gx;
+    g[1][q] = gy;
+    g[2][q] = gz;
+    lap[q] = l;
+  }
+  c = Sym<S>{v[0], v[1], v[2], v[3], v[4]};
+#pragma unroll
+  for (int a = 0; a < 3; a++) d[a] = Sym<S>{g[a][0], g[a][1], g[a][2], g[a][3], g[a][4]};
   L = Sym<S>{lap[0], lap[1], lap[2], lap[3], lap[4]};
 }
 
@@ -269,17 +307,17 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
   // tau_{a x} is needed at x +- 1 (rows 1..TY of the R1 region, all
   // columns) and tau_{a y} at y +- 1 (columns 1..TX, all rows)
   constexpr int NXA = T::W1 * TY, NYA = TX * T::H1;
-  // isotropic stencils (2D): the body force needs tau_{a x} and tau_{a y}
-  // at the eight neighbours, so the whole stress of the tile, its ring and
-  // the ring's corners goes to LDS (sTi[a][b][R1 index])
+  // isotropic stencils: the body force needs the stress at every lattice
+  // neighbour, so the whole stress of the tile, its ring and the ring's
+  // corners goes to LDS (sTi[plane slot][a][b][R1 index]; in 3D a ring of
+  // the three planes p-1, p, p+1)
   constexpr bool ISO = ST == STENCIL_ISO;
-  static_assert(!ISO || DIM == 2, "the sweeps take the isotropic stencils on two-dimensional lattices only");
   static_assert(!ISO || T::RING + 4 <= T::NT, "tile too thin for its ring and corners");
-  constexpr int NI = ISO ? 2 : 1, RI = ISO ? T::R1 : 1;
+  constexpr int NI = ISO ? DIM : 1, RI = ISO ? T::R1 : 1, NPI = (ISO && DIM == 3) ? 3 : 1;
   __shared__ QT sQ[NQP][5][T::R2];
   __shared__ QT sTx[NTP][DIM][ISO ? 1 : NXA];
   __shared__ QT sTy[NTP][DIM][ISO ? 1 : NYA];
-  __shared__ QT sTi[NI][NI][RI];
+  __shared__ QT sTi[NPI][NI][NI][RI];
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
   const int x0 = bx * TX, y0 = by * TY;
@@ -291,8 +329,10 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
   // stress at the R1 point (i, j) of plane slot m with z neighbours zp/zm
   auto tau_point = [&](int m, int zp, int zm, int i, int j, QT (&t)[3][3]) {
     Sym<QT> q, Lq, d[3];
-    if constexpr (ISO)
+    if constexpr (ISO && DIM == 2)
       stencil_lds_iso2<QT, T::W2, T::R2>(sQ[m], T::r2(i, j), q, d, Lq);
+    else if constexpr (ISO)
+      stencil_lds_iso3<QT, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
     else
       stencil_lds<QT, DIM, T::W2, T::R2>(sQ[m], sQ[zp], sQ[zm], T::r2(i, j), q, d, Lq);
     const Sym<QT> H = molecular_field(q, Lq, cq);
@@ -314,15 +354,15 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
   // stress of the whole region of plane slot m into sT[ts]; returns the
   // owner's tau_{a z}
   auto tau_plane = [&](int m, int zp, int zm, int ts, QT (&tz)[3]) {
-    if constexpr (ISO) {  // every site of the R1 region, corners included
+    if constexpr (ISO) {  // every site of the R1 region, corners included, into plane slot m
       auto put = [&](int i, int j) {
         QT t[3][3];
         tau_point(m, zp, zm, i, j, t);
         const int k = i + T::W1 * j;
 #pragma unroll
-        for (int a = 0; a < 2; a++)
+        for (int a = 0; a < DIM; a++)
 #pragma unroll
-          for (int b = 0; b < 2; b++) sTi[a][b][k] = t[a][b];
+          for (int b = 0; b < DIM; b++) sTi[NPI == 3 ? m : 0][a][b][k] = t[a][b];
       };
       put(tx + 1, ty + 1);
       if (tid < T::RING + 4) {
@@ -423,23 +463,26 @@ __device__ __forceinline__ void split_lb_body(const QT* __restrict__ Qin, const 
     const int kx = (tx + 1) + T::W1 * ty, ky = tx + TX * (ty + 1);
     S F[3] = {S(0), S(0), S(0)};
     if constexpr (ISO) {  // F_a = 3 sum_i w_i sum_b c_ib tau_ab(x + c_i), over pairs
-      using Lt = Lattice<0>;
+      using Lt = Lattice<LAT>;
       const int k1 = (tx + 1) + T::W1 * (ty + 1);
+      // plane slots of z, z+1 and z-1 (3D): the stress of planes z-1..z+1
+      const int sc = NPI == 3 ? (z + 3) % 3 : 0, sp = NPI == 3 ? (z + 4) % 3 : 0, sm = NPI == 3 ? (z + 2) % 3 : 0;
 #pragma unroll
-      for (int a = 0; a < 2; a++) {
+      for (int a = 0; a < DIM; a++) {
         QT acc = QT(0);
 #pragma unroll
         for (int i = 1; i < Lt::q; i++) {
           if (Lt::opp(i) < i) continue;
           const int o = Lt::cx(i) + T::W1 * Lt::cy(i);
+          const int pp = Lt::cz(i) > 0 ? sp : (Lt::cz(i) < 0 ? sm : sc);
+          const int pm = Lt::cz(i) > 0 ? sm : (Lt::cz(i) < 0 ? sp : sc);
           QT dsum = QT(0);
-          if (Lt::cx(i) != 0) {
-            const QT dt = sTi[a][0][k1 + o] - sTi[a][0][k1 - o];
-            dsum += Lt::cx(i) > 0 ? dt : -dt;
-          }
-          if (Lt::cy(i) != 0) {
-            const QT dt = sTi[a][1][k1 + o] - sTi[a][1][k1 - o];
-            dsum += Lt::cy(i) > 0 ? dt : -dt;
+#pragma unroll
+          for (int b = 0; b < DIM; b++) {
+            const int cb = b == 0 ? Lt::cx(i) : (b == 1 ? Lt::cy(i) : Lt::cz(i));
+            if (cb == 0) continue;
+            const QT dt = sTi[pp][a][b][k1 + o] - sTi[pm][a][b][k1 - o];
+            dsum += cb > 0 ? dt : -dt;
           }
           acc += QT(3.0 * Lt::w(i)) * dsum;
         }
@@ -539,13 +582,14 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   // owner's own predictor values kept in registers; in double precision
   // (one wave per SIMD, where registers are the scarcer resource) three LDS
   // planes, z-1, z and z+1 of the corrector.
-  constexpr bool ZREG = DIM == 3 && sizeof(S) == 4;
+  // isotropic stencils: the predictor also runs at the ring's corners, and
+  // in 3D the corrector reads the predictor's diagonal neighbours in the
+  // planes above and below, so three LDS planes of it are kept
+  constexpr bool ISO = ST == STENCIL_ISO;
+  constexpr bool ZREG = DIM == 3 && sizeof(S) == 4 && !ISO;
   constexpr int NP = DIM == 3 ? 3 : 1;
   constexpr int NPS = (DIM == 3 && !ZREG) ? 3 : 1;
   constexpr int NC = 5 + DIM;  // Q components then u components
-  // isotropic stencils (2D): the predictor also runs at the ring's corners
-  constexpr bool ISO = ST == STENCIL_ISO;
-  static_assert(!ISO || DIM == 2, "the sweeps take the isotropic stencils on two-dimensional lattices only");
   constexpr int NRING = ISO ? T::RING + 4 : T::RING;
   static_assert(NRING <= T::NT, "tile too thin for its ring");
   __shared__ S sQ[NP][NC][T::R2];
@@ -579,8 +623,10 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   auto pred_point = [&](int m, int zp, int zm, int i, int j, Stash& st) {
     const int k = T::r2(i, j);
     Sym<S> q, Lq, d[3];
-    if constexpr (ISO)
+    if constexpr (ISO && DIM == 2)
       stencil_lds_iso2<S, T::W2, T::R2, false>(sQ[m], k, q, d, Lq);
+    else if constexpr (ISO)
+      stencil_lds_iso3<S, T::W2, T::R2, false>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
     else
       stencil_lds<S, DIM, T::W2, T::R2, false>(sQ[m], sQ[zp], sQ[zm], k, q, d, Lq);
     const Sym<S> H = SR ? molecular_field_exact(q, Lq, c) : molecular_field(q, Lq, c);
@@ -589,21 +635,24 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
     for (int a = 0; a < 3; a++) {
       u[a] = a < DIM ? sQ[m][5 + a][k] * S(0.5) : S(0);
       if constexpr (ISO) {  // undivided: 6 sum_i w_i c_ib u_a(x + c_i), over pairs
-        using Lt = Lattice<0>;
-        S g0 = S(0), g1 = S(0);
+        using Lt = Lattice<LAT>;
+        S g0 = S(0), g1 = S(0), g2 = S(0);
         if (a < DIM) {
 #pragma unroll
           for (int n = 1; n < Lt::q; n++) {
             if (Lt::opp(n) < n) continue;
             const int o = Lt::cx(n) + T::W2 * Lt::cy(n);
-            const S du = S(6.0 * Lt::w(n)) * (sQ[m][5 + a][k + o] - sQ[m][5 + a][k - o]);
+            const int pp = Lt::cz(n) > 0 ? zp : (Lt::cz(n) < 0 ? zm : m);
+            const int pm = Lt::cz(n) > 0 ? zm : (Lt::cz(n) < 0 ? zp : m);
+            const S du = S(6.0 * Lt::w(n)) * (sQ[pp][5 + a][k + o] - sQ[pm][5 + a][k - o]);
             if (Lt::cx(n) != 0) g0 += Lt::cx(n) > 0 ? du : -du;
             if (Lt::cy(n) != 0) g1 += Lt::cy(n) > 0 ? du : -du;
+            if (Lt::cz(n) != 0) g2 += Lt::cz(n) > 0 ? du : -du;
           }
         }
         G[a][0] = g0;
         G[a][1] = g1;
-        G[a][2] = S(0);
+        G[a][2] = g2;
         continue;
       }
       G[a][0] = a < DIM ? sQ[m][5 + a][k + 1] - sQ[m][5 + a][k - 1] : S(0);
@@ -630,11 +679,17 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
   auto pred_at = [&](int b) { return Sym<S>{sP[b][0][k1], sP[b][1][k1], sP[b][2][k1], sP[b][3][k1], sP[b][4][k1]}; };
   // corrector at the owner's site of plane z: in-plane neighbours of Q^P
   // from sP[b], the centre pc and the z neighbours pzp / pzm (3D)
-  auto corr_site = [&](int z, int b, const Stash& st, const Sym<S>& pc, const Sym<S>& pzp, const Sym<S>& pzm) {
+  // (bzp, bzm: the predictor planes above and below, read by the isotropic
+  // stencil in 3D)
+  auto corr_site = [&](int z, int b, const Stash& st, const Sym<S>& pc, const Sym<S>& pzp, const Sym<S>& pzm,
+                       int bzp = 0, int bzm = 0) {
     if (!own) return;
     if constexpr (ISO) {
       Sym<S> pcc, Lp, d[3];
-      stencil_lds_iso2<S, T::W1, T::R1, false>(sP[b], k1, pcc, d, Lp);
+      if constexpr (DIM == 2)
+        stencil_lds_iso2<S, T::W1, T::R1, false>(sP[b], k1, pcc, d, Lp);
+      else
+        stencil_lds_iso3<S, T::W1, T::R1, false>(sP[b], sP[bzp], sP[bzm], k1, pcc, d, Lp);
       const Sym<S> H = SR ? molecular_field_exact(pcc, Lp, c) : molecular_field(pcc, Lp, c);
       const Sym<S> Rp = be_rate_flow<S, true>(pcc, H, d, st.fl, c);
       const int64_t s = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
@@ -711,11 +766,11 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
       // iteration p-1, and the predictor values go there at once
       const Sym<S> own_p = pred_point(slot(p), slot(p + 1), slot(p - 1), tx + 1, ty + 1, cur);
       if constexpr (!ZREG) store_pred(pslot(p), tx + 1, ty + 1, own_p);
-      const bool ring = tid < T::RING;
+      const bool ring = tid < NRING;
       int ri = 0, rj = 0;
       Sym<S> ring_p = sym_zero<S>();
       if (ring) {
-        T::ring(tid, ri, rj);
+        ring_point<TX, TY>(tid, ri, rj);
         Stash tmp;
         ring_p = pred_point(slot(p), slot(p + 1), slot(p - 1), ri, rj, tmp);
         if constexpr (!ZREG) store_pred(pslot(p), ri, rj, ring_p);
@@ -734,7 +789,8 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
         // and u, which may be overwritten
         __syncthreads();
         if (p - 1 >= zb)
-          corr_site(p - 1, pslot(p - 1), prev, pred_at(pslot(p - 1)), pred_at(pslot(p)), pred_at(pslot(p - 2)));
+          corr_site(p - 1, pslot(p - 1), prev, pred_at(pslot(p - 1)), pred_at(pslot(p)), pred_at(pslot(p - 2)),
+                    pslot(p), pslot(p - 2));
       }
     };
     // two planes per trip, so the two stashes swap roles without copies

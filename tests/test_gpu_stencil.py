@@ -1,9 +1,9 @@
 """GPU parity of the isotropic difference stencils (lc_set_stencil) against
 the oracle's isotropic option (oracle.run(..., stencil="isotropic")).
 
-The library's staged kernels, and on D2Q9 its two-sweep kernels, take every
-derivative of the step (grad Q, lap Q, the divergence of the stress, grad u)
-from the lattice's velocities and weights when LC_STENCIL_ISOTROPIC is set.  Double precision must agree
+The library's two-sweep and staged kernels take every derivative of the
+step (grad Q, lap Q, the divergence of the stress, grad u) from the
+lattice's velocities and weights when LC_STENCIL_ISOTROPIC is set.  Double precision must agree
 with the oracle to 1e-12 in the normwise metric of gpu_util.rel_err, for the
 state, the derived fields and the observables, with BGK and MRT collisions;
 the FP32 deviation form must keep S within 1e-5.  The calls the stencils do
@@ -45,11 +45,11 @@ def _state(lc, lat, shape, seed):
     return q5, rel, w.reshape((q, 1, 1, 1)) * (1.0 + rel)
 
 
-# variant 0 (AUTO): the two-sweep kernels on D2Q9, the staged ones on D3Q19;
-# variant 1: the staged kernels
+# variant 0 (AUTO): the two-sweep kernels; variant 1: the staged kernels
 @pytest.mark.parametrize("coll", ["bgk", "mrt"])
-@pytest.mark.parametrize("lat,shape,variant", [(0, (1, 23, 37), 0), (0, (1, 70, 130), 0), (0, (1, 23, 37), 1),
-                                               (0, (1, 70, 130), 1), (1, (9, 11, 13), 0), (1, (17, 6, 67), 0)])
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("lat,shape", [(0, (1, 23, 37)), (0, (1, 70, 130)), (1, (9, 11, 13)), (1, (17, 6, 67)),
+                                       (1, (40, 9, 35))])
 def test_isotropic_parity_random_state_ragged(lat, shape, variant, coll):
     """Random Q and perturbed populations on ragged grids spanning several
     site tiles, 12 steps: state, rho, u and the body force, and the
@@ -121,12 +121,15 @@ def test_isotropic_flat_interface_1000_steps_fp64_and_fp32(variant):
             assert err < 1e-5
 
 
-def test_isotropic_slab_32cubed_d3q19_500_steps():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_isotropic_slab_32cubed_d3q19_500_steps(variant):
     """The slab recipe on a 32^3 D3Q19 grid with isotropic stencils, 500
-    steps, against the oracle to 1e-12; lattice momentum conserved."""
+    steps, two-sweep (0) and staged (1) kernels, against the oracle to
+    1e-12; lattice momentum conserved."""
     lc = _lc()
     w = inputs.config2(32)
     s = lc.Solver("D3Q19", "fp64", w.shape, w.params)
+    s.set_variant(variant)
     s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
     s.load(w.q5)
     j0 = s.observe()["mom"]
@@ -142,9 +145,9 @@ def test_isotropic_slab_32cubed_d3q19_500_steps():
 
 @pytest.mark.parametrize("lat", [0, 1])
 def test_isotropic_stencil_unsupported_combinations(lat):
-    """The fused variant with the isotropic stencils, and on D3Q19 the
-    explicit two-sweep variant, fail with LC_EUNSUPPORTED; compact again
-    runs the split sweeps bit for bit as a fresh context does."""
+    """The fused variant with the isotropic stencils fails with
+    LC_EUNSUPPORTED; compact again runs the default variant bit for bit as
+    a fresh context does."""
     lc = _lc()
     shape = (1, 16, 24) if lat == 0 else (6, 8, 10)
     q5, rel, f_gpu = _state(lc, lat, shape, 7)
@@ -153,11 +156,10 @@ def test_isotropic_stencil_unsupported_combinations(lat):
     s = lc.Solver(name, "fp64", shape, p)
     s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
     s.load(q5, f_gpu)
-    for v in ((lc.LC_VARIANT_FUSED,) if lat == 0 else (lc.LC_VARIANT_SPLIT, lc.LC_VARIANT_FUSED)):
-        s.set_variant(v)
-        with pytest.raises(lc.LCError) as e:
-            s.step(1)
-        assert e.value.code == lc.LC_EUNSUPPORTED
+    s.set_variant(lc.LC_VARIANT_FUSED)
+    with pytest.raises(lc.LCError) as e:
+        s.step(1)
+    assert e.value.code == lc.LC_EUNSUPPORTED
     s.set_variant(lc.LC_VARIANT_AUTO)
     s.set_stencil(lc.LC_STENCIL_COMPACT)
     s.step(3)
@@ -168,16 +170,18 @@ def test_isotropic_stencil_unsupported_combinations(lat):
     assert np.array_equal(s.export(lc.LC_FIELD_Q), ref.export(lc.LC_FIELD_Q))
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("lat,shape", [(0, (1, 1, 5)), (0, (1, 2, 3)), (0, (1, 3, 1)), (1, (1, 2, 3)),
-                                       (1, (2, 1, 3)), (1, (3, 2, 1)), (1, (1, 1, 1))])
-def test_isotropic_parity_degenerate_grids(lat, shape):
+                                       (1, (2, 1, 3)), (1, (3, 2, 1)), (1, (1, 1, 1)), (1, (4, 1, 2))])
+def test_isotropic_parity_degenerate_grids(lat, shape, variant):
     """Axes of length one and two, where several lattice neighbours of a site
     are the same site (the periodic wrap), against the oracle to 1e-12."""
     lc = _lc()
-    _say("isotropic degenerate lat %d shape %s" % (lat, shape))
+    _say("isotropic degenerate lat %d shape %s variant %d" % (lat, shape, variant))
     q5, rel, f_gpu = _state(lc, lat, shape, 600 + sum(shape))
     p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
     s = lc.Solver(lattice_name(lat), "fp64", shape, p)
+    s.set_variant(variant)
     s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
     s.load(q5, f_gpu)
     s.step(6)
@@ -224,3 +228,27 @@ def test_isotropic_two_sweep_and_staged_agree_on_d2q9():
         d = float(np.abs(S[0] - S[1]).max())
         _say("isotropic %s, two-sweep vs staged after 3000 steps: max|dS| %.2e" % (prec, d))
         assert d < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32dev", 1e-5)])
+def test_isotropic_two_sweep_and_staged_agree_on_d3q19_slab(prec, tol):
+    """The slab recipe on 48 x 40 x 36 sites (several tiles and z-chunks,
+    ragged), 300 steps: the two-sweep and staged kernels with the isotropic
+    stencils agree in S to rounding."""
+    lc = _lc()
+    w = inputs.config2(48)
+    q5 = w.q5[:, :36, :40, :].copy()
+    S = {}
+    for v, chunk in ((0, 0), (0, 7), (1, 0)):
+        s = lc.Solver("D3Q19", prec, q5.shape[1:], w.params)
+        s.set_variant(v)
+        s.set_chunk(chunk)
+        s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+        s.load(q5)
+        s.step(300)
+        S[(v, chunk)] = s.export(lc.LC_FIELD_S)
+    d = float(np.abs(S[(0, 0)] - S[(1, 0)]).max())
+    _say("isotropic D3Q19 %s, two-sweep vs staged after 300 steps: max|dS| %.2e" % (prec, d))
+    assert d < tol
+    # z-chunks that cut the march change nothing in the two sweeps
+    assert np.array_equal(S[(0, 0)], S[(0, 7)])
