@@ -321,7 +321,10 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
                            q0, f0, f1, u, gd, k, kq, zc1, rec_lb);
       ctx_end(c, st, e, 0);
       e = mark ? ctx_begin(c, st) : nullptr;
-      hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, C::Q_WPE, false, STENCIL_ISO>), g2,
+      // the 3D float Q sweep with these stencils is held to two waves per
+      // SIMD (some registers spill; measured 12% faster than one wave)
+      constexpr int IQW = (C::d3 && sizeof(QT) == 4) ? 2 : C::Q_WPE;
+      hipLaunchKernelGGL((split_q<LAT, QT, C::Q_TX, C::Q_TY, IQW, false, STENCIL_ISO>), g2,
                          dim3(C::Q_TX, C::Q_TY), 0, st, q0, u, q1, gd, kq, zc2, rec_q, 0u);
       ctx_end(c, st, e, 1);
       return;
