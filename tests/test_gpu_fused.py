@@ -100,3 +100,28 @@ def test_fused_full_size_slab_equals_split():
         del s
         torch.cuda.empty_cache()
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32dev", "fp32sr", "mixed"])
+@pytest.mark.parametrize("n", [64, 256, 257])
+def test_auto_variant_on_small_2d_grids(prec, n):
+    """AUTO runs the single pass on D2Q9 grids of at most 65536 sites and
+    the two sweeps above: either way its state equals the explicit two-sweep
+    variant bit for bit (256^2 = 65536 sites, 257^2 just above)."""
+    require_gpu()
+    from paper_1907_13415_amd import lc
+    rng = np.random.default_rng(900 + n)
+    shape = (1, n, n)
+    q5 = inputs.random_q5(shape, rng, amp=0.12)
+    rel = inputs.random_rel(9, shape, rng, amp=2e-3)
+    _, w = lc.lc_lattice_info(0)
+    f = w.reshape((9, 1, 1, 1)) * (1.0 + rel)
+    runs = []
+    for variant in (lc.LC_VARIANT_AUTO, lc.LC_VARIANT_SPLIT):
+        s = lc.Solver("D2Q9", prec, shape, PARAMS)
+        s.set_variant(variant)
+        s.load(q5, f)
+        s.step(9)
+        runs.append(s)
+    _say("auto vs split, D2Q9 %s %dx%d" % (prec, n, n))
+    assert _same(lc, runs[0], runs[1], 9)

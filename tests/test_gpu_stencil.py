@@ -252,3 +252,22 @@ def test_isotropic_two_sweep_and_staged_agree_on_d3q19_slab(prec, tol):
     assert d < tol
     # z-chunks that cut the march change nothing in the two sweeps
     assert np.array_equal(S[(0, 0)], S[(0, 7)])
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_isotropic_fp32dev_slab_32cubed_within_tolerance_on_S(variant):
+    """The FP32 deviation form with the isotropic stencils on the 32^3 slab
+    recipe, 500 steps: S within 1e-5 of the double-precision oracle."""
+    lc = _lc()
+    w = inputs.config2(32)
+    s = lc.Solver("D3Q19", "fp32dev", w.shape, w.params)
+    s.set_variant(variant)
+    s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+    s.load(w.q5)
+    s.step(500)
+    _, q_ref = oracle.run(1, oracle.rest_populations(1, w.shape), w.q5, w.params, 500, stencil=ISO)
+    S_ref = np.sqrt(1.5 * (q_ref[0] ** 2 + q_ref[3] ** 2 + (q_ref[0] + q_ref[3]) ** 2
+                           + 2 * (q_ref[1] ** 2 + q_ref[2] ** 2 + q_ref[4] ** 2)))
+    err = float(np.abs(s.export(lc.LC_FIELD_S)[0] - S_ref).max())
+    _say("isotropic fp32dev slab 32^3 variant %d, 500 steps: max|dS| %.2e" % (variant, err))
+    assert err < 1e-5
