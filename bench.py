@@ -27,6 +27,7 @@ import math
 import os
 import re
 import statistics
+import subprocess
 import sys
 import time
 
@@ -104,6 +105,11 @@ def cpu_baseline(n=128, min_s=10.0, max_steps=200):
         rate1, steps1, dt1 = _oracle_rate(oracle, inputs, 64, min_s / 3, max_steps)
     finally:
         oracle.set_threads(threads)
+    # the oracle's own operation count of one D3Q19 step (oracle/opcount.cpp)
+    try:
+        flops = oracle.opcount(oracle.D3Q19, 4)["flops_per_site"]
+    except (OSError, subprocess.CalledProcessError, ValueError):
+        flops = None
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -114,6 +120,8 @@ def cpu_baseline(n=128, min_s=10.0, max_steps=200):
                 sample="oracle FP64 on the D3Q19 slab recipe at %d^3, %d steps in %.1f s" % (n, steps, dt),
                 single_thread=dict(value=round(rate1, 4), unit="MLUPS", cores=1,
                                    sample="the same at 64^3, %d steps in %.1f s" % (steps1, dt1)),
+                oracle_flops_per_site=flops,
+                gflops=None if flops is None else round(rate * flops / 1e3, 2),
                 cpu_model=model, nproc=os.cpu_count())
 
 
@@ -422,7 +430,7 @@ def main():
     ap.add_argument("--batch-tiles", help="LB,Q tile shapes of the batched leg instead of tuning (0..6)")
     ap.add_argument("--no-physics", action="store_true",
                     help="with --only batch: skip the 5000-step front-speed window (for counter runs)")
-    ap.add_argument("--only", choices=["batch", "adjoint", "mrt", "fused", "stencil"],
+    ap.add_argument("--only", choices=["batch", "adjoint", "mrt", "fused", "stencil", "droplets"],
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -451,6 +459,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps({"adjoint": run_adjoint(torch)}), flush=True)
+        return
+    if args.only == "droplets":
+        print(json.dumps({"droplets": run_droplets(torch, lc, dev, stream)}), flush=True)
         return
 
     w = inputs.config2(args.n)

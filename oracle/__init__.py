@@ -28,6 +28,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lc_oracle.c")
 _LIB = os.path.join(_HERE, "liblc_oracle.so")
+_OPC_SRC = os.path.join(_HERE, "opcount.cpp")
+_OPC_BIN = os.path.join(_HERE, "opcount")
 
 D2Q9 = 0
 D3Q19 = 1
@@ -50,10 +52,39 @@ def compile_source(src: str, out: str) -> str:
 
 def build(force: bool = False) -> str:
     """Compile the oracle (see compile_source) if its library is missing or
-    older than the source."""
+    older than the source; with force, also the operation counter."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         compile_source(_SRC, _LIB)
+    if force:
+        build_opcount(force=True)
     return _LIB
+
+
+def build_opcount(force: bool = False) -> str:
+    """Compile opcount.cpp (the oracle's source counted operation by
+    operation, see that file) with g++ if the program is missing or older
+    than either source."""
+    stale = not os.path.exists(_OPC_BIN) or any(
+        os.path.getmtime(_OPC_BIN) < os.path.getmtime(s) for s in (_SRC, _OPC_SRC))
+    if force or stale:
+        tmp = _OPC_BIN + ".tmp%d" % os.getpid()
+        subprocess.run(["g++", "-O1", "-fpermissive", "-fopenmp", "-w", "-o", tmp, _OPC_SRC, "-lm"], check=True)
+        os.replace(tmp, _OPC_BIN)
+    return _OPC_BIN
+
+
+def opcount(lat: int, n: int, mrt: bool = False, stencil: str = "compact") -> dict:
+    """Floating-point operations of one oracle step on an n x n (D2Q9) or
+    n^3 (D3Q19) grid: counts of additions (and subtractions),
+    multiplications, divisions, square roots and comparisons, and the
+    operations per site."""
+    import json
+    if stencil not in STENCILS:
+        raise ValueError("stencil must be one of %s" % sorted(STENCILS))
+    exe = build_opcount()
+    r = subprocess.run([exe, str(int(lat)), str(int(n)), str(int(bool(mrt))), str(STENCILS[stencil])],
+                       check=True, stdout=subprocess.PIPE, text=True)
+    return json.loads(r.stdout)
 
 
 def _load():
