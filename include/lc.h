@@ -204,7 +204,8 @@ lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
  * same arithmetic in each; SPLIT and FUSED agree bit for bit).  AUTO (the
  * default) picks the fastest the build provides for the context's stencil
  * and grid: the two-sweep variant, except FUSED for compact stencils on
- * D2Q9 grids of at most 65536 sites, where launches are latency bound.  FUSED runs every
+ * D2Q9 grids of at most 147456 (384^2) sites, where launches are latency
+ * bound and the single pass measured faster in every precision.  FUSED runs every
  * stage of a step in one pass over the grid: a block recomputes the
  * stress, moments and predictor on shrinking rings around its tile instead
  * of reading them back from HBM.  LC_EUNSUPPORTED for the staged variant in

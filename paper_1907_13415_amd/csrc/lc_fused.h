@@ -72,6 +72,8 @@ __device__ __forceinline__ void tile_first(int k, int& i, int& j) {
 // Tile shapes of the single pass (LDS per block: FP32 D3Q19 about 132 KB,
 // FP64 D3Q19 about 152 KB, so one block per CU in 3D) and threads per block
 // (more threads than tile sites share the ring work and hide latency).
+// On two-dimensional grids the runtime picks one of the FUSED2D_* shapes
+// from the number of tiles.
 template <int LAT, typename QT>
 struct FusedCfg {
   static constexpr bool d3 = Lattice<LAT>::dim == 3;
@@ -80,6 +82,23 @@ struct FusedCfg {
   static constexpr int NTHR = d3 ? (f64 ? 256 : 512) : TX * TY;
   static constexpr int ZC = 64;  // planes per block along z
 };
+
+// Two-dimensional shapes (TX, TY, threads).  A grid of at most one tile per
+// CU is latency bound (one wave per SIMD with one thread per site): there a
+// block of 1024 threads shares each stage's ring points among four threads
+// per tile site, which shortens every wave's instruction stream and puts
+// four waves on each SIMD; 16x8 tiles where the grid has few enough of
+// them, else 32x8.  Up to four tiles per CU, two threads per site; larger
+// grids keep one thread per site.  Measured on 65536 sites (256^2): 8.3 ->
+// 6.1 us per step in FP32, 9.2 -> 7.3 us in FP64; on 16384 sites (128^2)
+// 16x8 tiles 5.3 us (FP32) against 5.7 for 32x8 at 1024 threads; on 384^2
+// two threads per site 9.5 against 10.8 us (FP32), 14.6 against 18.2 us
+// (FP64).
+constexpr int FUSED2D_SMALL_TX = 16, FUSED2D_SMALL_TY = 8, FUSED2D_SMALL_NTHR = 1024;
+constexpr int FUSED2D_MID_TX = 32, FUSED2D_MID_TY = 8, FUSED2D_MID_NTHR = 1024;
+constexpr int FUSED2D_HALF_TX = 32, FUSED2D_HALF_TY = 8, FUSED2D_HALF_NTHR = 512;
+constexpr int FUSED2D_WIDE_TX = 32, FUSED2D_WIDE_TY = 8, FUSED2D_WIDE_NTHR = 256;
+constexpr int FUSED2D_CUS = 256;  // compute units of the chip
 
 template <int LAT, typename S, bool DEV, int TX, int TY, int NTHR, bool MRT, typename QT, bool SR>
 __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* __restrict__ fin,

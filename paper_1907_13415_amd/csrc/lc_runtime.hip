@@ -347,33 +347,53 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   ctx_end(c, st, e, 1);
 }
 
-// One step of the single pass between explicit buffers on stream st.
-template <int LAT, typename S, bool DEV, typename QT = S>
-static void step_fused_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const QT* q0, S* f1, QT* q1) {
-  using C = FusedCfg<LAT, QT>;
+// One launch of the single pass with tile TX x TY and NTHR threads.
+template <int LAT, typename S, bool DEV, typename QT, int TX, int TY, int NTHR>
+static void launch_fused(lc_ctx* c, hipStream_t st, int zc, const S* f0, const QT* q0, S* f1, QT* q1) {
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = ctx_coef<S>(c);
   const Coef<QT> kq = ctx_coef<QT>(c);
-  const int zc = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC) : 1;
-  const dim3 grid((c->g.nx + C::TX - 1) / C::TX, (c->g.ny + C::TY - 1) / C::TY, unsigned((c->g.nz + zc - 1) / zc));
+  const dim3 grid((c->g.nx + TX - 1) / TX, (c->g.ny + TY - 1) / TY, unsigned((c->g.nz + zc - 1) / zc));
   constexpr bool F32 = std::is_same<QT, float>::value;
   const bool sr = F32 && c->g.precision == LC_FP32_SR;
   const uint32_t key = step_key(c->step);
-  hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
   if (c->coll == LC_COLL_MRT) {
     if (sr)
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, true, QT, F32>), grid, dim3(C::NTHR), 0, st,
-                         q0, f0, f1, q1, gd, k, kq, zc, key);
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, TX, TY, NTHR, true, QT, F32>), grid, dim3(NTHR), 0, st, q0, f0, f1,
+                         q1, gd, k, kq, zc, key);
     else
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, true, QT, false>), grid, dim3(C::NTHR), 0, st,
-                         q0, f0, f1, q1, gd, k, kq, zc, key);
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, TX, TY, NTHR, true, QT, false>), grid, dim3(NTHR), 0, st, q0, f0,
+                         f1, q1, gd, k, kq, zc, key);
   } else {
     if (sr)
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, false, QT, F32>), grid, dim3(C::NTHR), 0, st,
-                         q0, f0, f1, q1, gd, k, kq, zc, key);
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, TX, TY, NTHR, false, QT, F32>), grid, dim3(NTHR), 0, st, q0, f0,
+                         f1, q1, gd, k, kq, zc, key);
     else
-      hipLaunchKernelGGL((fused_step<LAT, S, DEV, C::TX, C::TY, C::NTHR, false, QT, false>), grid, dim3(C::NTHR), 0,
-                         st, q0, f0, f1, q1, gd, k, kq, zc, key);
+      hipLaunchKernelGGL((fused_step<LAT, S, DEV, TX, TY, NTHR, false, QT, false>), grid, dim3(NTHR), 0, st, q0, f0,
+                         f1, q1, gd, k, kq, zc, key);
+  }
+}
+
+// One step of the single pass between explicit buffers on stream st.  On a
+// two-dimensional grid the tile shape and threads per tile follow from the
+// number of tiles (FUSED2D_* in lc_fused.h).
+template <int LAT, typename S, bool DEV, typename QT = S>
+static void step_fused_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, const QT* q0, S* f1, QT* q1) {
+  using C = FusedCfg<LAT, QT>;
+  hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
+  if constexpr (C::d3) {
+    const int zc = c->zchunk > 0 ? c->zchunk : C::ZC;
+    launch_fused<LAT, S, DEV, QT, C::TX, C::TY, C::NTHR>(c, st, zc, f0, q0, f1, q1);
+  } else {
+    auto tiles = [&](int tx, int ty) { return int64_t((c->g.nx + tx - 1) / tx) * ((c->g.ny + ty - 1) / ty); };
+    if (tiles(FUSED2D_SMALL_TX, FUSED2D_SMALL_TY) <= FUSED2D_CUS)
+      launch_fused<LAT, S, DEV, QT, FUSED2D_SMALL_TX, FUSED2D_SMALL_TY, FUSED2D_SMALL_NTHR>(c, st, 1, f0, q0, f1, q1);
+    else if (tiles(FUSED2D_MID_TX, FUSED2D_MID_TY) <= FUSED2D_CUS)
+      launch_fused<LAT, S, DEV, QT, FUSED2D_MID_TX, FUSED2D_MID_TY, FUSED2D_MID_NTHR>(c, st, 1, f0, q0, f1, q1);
+    else if (tiles(FUSED2D_HALF_TX, FUSED2D_HALF_TY) <= 4 * FUSED2D_CUS)
+      launch_fused<LAT, S, DEV, QT, FUSED2D_HALF_TX, FUSED2D_HALF_TY, FUSED2D_HALF_NTHR>(c, st, 1, f0, q0, f1, q1);
+    else
+      launch_fused<LAT, S, DEV, QT, FUSED2D_WIDE_TX, FUSED2D_WIDE_TY, FUSED2D_WIDE_NTHR>(c, st, 1, f0, q0, f1, q1);
   }
   ctx_end(c, st, e, 0);
 }
@@ -406,10 +426,13 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
 
 // The variant a step runs.  AUTO is the two-sweep variant, except the
 // single pass (with the compact stencils) on two-dimensional grids of at
-// most 65536 sites, whose launches are latency bound (one wave per SIMD)
-// and where one launch per step instead of two measured 4-6% faster at
-// 128^2 and 256^2 (bit-identical results).
-constexpr int64_t AUTO_FUSED_MAX_SITES = 65536;
+// most 384^2 sites, whose launches are latency bound and where one launch
+// per step with several threads per tile site measured faster than the two
+// sweeps in every precision (bit-identical results; 256^2: 6.1 against 8.8
+// us in FP32, 7.3 against 9.5 us in FP64; 384^2: 9.3 against 11.1 and 14.5
+// against 14.7 us; from 448^2 the mixed form, from 512^2 FP64 and FP32 with
+// stochastic rounding are faster in two sweeps).
+constexpr int64_t AUTO_FUSED_MAX_SITES = 384 * 384;
 static int resolved_variant(const lc_ctx* c) {
   if (c->variant != LC_VARIANT_AUTO) return c->variant;
   if (c->stencil == LC_STENCIL_ISOTROPIC) return LC_VARIANT_SPLIT;

@@ -52,7 +52,12 @@ def _same(lc, a, b, n):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32dev", "mixed", "fp32sr"])
-@pytest.mark.parametrize("lat,shape,chunk", [(0, (1, 23, 37), 0), (0, (1, 70, 130), 0), (1, (9, 11, 13), 0),
+# two-dimensional shapes: the library's single pass takes 16x8 tiles with
+# 1024 threads on grids of at most 256 such tiles (23x37, 70x130), 32x8
+# tiles with 1024 threads on at most 256 of those (130x250), with 512
+# threads on at most 1024 (300x301), else with 256 threads (270x1030)
+@pytest.mark.parametrize("lat,shape,chunk", [(0, (1, 23, 37), 0), (0, (1, 70, 130), 0), (0, (1, 130, 250), 0),
+                                             (0, (1, 300, 301), 0), (0, (1, 270, 1030), 0), (1, (9, 11, 13), 0),
                                              (1, (17, 6, 67), 5), (1, (40, 20, 36), 0), (1, (13, 18, 35), 3),
                                              (1, (7, 9, 40), 1)])
 def test_fused_equals_split_bitwise(prec, lat, shape, chunk):
@@ -68,6 +73,7 @@ def test_fused_equals_split_bitwise(prec, lat, shape, chunk):
 
 
 @pytest.mark.parametrize("lat,shape,rates", [(0, (1, 33, 45), (1.64, 1.54, 1.9)),
+                                             (0, (1, 130, 250), (1.64, 1.54, 1.9)),
                                              (1, (11, 9, 35), (1.19, 1.4, 1.2, 1.4, 1.98))])
 def test_fused_equals_split_with_mrt(lat, shape, rates):
     require_gpu()
@@ -103,11 +109,12 @@ def test_fused_full_size_slab_equals_split():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32dev", "fp32sr", "mixed"])
-@pytest.mark.parametrize("n", [64, 256, 257])
+@pytest.mark.parametrize("n", [64, 256, 384, 385])
 def test_auto_variant_on_small_2d_grids(prec, n):
-    """AUTO runs the single pass on D2Q9 grids of at most 65536 sites and
+    """AUTO runs the single pass on D2Q9 grids of at most 384^2 sites and
     the two sweeps above: either way its state equals the explicit two-sweep
-    variant bit for bit (256^2 = 65536 sites, 257^2 just above)."""
+    variant bit for bit (64^2 and 256^2 in the two shapes with 1024 threads
+    per tile, 384^2 with 512, 385^2 just above)."""
     require_gpu()
     from paper_1907_13415_amd import lc
     rng = np.random.default_rng(900 + n)
