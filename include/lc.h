@@ -96,9 +96,9 @@ typedef int32_t lc_status;
 #define LC_VARIANT_FUSED 3  /* one pass: reads f and Q once, writes them once */
 
 /* A periodic grid of nx * ny * nz sites (nz == 1 for D2Q9; Sec. 2 runs
- * periodic boxes).  Every dimension >= 1 and ny, nz <= 65535, else
- * LC_EINVAL; more than 4e9 sites (beyond the sweeps' 32-bit site indices)
- * is LC_ENOMEM. */
+ * periodic boxes).  Every dimension >= 1, nx <= 2^30 and ny, nz <= 65535,
+ * else LC_EINVAL; more than 4e9 sites (beyond the sweeps' 32-bit site
+ * indices) is LC_ENOMEM. */
 typedef struct {
   int32_t lattice;   /* LC_D2Q9 or LC_D3Q19 */
   int32_t precision; /* LC_FP64, LC_FP32_DEV, LC_MIXED or LC_FP32_SR */

@@ -52,10 +52,12 @@ lc_status check_grid(const lc_grid* g) {
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(LC_EINVAL, "grid dimensions must be >= 1");
   if (g->lattice == LC_D2Q9 && g->nz != 1) return fail(LC_EINVAL, "D2Q9 requires nz == 1");
   // site indices are 32-bit unsigned inside the sweeps; ny and nz index
-  // launch grid dimensions, which are limited to 65535 blocks
+  // launch grid dimensions, which are limited to 65535 blocks; launch
+  // sizes round nx up to whole tiles in 32-bit arithmetic
   const double n = double(g->nx) * g->ny * g->nz;
   if (n > 4.0e9) return fail(LC_ENOMEM, "grid too large (%.3g sites; at most 4e9)", n);
   if (g->ny > 65535 || g->nz > 65535) return fail(LC_EINVAL, "ny and nz must not exceed 65535");
+  if (g->nx > (1 << 30)) return fail(LC_EINVAL, "nx must not exceed 2^30");
   return LC_OK;
 }
 

@@ -64,7 +64,7 @@ def test_init_rejects_bad_params(bad):
 
 @pytest.mark.parametrize("grid", [(0, 0, 16, 16, 2), (0, 0, 0, 16, 1), (2, 0, 16, 16, 1), (0, 4, 16, 16, 1),
                                   (1, 1, 8, -1, 8), (1, 1, 8, 65536, 8), (1, 1, 8, 8, 65536),
-                                  (1, 1, 2000, 2000, 1001)])
+                                  (1, 1, 2000, 2000, 1001), (0, 1, (1 << 30) + 1, 1, 1)])
 def test_init_rejects_bad_grid(grid):
     """Malformed grids are LC_EINVAL; a grid beyond 4e9 sites is LC_ENOMEM."""
     from paper_1907_13415_amd import lc
