@@ -3,7 +3,7 @@ import numpy as np
 
 # Field scales for the normwise parity metric: an error is measured against
 # max(max |reference|, scale), so that small derived fields (the velocity)
-# are not judged relative to round-off-sized values.
+# are not measured relative to round-off-sized values.
 SCALES = dict(f=1.0 / 36.0, q=1.0 / 3.0, rho=1.0, u=1.0 / np.sqrt(3.0), F=1e-3, S=1.0 / 3.0)
 
 
