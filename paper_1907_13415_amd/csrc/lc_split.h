@@ -101,7 +101,10 @@ __device__ __forceinline__ void stencil_lds(const S (*m)[R2], const S (*zp)[R2],
 
 // Isotropic stencil (D2Q9) of a symmetric tensor from an LDS plane with row
 // stride W: the centre value, the gradients (times two with HALF unset)
-// and the Laplacian, each from the pairs of opposite velocities.
+// and the Laplacian, each from the pairs of opposite velocities.  Per pair
+// and component one difference and one sum: the gradient components take
+// +-w_g (v+ - v-), the Laplacian 6 w_i (v+ + v-), and the centre's share,
+// 6 sum_{i != 0} w_i v(x) = 6 (1 - w_0) v(x), is taken off once at the end.
 template <typename S, int W, int RN, bool HALF = true>
 __device__ __forceinline__ void stencil_lds_iso2(const S (*m)[RN], int k, Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
   using Lt = Lattice<0>;
@@ -116,15 +119,15 @@ __device__ __forceinline__ void stencil_lds_iso2(const S (*m)[RN], int k, Sym<S>
       const int o = Lt::cx(i) + W * Lt::cy(i);
       const S vp = m[q][k + o], vm = m[q][k - o];
       const S wg = S((HALF ? 3.0 : 6.0) * Lt::w(i)), wl = S(6.0 * Lt::w(i));
-      const S df = wg * (vp - vm);
-      if (Lt::cx(i) != 0) gx += Lt::cx(i) > 0 ? df : -df;
-      if (Lt::cy(i) != 0) gy += Lt::cy(i) > 0 ? df : -df;
-      l += wl * ((vp - cc) + (vm - cc));
+      const S dif = vp - vm, sum = vp + vm;
+      if (Lt::cx(i) != 0) gx += (Lt::cx(i) > 0 ? wg : -wg) * dif;
+      if (Lt::cy(i) != 0) gy += (Lt::cy(i) > 0 ? wg : -wg) * dif;
+      l += wl * sum;
     }
     v[q] = cc;
     dx[q] = gx;
     dy[q] = gy;
-    lap[q] = l;
+    lap[q] = l - S(6.0 * (1.0 - Lt::w(0))) * cc;
   }
   c = Sym<S>{v[0], v[1], v[2], v[3], v[4]};
   d[0] = Sym<S>{dx[0], dx[1], dx[2], dx[3], dx[4]};
@@ -134,7 +137,8 @@ __device__ __forceinline__ void stencil_lds_iso2(const S (*m)[RN], int k, Sym<S>
 }
 
 // Isotropic stencil (D3Q19) of a symmetric tensor from three LDS planes
-// (centre m, above zp, below zm) with row stride W.
+// (centre m, above zp, below zm) with row stride W; the sums as in
+// stencil_lds_iso2.
 template <typename S, int W, int RN, bool HALF = true>
 __device__ __forceinline__ void stencil_lds_iso3(const S (*m)[RN], const S (*zp)[RN], const S (*zm)[RN], int k,
                                                  Sym<S>& c, Sym<S> (&d)[3], Sym<S>& L) {
@@ -152,17 +156,17 @@ __device__ __forceinline__ void stencil_lds_iso3(const S (*m)[RN], const S (*zp)
       const S(*pm)[RN] = Lt::cz(i) > 0 ? zm : (Lt::cz(i) < 0 ? zp : m);
       const S vp = pp[q][k + o], vm = pm[q][k - o];
       const S wg = S((HALF ? 3.0 : 6.0) * Lt::w(i)), wl = S(6.0 * Lt::w(i));
-      const S df = wg * (vp - vm);
-      if (Lt::cx(i) != 0) gx += Lt::cx(i) > 0 ? df : -df;
-      if (Lt::cy(i) != 0) gy += Lt::cy(i) > 0 ? df : -df;
-      if (Lt::cz(i) != 0) gz += Lt::cz(i) > 0 ? df : -df;
-      l += wl * ((vp - cc) + (vm - cc));
+      const S dif = vp - vm, sum = vp + vm;
+      if (Lt::cx(i) != 0) gx += (Lt::cx(i) > 0 ? wg : -wg) * dif;
+      if (Lt::cy(i) != 0) gy += (Lt::cy(i) > 0 ? wg : -wg) * dif;
+      if (Lt::cz(i) != 0) gz += (Lt::cz(i) > 0 ? wg : -wg) * dif;
+      l += wl * sum;
     }
     v[q] = cc;
     g[0][q] = gx;
     g[1][q] = gy;
     g[2][q] = gz;
-    lap[q] = l;
+    lap[q] = l - S(6.0 * (1.0 - Lt::w(0))) * cc;
   }
   c = Sym<S>{v[0], v[1], v[2], v[3], v[4]};
 #pragma unroll
@@ -644,10 +648,11 @@ __device__ __forceinline__ void split_q_body(const S* __restrict__ Qin, const S*
             const int o = Lt::cx(n) + T::W2 * Lt::cy(n);
             const int pp = Lt::cz(n) > 0 ? zp : (Lt::cz(n) < 0 ? zm : m);
             const int pm = Lt::cz(n) > 0 ? zm : (Lt::cz(n) < 0 ? zp : m);
-            const S du = S(6.0 * Lt::w(n)) * (sQ[pp][5 + a][k + o] - sQ[pm][5 + a][k - o]);
-            if (Lt::cx(n) != 0) g0 += Lt::cx(n) > 0 ? du : -du;
-            if (Lt::cy(n) != 0) g1 += Lt::cy(n) > 0 ? du : -du;
-            if (Lt::cz(n) != 0) g2 += Lt::cz(n) > 0 ? du : -du;
+            const S dif = sQ[pp][5 + a][k + o] - sQ[pm][5 + a][k - o];
+            const S w6 = S(6.0 * Lt::w(n));
+            if (Lt::cx(n) != 0) g0 += (Lt::cx(n) > 0 ? w6 : -w6) * dif;
+            if (Lt::cy(n) != 0) g1 += (Lt::cy(n) > 0 ? w6 : -w6) * dif;
+            if (Lt::cz(n) != 0) g2 += (Lt::cz(n) > 0 ? w6 : -w6) * dif;
           }
         }
         G[a][0] = g0;
