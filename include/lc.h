@@ -203,9 +203,10 @@ lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 /* Choose the kernel variant (LC_VARIANT_*) of the step of Sec. 1.2 (the
  * same arithmetic in each; SPLIT and FUSED agree bit for bit).  AUTO (the
  * default) picks the fastest the build provides for the context's stencil
- * and grid: the two-sweep variant, except FUSED for compact stencils on
- * D2Q9 grids of at most 147456 (384^2) sites, where launches are latency
- * bound and the single pass measured faster in every precision.  FUSED runs every
+ * and grid: the two-sweep variant, except FUSED on D2Q9 grids of at most
+ * 147456 (384^2) sites with the compact stencils and 65536 (256^2) with the
+ * isotropic ones, where launches are latency bound and the single pass
+ * measured faster in every precision.  FUSED runs every
  * stage of a step in one pass over the grid: a block recomputes the
  * stress, moments and predictor on shrinking rings around its tile instead
  * of reading them back from HBM.  LC_EUNSUPPORTED for the staged variant in
@@ -238,10 +239,11 @@ lc_status lc_set_collision(lc_ctx *ctx, int32_t kind, const double *rates, int32
  *   d_g V = 3 sum_i w_i c_ig V(x + c_i),  lap V = 6 sum_i w_i [V(x + c_i) - V(x)],
  * second order as well, with leading errors independent of direction.
  * Applies to the steps, exports and observables after the call.  The
- * isotropic stencils run in the two-sweep and staged variants (lc_step
- * returns LC_EUNSUPPORTED for LC_VARIANT_FUSED set explicitly), in LC_FP64
- * and LC_FP32_DEV (LC_EUNSUPPORTED otherwise), with either collision; the
- * reverse step and the batched form use the compact stencils only.
+ * isotropic stencils run in the two-sweep and staged variants, and in the
+ * single pass on D2Q9 grids (lc_step returns LC_EUNSUPPORTED for
+ * LC_VARIANT_FUSED on D3Q19), in LC_FP64 and LC_FP32_DEV (LC_EUNSUPPORTED
+ * otherwise), with either collision; the reverse step and the batched form
+ * use the compact stencils only.
  * LC_EINVAL for an unknown stencil. */
 lc_status lc_set_stencil(lc_ctx *ctx, int32_t stencil);
 

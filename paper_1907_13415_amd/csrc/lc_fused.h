@@ -100,7 +100,13 @@ constexpr int FUSED2D_HALF_TX = 32, FUSED2D_HALF_TY = 8, FUSED2D_HALF_NTHR = 512
 constexpr int FUSED2D_WIDE_TX = 32, FUSED2D_WIDE_TY = 8, FUSED2D_WIDE_NTHR = 256;
 constexpr int FUSED2D_CUS = 256;  // compute units of the chip
 
-template <int LAT, typename S, bool DEV, int TX, int TY, int NTHR, bool MRT, typename QT, bool SR>
+// ST: the difference stencils (lc_staged.h); the isotropic ones on
+// two-dimensional grids only, with the arithmetic of the two sweeps (the
+// whole stress of the radius-3 rectangle, corners included, in LDS for the
+// body force; the stencils of Q, u and Q^P from the pairs of opposite
+// velocities).
+template <int LAT, typename S, bool DEV, int TX, int TY, int NTHR, bool MRT, typename QT, bool SR,
+          int ST = STENCIL_COMPACT>
 __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* __restrict__ fin,
                                            S* __restrict__ fout, QT* __restrict__ Qout, const GridDims& g,
                                            const Coef<S>& c, const Coef<QT>& cq, int zc, int bx, int by, int bz,
@@ -121,9 +127,12 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   constexpr int NZS = DIM == 3 ? 3 : 1;  // tau_{a z} planes
   constexpr int NUS = DIM == 3 ? 3 : 1;  // velocity planes
   constexpr int NPS = DIM == 3 ? 2 : 1;  // predictor planes
+  constexpr bool ISO = ST == STENCIL_ISO;
+  static_assert(!ISO || DIM == 2, "isotropic stencils in the single pass: two-dimensional grids");
   __shared__ QT sQ[NQS][5][R4::N];
-  __shared__ QT sTx[NTS][DIM][NXA];
-  __shared__ QT sTy[NTS][DIM][NYA];
+  __shared__ QT sTx[NTS][DIM][ISO ? 1 : NXA];
+  __shared__ QT sTy[NTS][DIM][ISO ? 1 : NYA];
+  __shared__ QT sTi[ISO ? 2 : 1][ISO ? 2 : 1][ISO ? R3::N : 1];  // isotropic: tau_ab on the radius-3 rectangle
   __shared__ QT sTz[NZS][DIM == 3 ? 3 : 1][DIM == 3 ? R2::N : 1];
   __shared__ QT sU[NUS][DIM][R2::N];
   __shared__ QT sP[NPS][5][R1::N];
@@ -216,6 +225,21 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   // (b) stress of the plane in slot m (z neighbours in zp, zm) on the
   // radius-3 rectangle without its corners
   auto stress_plane = [&](int m, int zp, int zm, int ts, int zs) {
+    if constexpr (ISO) {  // every point of the rectangle: the body force reads the diagonal neighbours
+      for (int k = tid; k < R3::N; k += NTHR) {
+        const int i3 = k % R3::W, j3 = k / R3::W;
+        Sym<QT> q, Lq, d[3];
+        stencil_lds_iso2<QT, R4::W, R4::N>(sQ[m], (i3 + 1) + R4::W * (j3 + 1), q, d, Lq);
+        const Sym<QT> H = molecular_field(q, Lq, cq);
+        QT t[3][3];
+        stress(q, H, d, cq, t);
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+          for (int b = 0; b < 2; b++) sTi[a][b][k] = t[a][b];
+      }
+      return;
+    }
     for (int k = tid; k < R3::N; k += NTHR) {
       const int i3 = k % R3::W, j3 = k / R3::W;
       const bool xin = i3 >= 1 && i3 < R3::W - 1, yin = j3 >= 1 && j3 < R3::H - 1;
@@ -295,12 +319,35 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
       tile_first<TX, TY, 2>(k, i2, j2);
       const int k2 = i2 + R2::W * j2;
       S F[3] = {S(0), S(0), S(0)};
+      if constexpr (ISO) {  // F_a = 3 sum_i w_i sum_b c_ib tau_ab(x + c_i), over pairs
+        const int k3 = (i2 + 1) + R3::W * (j2 + 1);
 #pragma unroll
-      for (int a = 0; a < DIM; a++) {
-        const int kx = (i2 + 1) + WX * j2, ky = i2 + WY * (j2 + 1);
-        QT acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + WY] - sTy[ts][a][ky - WY]);
-        if constexpr (DIM == 3) acc += sTz[zsp][a][k2] - sTz[zsm][a][k2];
-        F[a] = S(QT(0.5) * acc);
+        for (int a = 0; a < DIM; a++) {
+          QT acc = QT(0);
+#pragma unroll
+          for (int i = 1; i < L::q; i++) {
+            if (L::opp(i) < i) continue;
+            const int o = L::cx(i) + R3::W * L::cy(i);
+            QT dsum = QT(0);
+#pragma unroll
+            for (int b = 0; b < DIM; b++) {
+              const int cb = b == 0 ? L::cx(i) : L::cy(i);
+              if (cb == 0) continue;
+              const QT dt = sTi[a][b][k3 + o] - sTi[a][b][k3 - o];
+              dsum += cb > 0 ? dt : -dt;
+            }
+            acc += QT(3.0 * L::w(i)) * dsum;
+          }
+          F[a] = S(acc);
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+          const int kx = (i2 + 1) + WX * j2, ky = i2 + WY * (j2 + 1);
+          QT acc = (sTx[ts][a][kx + 1] - sTx[ts][a][kx - 1]) + (sTy[ts][a][ky + WY] - sTy[ts][a][ky - WY]);
+          if constexpr (DIM == 3) acc += sTz[zsp][a][k2] - sTz[zsm][a][k2];
+          F[a] = S(QT(0.5) * acc);
+        }
       }
       const uint32_t site = plane + ip[n].s;
       S f[L::q];
@@ -341,12 +388,33 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
     const int k4 = (i1 + 3) + R4::W * (j1 + 3);
     const int k2 = (i1 + 1) + R2::W * (j1 + 1);
     Sym<QT> q, Lq, d[3];
-    stencil_lds<QT, DIM, R4::W, R4::N, false>(sQ[m], sQ[zp], sQ[zm], k4, q, d, Lq);
+    if constexpr (ISO)
+      stencil_lds_iso2<QT, R4::W, R4::N, false>(sQ[m], k4, q, d, Lq);
+    else
+      stencil_lds<QT, DIM, R4::W, R4::N, false>(sQ[m], sQ[zp], sQ[zm], k4, q, d, Lq);
     const Sym<QT> H = SR ? molecular_field_exact(q, Lq, cq) : molecular_field(q, Lq, cq);
     QT u[3], G[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       u[a] = a < DIM ? sU[um][a][k2] * QT(0.5) : QT(0);
+      if constexpr (ISO) {  // undivided: 6 sum_i w_i c_ib u_a(x + c_i), over pairs
+        QT g0 = QT(0), g1 = QT(0), g2 = QT(0);
+        if (a < DIM) {
+#pragma unroll
+          for (int i = 1; i < L::q; i++) {
+            if (L::opp(i) < i) continue;
+            const int o = L::cx(i) + R2::W * L::cy(i);
+            const QT dif = sU[um][a][k2 + o] - sU[um][a][k2 - o];
+            const QT w6 = QT(6.0 * L::w(i));
+            if (L::cx(i) != 0) g0 += (L::cx(i) > 0 ? w6 : -w6) * dif;
+            if (L::cy(i) != 0) g1 += (L::cy(i) > 0 ? w6 : -w6) * dif;
+          }
+        }
+        G[a][0] = g0;
+        G[a][1] = g1;
+        G[a][2] = g2;
+        continue;
+      }
       G[a][0] = a < DIM ? sU[um][a][k2 + 1] - sU[um][a][k2 - 1] : QT(0);
       G[a][1] = a < DIM ? sU[um][a][k2 + R2::W] - sU[um][a][k2 - R2::W] : QT(0);
       if constexpr (DIM == 3)
@@ -381,6 +449,15 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   const int k1 = (tx + 1) + R1::W * (ty + 1);
   auto corr_site = [&](int z, int ps, const Stash& st, const Sym<QT>& pc, const Sym<QT>& pzp, const Sym<QT>& pzm) {
     if (!own) return;
+    if constexpr (ISO) {
+      Sym<QT> pcc, Lp, d[3];
+      stencil_lds_iso2<QT, R1::W, R1::N, false>(sP[ps], k1, pcc, d, Lp);
+      const Sym<QT> H = SR ? molecular_field_exact(pcc, Lp, cq) : molecular_field(pcc, Lp, cq);
+      const Sym<QT> Rp = be_rate_flow<QT, true>(pcc, H, d, st.fl, cq);
+      const uint32_t s = uint32_t(x0 + tx) + uint32_t(g.nx) * (uint32_t(y0 + ty) + uint32_t(g.ny) * uint32_t(z));
+      store_q_update<QT, SR>(Qout, N, int64_t(s), st.q, st.r, Rp, srkey);
+      return;
+    }
     const QT vc[5] = {pc.xx, pc.xy, pc.xz, pc.yy, pc.yz};
     const QT vzp[5] = {pzp.xx, pzp.xy, pzp.xz, pzp.yy, pzp.yz};
     const QT vzm[5] = {pzm.xx, pzm.xy, pzm.xz, pzm.yy, pzm.yz};
@@ -470,13 +547,14 @@ __device__ __forceinline__ void fused_body(const QT* __restrict__ Qin, const S* 
   }
 }
 
-template <int LAT, typename S, bool DEV, int TX, int TY, int NTHR, bool MRT, typename QT, bool SR>
+template <int LAT, typename S, bool DEV, int TX, int TY, int NTHR, bool MRT, typename QT, bool SR,
+          int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(NTHR)
     fused_step(const QT* __restrict__ Qin, const S* __restrict__ fin, S* __restrict__ fout, QT* __restrict__ Qout,
                GridDims g, Coef<S> c, Coef<QT> cq, int zc, uint32_t srkey) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int t = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
-  fused_body<LAT, S, DEV, TX, TY, NTHR, MRT, QT, SR>(Qin, fin, fout, Qout, g, c, cq, zc, t % gridDim.x,
+  fused_body<LAT, S, DEV, TX, TY, NTHR, MRT, QT, SR, ST>(Qin, fin, fout, Qout, g, c, cq, zc, t % gridDim.x,
                                                (t / gridDim.x) % gridDim.y, t / (gridDim.x * gridDim.y), srkey);
 }
 

@@ -359,6 +359,19 @@ static void launch_fused(lc_ctx* c, hipStream_t st, int zc, const S* f0, const Q
   constexpr bool F32 = std::is_same<QT, float>::value;
   const bool sr = F32 && c->g.precision == LC_FP32_SR;
   const uint32_t key = step_key(c->step);
+  // the isotropic stencils: two-dimensional grids, FP64 and the FP32
+  // deviation form (lc_set_stencil), BGK or MRT
+  if constexpr (Lattice<LAT>::dim == 2 && std::is_same<S, QT>::value) {
+    if (c->stencil == LC_STENCIL_ISOTROPIC) {
+      if (c->coll == LC_COLL_MRT)
+        hipLaunchKernelGGL((fused_step<LAT, S, DEV, TX, TY, NTHR, true, QT, false, STENCIL_ISO>), grid, dim3(NTHR), 0,
+                           st, q0, f0, f1, q1, gd, k, kq, zc, key);
+      else
+        hipLaunchKernelGGL((fused_step<LAT, S, DEV, TX, TY, NTHR, false, QT, false, STENCIL_ISO>), grid, dim3(NTHR),
+                           0, st, q0, f0, f1, q1, gd, k, kq, zc, key);
+      return;
+    }
+  }
   if (c->coll == LC_COLL_MRT) {
     if (sr)
       hipLaunchKernelGGL((fused_step<LAT, S, DEV, TX, TY, NTHR, true, QT, F32>), grid, dim3(NTHR), 0, st, q0, f0, f1,
@@ -435,9 +448,15 @@ static lc_status run_steps_split(lc_ctx* c, int64_t n) {
 // against 14.7 us; from 448^2 the mixed form, from 512^2 FP64 and FP32 with
 // stochastic rounding are faster in two sweeps).
 constexpr int64_t AUTO_FUSED_MAX_SITES = 384 * 384;
+// With the isotropic stencils the single pass measured faster up to 256^2
+// (128^2: 6.1 against 9.3 us in FP32, 7.1 against 10.6 in FP64; 256^2: 7.0
+// against 9.8 and 8.7 against 11.1 us; at 320^2 FP64 is faster in two
+// sweeps).
+constexpr int64_t AUTO_FUSED_MAX_SITES_ISO = 256 * 256;
 static int resolved_variant(const lc_ctx* c) {
   if (c->variant != LC_VARIANT_AUTO) return c->variant;
-  if (c->stencil == LC_STENCIL_ISOTROPIC) return LC_VARIANT_SPLIT;
+  if (c->stencil == LC_STENCIL_ISOTROPIC)
+    return c->g.lattice == LC_D2Q9 && c->L.N <= AUTO_FUSED_MAX_SITES_ISO ? LC_VARIANT_FUSED : LC_VARIANT_SPLIT;
   if (c->g.lattice == LC_D2Q9 && c->L.N <= AUTO_FUSED_MAX_SITES) return LC_VARIANT_FUSED;
   return LC_VARIANT_SPLIT;
 }
@@ -445,8 +464,8 @@ static int resolved_variant(const lc_ctx* c) {
 template <int LAT, typename S, bool DEV, typename QT = S>
 static lc_status run_steps(lc_ctx* c, int64_t n) {
   const int v = resolved_variant(c);
-  if (c->stencil == LC_STENCIL_ISOTROPIC && v == LC_VARIANT_FUSED)
-    return fail(LC_EUNSUPPORTED, "the isotropic stencils are provided by the two-sweep and staged variants");
+  if (c->stencil == LC_STENCIL_ISOTROPIC && v == LC_VARIANT_FUSED && c->g.lattice != LC_D2Q9)
+    return fail(LC_EUNSUPPORTED, "the single pass takes the isotropic stencils on D2Q9 grids only");
   if (v == LC_VARIANT_SPLIT) return run_steps_split<LAT, S, DEV, QT>(c, n);
   if (v == LC_VARIANT_FUSED) return run_steps_fused<LAT, S, DEV, QT>(c, n);
   return run_steps_staged<LAT, S, DEV, QT>(c, n);
