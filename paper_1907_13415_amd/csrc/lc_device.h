@@ -143,9 +143,9 @@ struct Coef {
   T A0;      // bulk coefficient (the adjoint needs d/dgamma of lin and quad)
   // MRT: rate of each ghost group minus 1/tau (unused by the BGK kernels)
   T mrt[5];
-  // lin, quad and K unrounded, for the molecular field of the float form
-  // with stochastic rounding (evaluated in double there)
-  double lin_d, quad_d, K_d;
+  // lin and quad unrounded, for the bulk part of the molecular field of the
+  // float form with stochastic rounding (evaluated in double there)
+  double lin_d, quad_d;
 };
 
 template <typename T>
@@ -198,15 +198,28 @@ LC_HD Sym<T> molecular_field(const Sym<T>& Q, const Sym<T>& L, const Coef<T>& c)
 }
 
 // The molecular field of the float form with stochastic rounding: the bulk
-// terms nearly cancel near the nematic minimum (and balance K L at an
-// interface), and their float rounding, the same at a site from one step to
-// the next while the state there is unchanged, acts as a small systematic
-// force; so does the rounding of the bulk coefficients, which shifts the
-// coexistence temperature.  The sum is formed in double from the float Q and
-// L with the unrounded coefficients and rounded once.
+// terms nearly cancel near the nematic minimum, and their float rounding,
+// the same at a site from one step to the next while the state there is
+// unchanged, acts as a small systematic force; so does the rounding of the
+// bulk coefficients, which shifts the coexistence temperature.  The bulk
+// part is summed in double from the float Q with the unrounded
+// coefficients and rounded once; K L is then added in float.
 template <typename T>
-LC_HD Sym<T> molecular_field_exact(const Sym<T>& Q, const Sym<T>& L, const Coef<T>& c) {
-  return molecular_field_in<double, T>(Q, L, c.lin_d, c.quad_d, c.K_d);
+LC_HD Sym<T> molecular_field_exact(const Sym<T>& Qt, const Sym<T>& L, const Coef<T>& c) {
+  const Sym<double> Q{double(Qt.xx), double(Qt.xy), double(Qt.xz), double(Qt.yy), double(Qt.yz)};
+  const double zz = Q.zz();
+  const double sxx = Q.xx * Q.xx + Q.xy * Q.xy + Q.xz * Q.xz;
+  const double syy = Q.xy * Q.xy + Q.yy * Q.yy + Q.yz * Q.yz;
+  const double szz = Q.xz * Q.xz + Q.yz * Q.yz + zz * zz;
+  const double sxy = Q.xx * Q.xy + Q.xy * Q.yy + Q.xz * Q.yz;
+  const double sxz = Q.xx * Q.xz + Q.xy * Q.yz + Q.xz * zz;
+  const double syz = Q.xy * Q.xz + Q.yy * Q.yz + Q.yz * zz;
+  const double tr2 = sxx + syy + szz;
+  const double a = c.lin_d - c.quad_d * tr2;
+  const double third = c.quad_d * tr2 * (1.0 / 3.0);
+  const T bxx = T(a * Q.xx + (c.quad_d * sxx - third)), byy = T(a * Q.yy + (c.quad_d * syy - third));
+  const T bxy = T(a * Q.xy + c.quad_d * sxy), bxz = T(a * Q.xz + c.quad_d * sxz), byz = T(a * Q.yz + c.quad_d * syz);
+  return Sym<T>{bxx + c.K * L.xx, bxy + c.K * L.xy, bxz + c.K * L.xz, byy + c.K * L.yy, byz + c.K * L.yz};
 }
 
 // ---------------------------------------------------------------------------

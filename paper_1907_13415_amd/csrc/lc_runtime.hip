@@ -92,7 +92,6 @@ Coef<S> make_coef(const lc_params& p) {
   for (int g = 0; g < 5; g++) c.mrt[g] = S(0);
   c.lin_d = -p.A0 * (1.0 - p.gamma / 3.0);
   c.quad_d = p.A0 * p.gamma;
-  c.K_d = p.K;
   return c;
 }
 
