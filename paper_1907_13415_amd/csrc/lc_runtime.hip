@@ -301,7 +301,10 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   const GridDims gd{c->g.nx, c->g.ny, c->g.nz, c->L.N};
   const Coef<S> k = ctx_coef<S>(c);
   const Coef<QT> kq = ctx_coef<QT>(c);
-  const int zc1 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_LB) : 1;
+  // MRT and the isotropic stencils march 32-plane chunks in the float
+  // stress/LB sweep (1% and 3% faster there than 16)
+  const bool wide = sizeof(S) == 4 && (c->coll == LC_COLL_MRT || c->stencil == LC_STENCIL_ISOTROPIC);
+  const int zc1 = C::d3 ? (c->zchunk > 0 ? c->zchunk : (wide ? 32 : C::ZC_LB)) : 1;
   const int zc2 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_Q) : 1;
   const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY,
                 unsigned((c->g.nz + zc1 - 1) / zc1));
