@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "../../include/lc.h"
 #include "lc_aux.h"
@@ -16,8 +17,6 @@
 #include "lc_fused.h"
 #include "lc_batch.h"
 #include "lc_vjp.h"
-
-#include <vector>
 #include "lc_runtime.h"
 
 namespace lc {
@@ -1460,7 +1459,6 @@ lc_status lc_batch_init(int32_t ngrids, const lc_grid* grids, const lc_params* p
     return st;
   }
   char* scr = static_cast<char*>(arena->scratch);
-  const size_t es = grids[0].precision == LC_FP64 ? 8 : 4;
   b->views.resize(ngrids);
   for (int k = 0; k < ngrids; k++) {
     lc_ctx& v = b->views[k];
@@ -1478,7 +1476,9 @@ lc_status lc_batch_init(int32_t ngrids, const lc_grid* grids, const lc_params* p
     v.loaded = false;
     v.variant = LC_VARIANT_SPLIT;
     v.zchunk = 0;
-    (void)es;
+    v.coll = LC_COLL_BGK;
+    for (double& r : v.mrt) r = 0.0;
+    v.timing = false;
   }
   // tile -> grid maps for every tile shape
   for (int vv = 0; vv < BATCH_NV; vv++) {

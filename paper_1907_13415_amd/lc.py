@@ -280,9 +280,12 @@ def _torch():
 class Solver:
     """One grid: torch-owned buffers plus a library context.
 
-    lattice: "D2Q9" | "D3Q19"; precision: "fp64" | "fp32dev" | "mixed" (f as
-    float deviations, Q and its right-hand side in double);
-    params: (A0, gamma, K, Gamma, xi, tau).
+    lattice: "D2Q9" | "D3Q19"; precision: "fp64", "fp32dev" (f as float
+    deviations from the rest weights, Q in float, float arithmetic),
+    "fp32sr" (the same storage; bulk molecular field summed in double and
+    the Q update rounded stochastically) or "mixed" (f as float deviations,
+    Q and its right-hand side in double);
+    shape: (nz, ny, nx); params: (A0, gamma, K, Gamma, xi, tau).
     """
 
     def __init__(self, lattice, precision, shape, params, device="cuda", stream=None, variant=LC_VARIANT_AUTO):
