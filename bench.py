@@ -434,7 +434,7 @@ def main():
                     help="run one secondary leg alone and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the slab decomposition over xGMI is a design note).", file=sys.stderr)
         sys.exit(2)
 

@@ -71,7 +71,7 @@ typedef int32_t lc_status;
 #define LC_EDEVICE (-3)      /* HIP runtime error (message has the details) */
 #define LC_ENONFINITE (-4)   /* NaN or Inf found in the state by lc_observe */
 #define LC_ESTATE (-5)       /* call out of order (e.g. step before load) */
-#define LC_EUNSUPPORTED (-6) /* valid request this build does not provide */
+#define LC_EUNSUPPORTED (-6) /* valid request the library does not provide */
 
 #define LC_D2Q9 0
 #define LC_D3Q19 1
@@ -202,7 +202,7 @@ lc_status lc_set_params(lc_ctx *ctx, const lc_params *params);
 
 /* Choose the kernel variant (LC_VARIANT_*) of the step of Sec. 1.2 (the
  * same arithmetic in each; SPLIT and FUSED agree bit for bit).  AUTO (the
- * default) picks the fastest the build provides for the context's stencil
+ * default) picks the fastest the library provides for the context's stencil
  * and grid: the two-sweep variant, except FUSED on D2Q9 grids of at most
  * 147456 (384^2) sites with the compact stencils and 65536 (256^2) with the
  * isotropic ones, where launches are latency bound and the single pass

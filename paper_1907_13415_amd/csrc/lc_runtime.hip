@@ -1005,7 +1005,7 @@ lc_status lc_vjp_backward(lc_ctx* c, int32_t nseg, const double* const* f_cks, c
       vjp_replay(c, c->aux, f_cks[k], q_cks[k], ns[k], H[k & 1]);
       ok = ok && chk(hipEventRecord(rep[k & 1], c->aux));
     }
-    const int32_t w = k + 1;  // the segment walked in this round
+    const int32_t w = k + 1;  // the segment walked in this pass
     if (w < nseg) {
       ok = ok && chk(hipStreamWaitEvent(c->stream, rep[w & 1], 0));
       vjp_walk(c, v, ns[w], H[w & 1], adj_f, adj_q);

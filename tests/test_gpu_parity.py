@@ -17,7 +17,7 @@ from gpu_util import SCALES, rel_err, require_gpu
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-VARIANTS = None  # filled lazily: variants the build provides
+VARIANTS = None  # filled lazily: variants the library provides
 
 
 def _lc():
