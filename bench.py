@@ -366,13 +366,29 @@ def run_batch(torch, lc, stream, dev, steps, tiles=None, physics=True):
         ms = t0.elapsed_time(t1) / steps
         obs = b.observe()
         sweep = batch_velocities(b, ws) if physics else None
+        del b
+        # the same batch in the float form with stochastic rounding, on the
+        # tile shapes just chosen
+        bs = lc.BatchSolver("fp32sr", shapes, [w.params for w in ws], device=dev, stream=stream)
+        for k, w in enumerate(ws):
+            bs.load(k, w.q5)
+        bs.set_tiles(tile % 7, tile // 7)
+        bs.step(64)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        bs.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_sr = t0.elapsed_time(t1) / steps
+        del bs
     sites = sum(w.shape[1] * w.shape[2] for w in ws)
     shapes_ = ["32x8", "64x4", "16x16", "32x16", "64x8", "64x16", "128x8"]
     return dict(grids=len(ws), sites=sites, tiles={"lb": shapes_[tile % 7], "q": shapes_[tile // 7]},
                 ms_per_step=round(ms, 5),
                 mlups=round(sites / (ms * 1e-3) / 1e6, 2),
                 roofline_frac=round(alg_bytes_per_site(9, 4) * sites / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                nonfinite=int(sum(o["nonfinite"] for o in obs)), sweep=sweep)
+                nonfinite=int(sum(o["nonfinite"] for o in obs)), sweep=sweep,
+                fp32sr={"ms_per_step": round(ms_sr, 5), "mlups": round(sites / (ms_sr * 1e-3) / 1e6, 2)})
 
 
 def run_adjoint(torch, repeats=5):

@@ -395,8 +395,11 @@ lc_status lc_step_static(const lc_grid *grid, const lc_params *params, void *con
  * Batched form: many independent two-dimensional D2Q9 grids of their own
  * sizes and parameters (for example a temperature sweep in gamma around the
  * coexistence value of Sec. 2.1) advanced together.  All grids share one
- * storage precision, LC_FP64 or LC_FP32_DEV (LC_MIXED: LC_EUNSUPPORTED from
- * lc_batch_layout and lc_batch_init).  The grids' fields live in
+ * storage precision, LC_FP64, LC_FP32_DEV or LC_FP32_SR (LC_MIXED:
+ * LC_EUNSUPPORTED from lc_batch_layout and lc_batch_init).  With
+ * LC_FP32_SR every grid rounds its Q update with the uniform numbers of its
+ * step count, so each grid of a batch equals the same grid stepped alone by
+ * lc_step bit for bit.  The grids' fields live in
  * caller-owned arenas: grid k
  * occupies f_offsets[k] bytes into each f arena (9*N_k values) and
  * q_offsets[k] bytes into each Q arena (5*N_k values), in the single-grid

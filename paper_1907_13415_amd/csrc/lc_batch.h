@@ -13,6 +13,12 @@
 
 namespace lc {
 
+// Key of the uniform numbers of the stochastic rounding at step `step` (the
+// hash of the step counter; sites hash their index xor this key).  The
+// single-grid step and the batched Q sweep take their keys from here, so a
+// grid of a batch rounds as the same grid stepped alone.
+LC_HD uint32_t step_key(int64_t step) { return pcg_hash(uint32_t(step) * 0x9E3779B9u + 0x7F4A7C15u); }
+
 template <typename S>
 struct BatchDesc {
   int nx, ny;
@@ -37,17 +43,24 @@ __global__ void __launch_bounds__(TX* TY)
                                                   d.c, 1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
 }
 
-template <int LAT, typename S, int TX, int TY>
+// SR: the float form with stochastic rounding.  Its step key comes from
+// the step count *step_base + step_off (modulo 2^32, as the key uses the
+// count's low 32 bits): the host writes step_base before each run of
+// launches (a captured graph of several steps, or one step), and each
+// launch of the run carries its offset, so replays of a graph draw the keys
+// of the steps they advance.
+template <int LAT, typename S, int TX, int TY, bool SR = false>
 __global__ void __launch_bounds__(TX* TY)
     batch_q(const BatchDesc<S>* __restrict__ desc, const int* __restrict__ tile_grid, const S* __restrict__ Qa,
-            const S* __restrict__ ua, S* __restrict__ Qb) {
+            const S* __restrict__ ua, S* __restrict__ Qb, const uint32_t* __restrict__ step_base, int step_off) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int k = tile_grid[b];
   const BatchDesc<S> d = desc[k];
   const int t = b - d.tile0[1];
   const GridDims g{d.nx, d.ny, 1, d.N};
-  split_q_body<LAT, S, TX, TY>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.c, 1, t % d.tiles_x[1],
-                               t / d.tiles_x[1], 0);
+  const uint32_t key = SR ? step_key(int64_t(*step_base) + step_off) : 0u;
+  split_q_body<LAT, S, TX, TY, SR>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.c, 1, t % d.tiles_x[1],
+                                   t / d.tiles_x[1], 0, nullptr, key);
 }
 
 // Tile shapes the batch can run with, chosen per sweep by lc_batch_autotune

@@ -198,10 +198,6 @@ static Coef<S> ctx_coef(const lc_ctx* c) {
   return k;
 }
 
-// Key of the uniform numbers of the stochastic rounding at step `step` (the
-// hash of the step counter; sites hash their index xor this key).
-static uint32_t step_key(int64_t step) { return pcg_hash(uint32_t(step) * 0x9E3779B9u + 0x7F4A7C15u); }
-
 // Launches whose events the context holds before folding them.
 constexpr size_t TIMED_CAP = 1024;
 
@@ -1183,6 +1179,7 @@ struct BatchLayout {
   std::vector<size_t> f_off, q_off, u_off;  // byte offsets into the arenas / scratch u region
   size_t f_bytes = 0, q_bytes = 0;
   size_t off_desc = 0, off_map[BATCH_NV] = {}, off_u = 0, off_view = 0, off_res = 0;
+  size_t off_step = 0;  // step count of the next run of launches (stochastic rounding keys)
   size_t scratch_bytes = 0;
   int tiles[BATCH_NV] = {};
   std::vector<int> tile0[BATCH_NV], tiles_x[BATCH_NV];
@@ -1195,8 +1192,6 @@ static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B
     if (st) return st;
     if (grids[k].lattice != LC_D2Q9) return fail(LC_EUNSUPPORTED, "the batched form runs D2Q9 grids");
     if (grids[k].precision == LC_MIXED) return fail(LC_EUNSUPPORTED, "the batched form has no mixed-precision form");
-    if (grids[k].precision == LC_FP32_SR)
-      return fail(LC_EUNSUPPORTED, "the batched form has no stochastic-rounding form");
     if (grids[k].precision != grids[0].precision) return fail(LC_EINVAL, "all grids must share one precision");
   }
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
@@ -1238,6 +1233,8 @@ static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B
   }
   B.off_res = off;
   off = up(off + size_t(n) * OBS_W * sizeof(double));
+  B.off_step = off;
+  off = up(off + sizeof(uint32_t));
   B.off_u = off;
   off = up(off + uo);
   B.off_view = off;
@@ -1317,21 +1314,22 @@ static void batch_launch_lb(lc_batch* b, hipStream_t st, int parity) {
                      q0, f0, f1, u);
 }
 
-template <typename S, int V>
-static void batch_launch_q(lc_batch* b, hipStream_t st, int parity) {
+template <typename S, bool SR, int V>
+static void batch_launch_q(lc_batch* b, hipStream_t st, int parity, int step_off) {
   constexpr int TX = batch_tx(V), TY = batch_ty(V);
   char* scr = static_cast<char*>(b->arena.scratch);
   const BatchDesc<S>* desc = reinterpret_cast<const BatchDesc<S>*>(scr + b->B.off_desc);
   const int* map = reinterpret_cast<const int*>(scr + b->B.off_map[V]);
   const S* u = reinterpret_cast<const S*>(scr + b->B.off_u);
+  const uint32_t* step_base = reinterpret_cast<const uint32_t*>(scr + b->B.off_step);
   const S* q0 = static_cast<const S*>(b->arena.Q[parity]);
   S* q1 = static_cast<S*>(b->arena.Q[parity ^ 1]);
-  hipLaunchKernelGGL((batch_q<0, S, TX, TY>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map, q0, u,
-                     q1);
+  hipLaunchKernelGGL((batch_q<0, S, TX, TY, SR>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map, q0,
+                     u, q1, step_base, step_off);
 }
 
-template <typename S, bool DEV>
-static void batch_launch(lc_batch* b, hipStream_t st, int parity) {
+template <typename S, bool DEV, bool SR>
+static void batch_launch(lc_batch* b, hipStream_t st, int parity, int step_off) {
   static_assert(BATCH_NV == 7, "one launch branch per tile shape");
   switch (b->vt[0]) {
     case 0: batch_launch_lb<S, DEV, 0>(b, st, parity); break;
@@ -1343,21 +1341,34 @@ static void batch_launch(lc_batch* b, hipStream_t st, int parity) {
     default: batch_launch_lb<S, DEV, 6>(b, st, parity); break;
   }
   switch (b->vt[1]) {
-    case 0: batch_launch_q<S, 0>(b, st, parity); break;
-    case 1: batch_launch_q<S, 1>(b, st, parity); break;
-    case 2: batch_launch_q<S, 2>(b, st, parity); break;
-    case 3: batch_launch_q<S, 3>(b, st, parity); break;
-    case 4: batch_launch_q<S, 4>(b, st, parity); break;
-    case 5: batch_launch_q<S, 5>(b, st, parity); break;
-    default: batch_launch_q<S, 6>(b, st, parity); break;
+    case 0: batch_launch_q<S, SR, 0>(b, st, parity, step_off); break;
+    case 1: batch_launch_q<S, SR, 1>(b, st, parity, step_off); break;
+    case 2: batch_launch_q<S, SR, 2>(b, st, parity, step_off); break;
+    case 3: batch_launch_q<S, SR, 3>(b, st, parity, step_off); break;
+    case 4: batch_launch_q<S, SR, 4>(b, st, parity, step_off); break;
+    case 5: batch_launch_q<S, SR, 5>(b, st, parity, step_off); break;
+    default: batch_launch_q<S, SR, 6>(b, st, parity, step_off); break;
   }
 }
 
-static void batch_launch_step(lc_batch* b, hipStream_t st, int parity) {
+// One step of every grid; step_off: the step's offset from the step count
+// last written to the batch's step slot (stochastic rounding only).
+static void batch_launch_step(lc_batch* b, hipStream_t st, int parity, int step_off) {
   if (b->grids[0].precision == LC_FP64)
-    batch_launch<double, false>(b, st, parity);
+    batch_launch<double, false, false>(b, st, parity, step_off);
+  else if (b->grids[0].precision == LC_FP32_SR)
+    batch_launch<float, true, true>(b, st, parity, step_off);
   else
-    batch_launch<float, true>(b, st, parity);
+    batch_launch<float, true, false>(b, st, parity, step_off);
+}
+
+// Write the step count of the next run of launches to the batch's step slot
+// (read by the stochastic-rounding Q sweep; on the stream, never captured).
+static lc_status batch_set_step(lc_batch* b) {
+  if (b->grids[0].precision != LC_FP32_SR) return LC_OK;
+  void* p = static_cast<char*>(b->arena.scratch) + b->B.off_step;
+  return hip_check(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(p), int(uint32_t(b->step)), 1, b->stream),
+                   "batch step count");
 }
 
 static void batch_drop_graphs(lc_batch* b) {
@@ -1375,7 +1386,7 @@ static lc_status batch_build_graph(lc_batch* b, int parity) {
   if (st) return st;
   int p = parity;
   for (int i = 0; i < lc_batch::G; i++) {
-    batch_launch_step(b, b->cap, p);
+    batch_launch_step(b, b->cap, p, i);
     p ^= 1;
   }
   hipGraph_t g = nullptr;
@@ -1548,13 +1559,17 @@ lc_status lc_batch_step(lc_batch* b, int64_t n) {
       lc_status st = batch_build_graph(b, b->parity);
       if (st) return st;
     }
-    lc_status st = hip_check(hipGraphLaunch(b->exec[b->parity], b->stream), "graph launch");
+    lc_status st = batch_set_step(b);
+    if (st) return st;
+    st = hip_check(hipGraphLaunch(b->exec[b->parity], b->stream), "graph launch");
     if (st) return st;
     n -= lc_batch::G;
     b->step += lc_batch::G;
   }
   for (int64_t i = 0; i < n; i++) {
-    batch_launch_step(b, b->stream, b->parity);
+    lc_status st = batch_set_step(b);
+    if (st) return st;
+    batch_launch_step(b, b->stream, b->parity, 0);
     b->parity ^= 1;
     b->step++;
   }

@@ -126,6 +126,21 @@ def test_mixed_precision_sizes_and_unsupported_paths():
     assert e.value.code == lc.LC_EUNSUPPORTED
 
 
+def test_batch_layout_of_the_stochastic_rounding_form():
+    """The batched form takes LC_FP32_SR with the float form's arenas; all
+    grids of a batch share one precision."""
+    from paper_1907_13415_amd import lc
+    shapes = [(48, 64), (40, 40), (17, 23)]
+    dev = lc.lc_batch_layout([lc.make_grid(lc.LC_D2Q9, lc.LC_FP32_DEV, nx, ny, 1) for ny, nx in shapes])
+    sr = lc.lc_batch_layout([lc.make_grid(lc.LC_D2Q9, lc.LC_FP32_SR, nx, ny, 1) for ny, nx in shapes])
+    assert dev == sr
+    assert sr[0] >= 9 * 4 * sum(nx * ny for ny, nx in shapes)
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_batch_layout([lc.make_grid(lc.LC_D2Q9, lc.LC_FP32_SR, 32, 32, 1),
+                            lc.make_grid(lc.LC_D2Q9, lc.LC_FP32_DEV, 32, 32, 1)])
+    assert e.value.code == lc.LC_EINVAL
+
+
 def test_host_side_validation_of_settings_and_reverse_calls():
     """Collision, variant and chunk settings and the reverse-sweep entry
     points reject bad arguments on the host, before any device work."""

@@ -41,8 +41,10 @@ def _batch_inputs(seed):
     return q5s, params
 
 
-@pytest.mark.parametrize("prec", ["fp32dev", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32dev", "fp64", "fp32sr"])
 def test_batch_equals_single_grid_across_graph_replays(prec):
+    """With stochastic rounding too: a graph replay draws the uniform
+    numbers of the steps it advances, as the single grid does."""
     lc = _lc()
     _say("batch vs single %s" % prec)
     q5s, params = _batch_inputs(1)
@@ -148,14 +150,15 @@ def test_temperature_sweep_workload_full_size():
 
 def test_sweep_front_speeds_fp32_against_fp64():
     """The reported quantity of the sweep, the front speed of each grid
-    between steps 1000 and 5000, in the FP32 deviation form against double
-    precision: grids whose front moves (neither melted nor filled) agree to
-    a small fraction of their speed."""
+    between steps 1000 and 5000, in the float forms (FP32 deviation, FP32
+    with stochastic rounding) against double precision: grids whose front
+    moves (neither melted nor filled) agree to a small fraction of their
+    speed."""
     lc = _lc()
     ws = inputs.config3()
     shapes = [w.shape[1:] for w in ws]
     half = {}
-    for prec in ("fp64", "fp32dev"):
+    for prec in ("fp64", "fp32dev", "fp32sr"):
         b = lc.BatchSolver(prec, shapes, [w.params for w in ws])
         for k, w in enumerate(ws):
             b.load(k, w.q5)
@@ -165,25 +168,27 @@ def test_sweep_front_speeds_fp32_against_fp64():
         o1 = b.observe(half_axis=0)
         half[prec] = [(a["ssum_half"], c["ssum_half"], c["ssum"]) for a, c in zip(o0, o1)]
         del b
-    worst, n = 0.0, 0
-    for w, h64, h32 in zip(ws, half["fp64"], half["fp32dev"]):
-        L, g = w.shape[2], w.params[1]
-        if g < 8.0 / 3.0:
-            continue
-        sn = 0.25 + 0.75 * (1.0 - 8.0 / (3.0 * g)) ** 0.5
-        if h64[2] < 1e-6 * L * L or h64[2] > 0.99 * sn * L * L:
-            continue  # melted or filled
-        v64 = (h64[1] - h64[0]) / (sn * L) / 4000
-        v32 = (h32[1] - h32[0]) / (sn * L) / 4000
-        if abs(v64) < 1e-7:
-            continue
-        worst = max(worst, abs(v32 - v64) / abs(v64))
-        n += 1
-    print("sweep front speeds, %d moving grids: worst FP32 relative error %.2e" % (n, worst), flush=True)
-    assert n >= 10 and worst < 1e-3  # measured 1.2e-5 over 24 moving grids
+    for prec in ("fp32dev", "fp32sr"):
+        worst, n = 0.0, 0
+        for w, h64, h32 in zip(ws, half["fp64"], half[prec]):
+            L, g = w.shape[2], w.params[1]
+            if g < 8.0 / 3.0:
+                continue
+            sn = 0.25 + 0.75 * (1.0 - 8.0 / (3.0 * g)) ** 0.5
+            if h64[2] < 1e-6 * L * L or h64[2] > 0.99 * sn * L * L:
+                continue  # melted or filled
+            v64 = (h64[1] - h64[0]) / (sn * L) / 4000
+            v32 = (h32[1] - h32[0]) / (sn * L) / 4000
+            if abs(v64) < 1e-7:
+                continue
+            worst = max(worst, abs(v32 - v64) / abs(v64))
+            n += 1
+        print("sweep front speeds, %d moving grids: worst %s relative error %.2e" % (n, prec, worst), flush=True)
+        assert n >= 10 and worst < 1e-3  # measured 1.3e-5 (FP32 deviation), 4.3e-6 (stochastic rounding) over 24 moving grids
 
 
-def test_batch_tile_shapes_agree_bitwise():
+@pytest.mark.parametrize("prec", ["fp32dev", "fp32sr"])
+def test_batch_tile_shapes_agree_bitwise(prec):
     """Every site runs the same code wherever it falls in a tile, so every
     tile shape of either sweep gives identical results (seven pairings that
     use each shape once in each sweep)."""
@@ -191,7 +196,7 @@ def test_batch_tile_shapes_agree_bitwise():
     q5s, params = _batch_inputs(4)
     res = []
     for v in range(7):
-        b = lc.BatchSolver("fp32dev", SHAPES, params)
+        b = lc.BatchSolver(prec, SHAPES, params)
         b.set_tiles(v, (3 * v + 1) % 7)
         for k, q5 in enumerate(q5s):
             b.load(k, q5)
