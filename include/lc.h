@@ -395,22 +395,22 @@ lc_status lc_step_static(const lc_grid *grid, const lc_params *params, void *con
  * Batched form: many independent two-dimensional D2Q9 grids of their own
  * sizes and parameters (for example a temperature sweep in gamma around the
  * coexistence value of Sec. 2.1) advanced together.  All grids share one
- * storage precision, LC_FP64, LC_FP32_DEV or LC_FP32_SR (LC_MIXED:
- * LC_EUNSUPPORTED from lc_batch_layout and lc_batch_init).  With
+ * storage precision (any of the four; LC_EINVAL otherwise).  With
  * LC_FP32_SR every grid rounds its Q update with the uniform numbers of its
  * step count, so each grid of a batch equals the same grid stepped alone by
  * lc_step bit for bit.  The grids' fields live in
  * caller-owned arenas: grid k
  * occupies f_offsets[k] bytes into each f arena (9*N_k values) and
- * q_offsets[k] bytes into each Q arena (5*N_k values), in the single-grid
- * layout.  A step of the batch is two kernel launches covering the tiles of
+ * q_offsets[k] bytes into each Q arena (5*N_k values, double in the mixed
+ * form), in the single-grid layout.  A step of the batch is two kernel launches covering the tiles of
  * every grid; runs of steps are captured once in a HIP graph (64 steps per
  * graph) and replayed on the batch stream.
  * ------------------------------------------------------------------------- */
 
 /* Arena sizes and per-grid byte offsets (f_offsets, q_offsets: ngrids
  * entries each, may be NULL) for the many grids of a temperature sweep
- * (Sec. 2.1).  LC_EINVAL for a bad grid, LC_EUNSUPPORTED as above. */
+ * (Sec. 2.1).  LC_EINVAL for a bad grid or mixed precisions,
+ * LC_EUNSUPPORTED for D3Q19 grids. */
 lc_status lc_batch_layout(int32_t ngrids, const lc_grid *grids, size_t *f_bytes, size_t *q_bytes,
                           size_t *scratch_bytes, size_t *f_offsets, size_t *q_offsets);
 

@@ -19,28 +19,32 @@ namespace lc {
 // grid of a batch rounds as the same grid stepped alone.
 LC_HD uint32_t step_key(int64_t step) { return pcg_hash(uint32_t(step) * 0x9E3779B9u + 0x7F4A7C15u); }
 
-template <typename S>
+// S: type of the populations; QT: type of Q, the velocity and the
+// molecular field, stress and body force (S, or double in the
+// mixed-precision form).
+template <typename S, typename QT = S>
 struct BatchDesc {
   int nx, ny;
   int64_t N;
-  int64_t f_off, q_off, u_off;  // element offsets into the arenas
+  int64_t f_off, q_off, u_off;  // element offsets into the arenas (f in S, Q and u in QT)
   int tile0[2], tiles_x[2];     // per sweep (0: LB, 1: Q): first block of this grid, tiles along x
-  Coef<S> c;
+  Coef<S> c;                    // constants in the population type
+  Coef<QT> cq;                  // the same in the order-tensor type
 };
 
-template <int LAT, typename S, bool DEV, int TX, int TY>
+template <int LAT, typename S, bool DEV, int TX, int TY, typename QT = S>
 __global__ void __launch_bounds__(TX* TY)
-    batch_lb(const BatchDesc<S>* __restrict__ desc, const int* __restrict__ tile_grid, const S* __restrict__ Qa,
-             const S* __restrict__ fa, S* __restrict__ fb, S* __restrict__ ua) {
+    batch_lb(const BatchDesc<S, QT>* __restrict__ desc, const int* __restrict__ tile_grid,
+             const QT* __restrict__ Qa, const S* __restrict__ fa, S* __restrict__ fb, QT* __restrict__ ua) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int k = tile_grid[b];
-  const BatchDesc<S> d = desc[k];
+  const BatchDesc<S, QT> d = desc[k];
   const int t = b - d.tile0[0];
   const GridDims g{d.nx, d.ny, 1, d.N};
   // many grids stream through the caches together: populations read with
   // nontemporal loads
-  split_lb_body<LAT, S, DEV, TX, TY, false, true>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g, d.c,
-                                                  d.c, 1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
+  split_lb_body<LAT, S, DEV, TX, TY, false, true, QT>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g,
+                                                      d.c, d.cq, 1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
 }
 
 // SR: the float form with stochastic rounding.  Its step key comes from
@@ -49,18 +53,21 @@ __global__ void __launch_bounds__(TX* TY)
 // launches (a captured graph of several steps, or one step), and each
 // launch of the run carries its offset, so replays of a graph draw the keys
 // of the steps they advance.
-template <int LAT, typename S, int TX, int TY, bool SR = false>
+// The Q sweep runs in the order-tensor type QT; S is the population type
+// of the descriptors.
+template <int LAT, typename S, typename QT, int TX, int TY, bool SR = false>
 __global__ void __launch_bounds__(TX* TY)
-    batch_q(const BatchDesc<S>* __restrict__ desc, const int* __restrict__ tile_grid, const S* __restrict__ Qa,
-            const S* __restrict__ ua, S* __restrict__ Qb, const uint32_t* __restrict__ step_base, int step_off) {
+    batch_q(const BatchDesc<S, QT>* __restrict__ desc, const int* __restrict__ tile_grid,
+            const QT* __restrict__ Qa, const QT* __restrict__ ua, QT* __restrict__ Qb,
+            const uint32_t* __restrict__ step_base, int step_off) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int k = tile_grid[b];
-  const BatchDesc<S> d = desc[k];
+  const BatchDesc<S, QT> d = desc[k];
   const int t = b - d.tile0[1];
   const GridDims g{d.nx, d.ny, 1, d.N};
   const uint32_t key = SR ? step_key(int64_t(*step_base) + step_off) : 0u;
-  split_q_body<LAT, S, TX, TY, SR>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.c, 1, t % d.tiles_x[1],
-                                   t / d.tiles_x[1], 0, nullptr, key);
+  split_q_body<LAT, QT, TX, TY, SR>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.cq, 1, t % d.tiles_x[1],
+                                    t / d.tiles_x[1], 0, nullptr, key);
 }
 
 // Tile shapes the batch can run with, chosen per sweep by lc_batch_autotune

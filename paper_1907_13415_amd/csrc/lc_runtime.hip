@@ -1191,11 +1191,12 @@ static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B
     lc_status st = check_grid(&grids[k]);
     if (st) return st;
     if (grids[k].lattice != LC_D2Q9) return fail(LC_EUNSUPPORTED, "the batched form runs D2Q9 grids");
-    if (grids[k].precision == LC_MIXED) return fail(LC_EUNSUPPORTED, "the batched form has no mixed-precision form");
     if (grids[k].precision != grids[0].precision) return fail(LC_EINVAL, "all grids must share one precision");
   }
   auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+  // element sizes of f and of Q and u (double Q and u in the mixed form)
   const size_t es = grids[0].precision == LC_FP64 ? 8 : 4;
+  const size_t es_q = grids[0].precision == LC_FP64 || grids[0].precision == LC_MIXED ? 8 : 4;
   B.f_off.resize(n);
   B.q_off.resize(n);
   B.u_off.resize(n);
@@ -1210,9 +1211,9 @@ static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B
     B.f_off[k] = fo;
     fo = up(fo + 9 * N * es);
     B.q_off[k] = qo;
-    qo = up(qo + 5 * N * es);
+    qo = up(qo + 5 * N * es_q);
     B.u_off[k] = uo;
-    uo = up(uo + 2 * N * es);
+    uo = up(uo + 2 * N * es_q);
     view = std::max(view, layout_of(grids[k]).scratch_bytes);
     for (int v = 0; v < BATCH_NV; v++) {
       const int tx = batch_tx(v), ty = batch_ty(v);
@@ -1226,7 +1227,7 @@ static lc_status batch_layout_of(int32_t n, const lc_grid* grids, BatchLayout& B
   B.q_bytes = qo;
   size_t off = 0;
   B.off_desc = off;
-  off = up(off + size_t(n) * sizeof(BatchDesc<double>));
+  off = up(off + size_t(n) * std::max(sizeof(BatchDesc<double>), sizeof(BatchDesc<float, double>)));
   for (int v = 0; v < BATCH_NV; v++) {
     B.off_map[v] = off;
     off = up(off + size_t(B.tiles[v]) * sizeof(int));
@@ -1267,23 +1268,24 @@ struct lc_batch {
 
 namespace lc {
 
-template <typename S>
+template <typename S, typename QT>
 static void batch_fill_desc(lc_batch* b) {
-  b->host_desc.assign(size_t(b->n) * sizeof(BatchDesc<S>), 0);
-  BatchDesc<S>* d = reinterpret_cast<BatchDesc<S>*>(b->host_desc.data());
-  const size_t es = sizeof(S);
+  using D = BatchDesc<S, QT>;
+  b->host_desc.assign(size_t(b->n) * sizeof(D), 0);
+  D* d = reinterpret_cast<D*>(b->host_desc.data());
   for (int k = 0; k < b->n; k++) {
     d[k].nx = b->grids[k].nx;
     d[k].ny = b->grids[k].ny;
     d[k].N = int64_t(b->grids[k].nx) * b->grids[k].ny;
-    d[k].f_off = int64_t(b->B.f_off[k] / es);
-    d[k].q_off = int64_t(b->B.q_off[k] / es);
-    d[k].u_off = int64_t(b->B.u_off[k] / es);
+    d[k].f_off = int64_t(b->B.f_off[k] / sizeof(S));
+    d[k].q_off = int64_t(b->B.q_off[k] / sizeof(QT));
+    d[k].u_off = int64_t(b->B.u_off[k] / sizeof(QT));
     for (int w = 0; w < 2; w++) {
       d[k].tile0[w] = b->B.tile0[b->vt[w]][k];
       d[k].tiles_x[w] = b->B.tiles_x[b->vt[w]][k];
     }
     d[k].c = make_coef<S>(b->params[k]);
+    d[k].cq = make_coef<QT>(b->params[k]);
   }
 }
 
@@ -1291,63 +1293,65 @@ static void batch_fill_desc(lc_batch* b) {
 // host copy lives in the batch object).
 static lc_status batch_upload(lc_batch* b) {
   if (b->grids[0].precision == LC_FP64)
-    batch_fill_desc<double>(b);
+    batch_fill_desc<double, double>(b);
+  else if (b->grids[0].precision == LC_MIXED)
+    batch_fill_desc<float, double>(b);
   else
-    batch_fill_desc<float>(b);
+    batch_fill_desc<float, float>(b);
   char* scr = static_cast<char*>(b->arena.scratch);
   return hip_check(hipMemcpyAsync(scr + b->B.off_desc, b->host_desc.data(), b->host_desc.size(),
                                   hipMemcpyHostToDevice, b->stream),
                    "batch descriptor upload");
 }
 
-template <typename S, bool DEV, int V>
+template <typename S, bool DEV, typename QT, int V>
 static void batch_launch_lb(lc_batch* b, hipStream_t st, int parity) {
   constexpr int TX = batch_tx(V), TY = batch_ty(V);
   char* scr = static_cast<char*>(b->arena.scratch);
-  const BatchDesc<S>* desc = reinterpret_cast<const BatchDesc<S>*>(scr + b->B.off_desc);
+  const BatchDesc<S, QT>* desc = reinterpret_cast<const BatchDesc<S, QT>*>(scr + b->B.off_desc);
   const int* map = reinterpret_cast<const int*>(scr + b->B.off_map[V]);
-  S* u = reinterpret_cast<S*>(scr + b->B.off_u);
+  QT* u = reinterpret_cast<QT*>(scr + b->B.off_u);
   const S* f0 = static_cast<const S*>(b->arena.f[parity]);
   S* f1 = static_cast<S*>(b->arena.f[parity ^ 1]);
-  const S* q0 = static_cast<const S*>(b->arena.Q[parity]);
-  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map,
-                     q0, f0, f1, u);
+  const QT* q0 = static_cast<const QT*>(b->arena.Q[parity]);
+  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY, QT>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc,
+                     map, q0, f0, f1, u);
 }
 
-template <typename S, bool SR, int V>
+template <typename S, typename QT, bool SR, int V>
 static void batch_launch_q(lc_batch* b, hipStream_t st, int parity, int step_off) {
   constexpr int TX = batch_tx(V), TY = batch_ty(V);
   char* scr = static_cast<char*>(b->arena.scratch);
-  const BatchDesc<S>* desc = reinterpret_cast<const BatchDesc<S>*>(scr + b->B.off_desc);
+  const BatchDesc<S, QT>* desc = reinterpret_cast<const BatchDesc<S, QT>*>(scr + b->B.off_desc);
   const int* map = reinterpret_cast<const int*>(scr + b->B.off_map[V]);
-  const S* u = reinterpret_cast<const S*>(scr + b->B.off_u);
+  const QT* u = reinterpret_cast<const QT*>(scr + b->B.off_u);
   const uint32_t* step_base = reinterpret_cast<const uint32_t*>(scr + b->B.off_step);
-  const S* q0 = static_cast<const S*>(b->arena.Q[parity]);
-  S* q1 = static_cast<S*>(b->arena.Q[parity ^ 1]);
-  hipLaunchKernelGGL((batch_q<0, S, TX, TY, SR>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map, q0,
-                     u, q1, step_base, step_off);
+  const QT* q0 = static_cast<const QT*>(b->arena.Q[parity]);
+  QT* q1 = static_cast<QT*>(b->arena.Q[parity ^ 1]);
+  hipLaunchKernelGGL((batch_q<0, S, QT, TX, TY, SR>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map,
+                     q0, u, q1, step_base, step_off);
 }
 
-template <typename S, bool DEV, bool SR>
+template <typename S, bool DEV, typename QT, bool SR>
 static void batch_launch(lc_batch* b, hipStream_t st, int parity, int step_off) {
   static_assert(BATCH_NV == 7, "one launch branch per tile shape");
   switch (b->vt[0]) {
-    case 0: batch_launch_lb<S, DEV, 0>(b, st, parity); break;
-    case 1: batch_launch_lb<S, DEV, 1>(b, st, parity); break;
-    case 2: batch_launch_lb<S, DEV, 2>(b, st, parity); break;
-    case 3: batch_launch_lb<S, DEV, 3>(b, st, parity); break;
-    case 4: batch_launch_lb<S, DEV, 4>(b, st, parity); break;
-    case 5: batch_launch_lb<S, DEV, 5>(b, st, parity); break;
-    default: batch_launch_lb<S, DEV, 6>(b, st, parity); break;
+    case 0: batch_launch_lb<S, DEV, QT, 0>(b, st, parity); break;
+    case 1: batch_launch_lb<S, DEV, QT, 1>(b, st, parity); break;
+    case 2: batch_launch_lb<S, DEV, QT, 2>(b, st, parity); break;
+    case 3: batch_launch_lb<S, DEV, QT, 3>(b, st, parity); break;
+    case 4: batch_launch_lb<S, DEV, QT, 4>(b, st, parity); break;
+    case 5: batch_launch_lb<S, DEV, QT, 5>(b, st, parity); break;
+    default: batch_launch_lb<S, DEV, QT, 6>(b, st, parity); break;
   }
   switch (b->vt[1]) {
-    case 0: batch_launch_q<S, SR, 0>(b, st, parity, step_off); break;
-    case 1: batch_launch_q<S, SR, 1>(b, st, parity, step_off); break;
-    case 2: batch_launch_q<S, SR, 2>(b, st, parity, step_off); break;
-    case 3: batch_launch_q<S, SR, 3>(b, st, parity, step_off); break;
-    case 4: batch_launch_q<S, SR, 4>(b, st, parity, step_off); break;
-    case 5: batch_launch_q<S, SR, 5>(b, st, parity, step_off); break;
-    default: batch_launch_q<S, SR, 6>(b, st, parity, step_off); break;
+    case 0: batch_launch_q<S, QT, SR, 0>(b, st, parity, step_off); break;
+    case 1: batch_launch_q<S, QT, SR, 1>(b, st, parity, step_off); break;
+    case 2: batch_launch_q<S, QT, SR, 2>(b, st, parity, step_off); break;
+    case 3: batch_launch_q<S, QT, SR, 3>(b, st, parity, step_off); break;
+    case 4: batch_launch_q<S, QT, SR, 4>(b, st, parity, step_off); break;
+    case 5: batch_launch_q<S, QT, SR, 5>(b, st, parity, step_off); break;
+    default: batch_launch_q<S, QT, SR, 6>(b, st, parity, step_off); break;
   }
 }
 
@@ -1355,11 +1359,13 @@ static void batch_launch(lc_batch* b, hipStream_t st, int parity, int step_off) 
 // last written to the batch's step slot (stochastic rounding only).
 static void batch_launch_step(lc_batch* b, hipStream_t st, int parity, int step_off) {
   if (b->grids[0].precision == LC_FP64)
-    batch_launch<double, false, false>(b, st, parity, step_off);
+    batch_launch<double, false, double, false>(b, st, parity, step_off);
+  else if (b->grids[0].precision == LC_MIXED)
+    batch_launch<float, true, double, false>(b, st, parity, step_off);
   else if (b->grids[0].precision == LC_FP32_SR)
-    batch_launch<float, true, true>(b, st, parity, step_off);
+    batch_launch<float, true, float, true>(b, st, parity, step_off);
   else
-    batch_launch<float, true, false>(b, st, parity, step_off);
+    batch_launch<float, true, float, false>(b, st, parity, step_off);
 }
 
 // Write the step count of the next run of launches to the batch's step slot

@@ -432,7 +432,7 @@ class BatchSolver:
     """Many independent D2Q9 grids advanced together.
 
     shapes: list of (ny, nx); params: list of (A0, gamma, K, Gamma, xi, tau);
-    precision: "fp64", "fp32dev" or "fp32sr".
+    precision: "fp64", "fp32dev", "fp32sr" or "mixed".
     """
 
     def __init__(self, precision, shapes, params, device="cuda", stream=None):

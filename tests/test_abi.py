@@ -101,8 +101,9 @@ def test_buffer_bytes():
 
 
 def test_mixed_precision_sizes_and_unsupported_paths():
-    """LC_MIXED: float populations and double Q (buffer sizes), no staged
-    variant, no reverse step and no batched form, refused on the host."""
+    """LC_MIXED: float populations and double Q (buffer sizes, also in the
+    batched form's arenas), no staged variant and no reverse step, refused
+    on the host."""
     from paper_1907_13415_amd import lc
     fb, qb, sb = lc.lc_buffer_bytes(lc.make_grid(lc.LC_D3Q19, lc.LC_MIXED, 16, 8, 4))
     assert fb == 19 * 512 * 4 and qb == 5 * 512 * 8
@@ -121,8 +122,12 @@ def test_mixed_precision_sizes_and_unsupported_paths():
         assert e.value.code == lc.LC_EUNSUPPORTED
     finally:
         lc.lc_free(ctx)
+    fb, qb, _, fo, qo = lc.lc_batch_layout([lc.make_grid(lc.LC_D2Q9, lc.LC_MIXED, 64, 64, 1),
+                                            lc.make_grid(lc.LC_D2Q9, lc.LC_MIXED, 40, 24, 1)])
+    assert fo[0] == 0 and fo[1] >= 9 * 4096 * 4 and fb >= fo[1] + 9 * 960 * 4
+    assert qo[0] == 0 and qo[1] >= 5 * 4096 * 8 and qb >= qo[1] + 5 * 960 * 8
     with pytest.raises(lc.LCError) as e:
-        lc.lc_batch_layout([lc.make_grid(lc.LC_D2Q9, lc.LC_MIXED, 64, 64, 1)])
+        lc.lc_batch_layout([lc.make_grid(lc.LC_D3Q19, lc.LC_MIXED, 16, 16, 4)])
     assert e.value.code == lc.LC_EUNSUPPORTED
 
 

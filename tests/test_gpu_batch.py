@@ -41,7 +41,7 @@ def _batch_inputs(seed):
     return q5s, params
 
 
-@pytest.mark.parametrize("prec", ["fp32dev", "fp64", "fp32sr"])
+@pytest.mark.parametrize("prec", ["fp32dev", "fp64", "fp32sr", "mixed"])
 def test_batch_equals_single_grid_across_graph_replays(prec):
     """With stochastic rounding too: a graph replay draws the uniform
     numbers of the steps it advances, as the single grid does."""
@@ -187,7 +187,7 @@ def test_sweep_front_speeds_fp32_against_fp64():
         assert n >= 10 and worst < 1e-3  # measured 1.3e-5 (FP32 deviation), 4.3e-6 (stochastic rounding) over 24 moving grids
 
 
-@pytest.mark.parametrize("prec", ["fp32dev", "fp32sr"])
+@pytest.mark.parametrize("prec", ["fp32dev", "fp32sr", "mixed"])
 def test_batch_tile_shapes_agree_bitwise(prec):
     """Every site runs the same code wherever it falls in a tile, so every
     tile shape of either sweep gives identical results (seven pairings that
