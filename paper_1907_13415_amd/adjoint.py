@@ -36,6 +36,8 @@ class LCSolve(torch.autograd.Function):
                 raise TypeError("%s must be a float64 tensor" % name)
         steps = int(cfg["steps"])
         every = int(cfg.get("every", 100))
+        if steps < 0 or every < 1:
+            raise ValueError("steps must be >= 0 and every >= 1 (got %d, %d)" % (steps, every))
         params = (cfg["A0"], float(gamma), float(K), float(Gamma), cfg["xi"], cfg["tau"])
         shape = tuple(q0.shape[1:])
         s = lc.Solver("D2Q9", "fp64", shape, params, device=q0.device)
@@ -67,6 +69,9 @@ class LCSolve(torch.autograd.Function):
         s = ctx.solver
         shape = ctx.shape
         dev = grad_q.device
+        if not ctx.checkpoints:  # zero steps: q_final is q0
+            zero = torch.zeros((), dtype=torch.float64, device=dev)
+            return grad_q.detach().to(torch.float64).clone(), zero, zero.clone(), zero.clone(), None
         s.stream.wait_stream(torch.cuda.current_stream(dev))  # grad_q may still be in flight
         with torch.cuda.stream(s.stream):
             adj_q = grad_q.detach().to(torch.float64).contiguous().clone()

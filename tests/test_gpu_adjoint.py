@@ -269,3 +269,24 @@ def test_checkpointed_gradients_adjoint_workload():
     parameters."""
     require_gpu()
     _fd_check(256, 2000, 100, 16)
+
+
+def test_zero_step_solve_passes_the_gradient_through():
+    """With no steps the final order tensor is the initial one: its gradient
+    passes through unchanged and the parameter gradients are zero; invalid
+    step counts are refused before any device work."""
+    require_gpu()
+    import torch
+    from paper_1907_13415_amd import adjoint
+    rng = np.random.default_rng(90)
+    q0 = torch.tensor(inputs.random_q5((1, 12, 16), rng, amp=0.1), device="cuda", requires_grad=True)
+    tg, tK, tG = (torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in (2.7, 0.04, 0.3))
+    qf = adjoint.solve(q0, tg, tK, tG, A0=1.0, xi=0.7, tau=1.0, steps=0, every=100)
+    assert torch.equal(qf, q0.detach())
+    w = torch.tensor(rng.standard_normal((5, 1, 12, 16)), device="cuda")
+    (qf * w).sum().backward()
+    assert torch.equal(q0.grad, w)
+    assert tg.grad.item() == 0.0 and tK.grad.item() == 0.0 and tG.grad.item() == 0.0
+    for bad in (dict(steps=-1, every=100), dict(steps=10, every=0)):
+        with pytest.raises(ValueError):
+            adjoint.solve(q0, tg, tK, tG, A0=1.0, xi=0.7, tau=1.0, **bad)
