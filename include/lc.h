@@ -249,8 +249,8 @@ lc_status lc_set_stencil(lc_ctx *ctx, int32_t stencil);
 
 /* Planes each block marches through along z in the two-sweep and fused
  * kernels (>= 1; larger chunks recompute fewer boundary planes, smaller
- * chunks give more blocks).  0 restores the built-in default.  Ignored by
- * 2D grids.  A launch-shape setting: implements no passage of the paper and
+ * chunks give more blocks; a chunk longer than nz is the whole depth).  0
+ * restores the built-in default.  Ignored by 2D grids.  A launch-shape setting: implements no passage of the paper and
  * does not change results.  LC_EINVAL for planes < 0. */
 lc_status lc_set_chunk(lc_ctx *ctx, int32_t planes);
 

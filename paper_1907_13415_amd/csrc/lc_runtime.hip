@@ -299,8 +299,10 @@ static void step_split_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   // MRT and the isotropic stencils march 32-plane chunks in the float
   // stress/LB sweep (1% and 3% faster there than 16)
   const bool wide = sizeof(S) == 4 && (c->coll == LC_COLL_MRT || c->stencil == LC_STENCIL_ISOTROPIC);
-  const int zc1 = C::d3 ? (c->zchunk > 0 ? c->zchunk : (wide ? 32 : C::ZC_LB)) : 1;
-  const int zc2 = C::d3 ? (c->zchunk > 0 ? c->zchunk : C::ZC_Q) : 1;
+  // chunks longer than the grid are the whole depth (the block index
+  // arithmetic stays within int)
+  const int zc1 = C::d3 ? std::min(c->zchunk > 0 ? c->zchunk : (wide ? 32 : C::ZC_LB), c->g.nz) : 1;
+  const int zc2 = C::d3 ? std::min(c->zchunk > 0 ? c->zchunk : C::ZC_Q, c->g.nz) : 1;
   const dim3 g1((c->g.nx + C::LB_TX - 1) / C::LB_TX, (c->g.ny + C::LB_TY - 1) / C::LB_TY,
                 unsigned((c->g.nz + zc1 - 1) / zc1));
   const dim3 g2((c->g.nx + C::Q_TX - 1) / C::Q_TX, (c->g.ny + C::Q_TY - 1) / C::Q_TY,
@@ -394,7 +396,7 @@ static void step_fused_ptrs(lc_ctx* c, hipStream_t st, bool mark, const S* f0, c
   using C = FusedCfg<LAT, QT>;
   hipEvent_t e = mark ? ctx_begin(c, st) : nullptr;
   if constexpr (C::d3) {
-    const int zc = c->zchunk > 0 ? c->zchunk : C::ZC;
+    const int zc = std::min(c->zchunk > 0 ? c->zchunk : C::ZC, c->g.nz);
     launch_fused<LAT, S, DEV, QT, C::TX, C::TY, C::NTHR>(c, st, zc, f0, q0, f1, q1);
   } else {
     auto tiles = [&](int tx, int ty) { return int64_t((c->g.nx + tx - 1) / tx) * ((c->g.ny + ty - 1) / ty); };

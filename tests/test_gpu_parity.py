@@ -408,12 +408,12 @@ def test_z_chunk_does_not_change_the_result(prec):
     f = w.reshape((19, 1, 1, 1)) * (1.0 + inputs.random_rel(19, shape, rng, amp=2e-3))
     p = (1.0, 2.72, 0.05, 0.3, 0.7, 1.3)
     out = {}
-    for zc in (0, 1, 5, 23, 64):
+    for zc in (0, 1, 5, 23, 64, 2 ** 31 - 1):
         _announce("z-chunk %d (%s)" % (zc, prec))
         s = lc.Solver("D3Q19", prec, shape, p)
         s.set_chunk(zc)
         s.load(q5, f)
         s.step(6)
         out[zc] = (s.export(lc.LC_FIELD_F), s.export(lc.LC_FIELD_Q))
-    for zc in (1, 5, 23, 64):
+    for zc in (1, 5, 23, 64, 2 ** 31 - 1):
         assert np.array_equal(out[zc][0], out[0][0]) and np.array_equal(out[zc][1], out[0][1]), zc
