@@ -443,6 +443,14 @@ lc_status lc_batch_set_tiles(lc_batch *b, int32_t v_lb, int32_t v_q);
  * passage of the paper and does not change results. */
 lc_status lc_batch_set_tile(lc_batch *b, int32_t variant);
 
+/* Collision operator of every grid of the batch, as lc_set_collision
+ * (Sec. 1.2.1; BGK by default, or MRT with the D2Q9 group rates
+ * (s_e, s_eps, s_q), each grid's density, momentum and stress relaxing at
+ * its own 1/tau).  Applies to the steps enqueued after the call and
+ * synchronises the stream once (descriptor upload).  LC_EINVAL for an
+ * unknown kind, a wrong count or a rate outside (0, 2). */
+lc_status lc_batch_set_collision(lc_batch *b, int32_t kind, const double *rates, int32_t nrates);
+
 /* Time every pair of tile shapes for trial_steps steps (after one untimed
  * step) with HIP events and keep the fastest; *chosen = v_lb + 7 * v_q.
  * The state advances by 49 * (trial_steps + 1) steps: tune before loading

@@ -32,7 +32,9 @@ struct BatchDesc {
   Coef<QT> cq;                  // the same in the order-tensor type
 };
 
-template <int LAT, typename S, bool DEV, int TX, int TY, typename QT = S>
+// MRT: the multiple-relaxation-time collision (rates in the descriptors'
+// constants).
+template <int LAT, typename S, bool DEV, int TX, int TY, typename QT = S, bool MRT = false>
 __global__ void __launch_bounds__(TX* TY)
     batch_lb(const BatchDesc<S, QT>* __restrict__ desc, const int* __restrict__ tile_grid,
              const QT* __restrict__ Qa, const S* __restrict__ fa, S* __restrict__ fb, QT* __restrict__ ua) {
@@ -43,7 +45,7 @@ __global__ void __launch_bounds__(TX* TY)
   const GridDims g{d.nx, d.ny, 1, d.N};
   // many grids stream through the caches together: populations read with
   // nontemporal loads
-  split_lb_body<LAT, S, DEV, TX, TY, false, true, QT>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g,
+  split_lb_body<LAT, S, DEV, TX, TY, MRT, true, QT>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g,
                                                       d.c, d.cq, 1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
 }
 

@@ -1260,6 +1260,8 @@ struct lc_batch {
   std::vector<char> host_desc;
   std::vector<int> host_map[BATCH_NV];
   int vt[2];  // tile shape of each sweep (0: LB, 1: Q)
+  int coll = LC_COLL_BGK;  // LC_COLL_*, for every grid
+  double mrt[5] = {};      // MRT rates of the ghost groups
   int parity;
   int64_t step;
   bool loaded;
@@ -1288,6 +1290,8 @@ static void batch_fill_desc(lc_batch* b) {
     }
     d[k].c = make_coef<S>(b->params[k]);
     d[k].cq = make_coef<QT>(b->params[k]);
+    if (b->coll == LC_COLL_MRT)  // each group's rate minus this grid's 1/tau
+      for (int g = 0; g < 5; g++) d[k].c.mrt[g] = S(b->mrt[g] - 1.0 / b->params[k].tau);
   }
 }
 
@@ -1306,7 +1310,7 @@ static lc_status batch_upload(lc_batch* b) {
                    "batch descriptor upload");
 }
 
-template <typename S, bool DEV, typename QT, int V>
+template <typename S, bool DEV, typename QT, bool MRT, int V>
 static void batch_launch_lb(lc_batch* b, hipStream_t st, int parity) {
   constexpr int TX = batch_tx(V), TY = batch_ty(V);
   char* scr = static_cast<char*>(b->arena.scratch);
@@ -1316,8 +1320,8 @@ static void batch_launch_lb(lc_batch* b, hipStream_t st, int parity) {
   const S* f0 = static_cast<const S*>(b->arena.f[parity]);
   S* f1 = static_cast<S*>(b->arena.f[parity ^ 1]);
   const QT* q0 = static_cast<const QT*>(b->arena.Q[parity]);
-  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY, QT>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc,
-                     map, q0, f0, f1, u);
+  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY, QT, MRT>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st,
+                     desc, map, q0, f0, f1, u);
 }
 
 template <typename S, typename QT, bool SR, int V>
@@ -1334,17 +1338,17 @@ static void batch_launch_q(lc_batch* b, hipStream_t st, int parity, int step_off
                      q0, u, q1, step_base, step_off);
 }
 
-template <typename S, bool DEV, typename QT, bool SR>
+template <typename S, bool DEV, typename QT, bool SR, bool MRT>
 static void batch_launch(lc_batch* b, hipStream_t st, int parity, int step_off) {
   static_assert(BATCH_NV == 7, "one launch branch per tile shape");
   switch (b->vt[0]) {
-    case 0: batch_launch_lb<S, DEV, QT, 0>(b, st, parity); break;
-    case 1: batch_launch_lb<S, DEV, QT, 1>(b, st, parity); break;
-    case 2: batch_launch_lb<S, DEV, QT, 2>(b, st, parity); break;
-    case 3: batch_launch_lb<S, DEV, QT, 3>(b, st, parity); break;
-    case 4: batch_launch_lb<S, DEV, QT, 4>(b, st, parity); break;
-    case 5: batch_launch_lb<S, DEV, QT, 5>(b, st, parity); break;
-    default: batch_launch_lb<S, DEV, QT, 6>(b, st, parity); break;
+    case 0: batch_launch_lb<S, DEV, QT, MRT, 0>(b, st, parity); break;
+    case 1: batch_launch_lb<S, DEV, QT, MRT, 1>(b, st, parity); break;
+    case 2: batch_launch_lb<S, DEV, QT, MRT, 2>(b, st, parity); break;
+    case 3: batch_launch_lb<S, DEV, QT, MRT, 3>(b, st, parity); break;
+    case 4: batch_launch_lb<S, DEV, QT, MRT, 4>(b, st, parity); break;
+    case 5: batch_launch_lb<S, DEV, QT, MRT, 5>(b, st, parity); break;
+    default: batch_launch_lb<S, DEV, QT, MRT, 6>(b, st, parity); break;
   }
   switch (b->vt[1]) {
     case 0: batch_launch_q<S, QT, SR, 0>(b, st, parity, step_off); break;
@@ -1359,15 +1363,23 @@ static void batch_launch(lc_batch* b, hipStream_t st, int parity, int step_off) 
 
 // One step of every grid; step_off: the step's offset from the step count
 // last written to the batch's step slot (stochastic rounding only).
-static void batch_launch_step(lc_batch* b, hipStream_t st, int parity, int step_off) {
+template <bool MRT>
+static void batch_launch_step_coll(lc_batch* b, hipStream_t st, int parity, int step_off) {
   if (b->grids[0].precision == LC_FP64)
-    batch_launch<double, false, double, false>(b, st, parity, step_off);
+    batch_launch<double, false, double, false, MRT>(b, st, parity, step_off);
   else if (b->grids[0].precision == LC_MIXED)
-    batch_launch<float, true, double, false>(b, st, parity, step_off);
+    batch_launch<float, true, double, false, MRT>(b, st, parity, step_off);
   else if (b->grids[0].precision == LC_FP32_SR)
-    batch_launch<float, true, float, true>(b, st, parity, step_off);
+    batch_launch<float, true, float, true, MRT>(b, st, parity, step_off);
   else
-    batch_launch<float, true, float, false>(b, st, parity, step_off);
+    batch_launch<float, true, float, false, MRT>(b, st, parity, step_off);
+}
+
+static void batch_launch_step(lc_batch* b, hipStream_t st, int parity, int step_off) {
+  if (b->coll == LC_COLL_MRT)
+    batch_launch_step_coll<true>(b, st, parity, step_off);
+  else
+    batch_launch_step_coll<false>(b, st, parity, step_off);
 }
 
 // Write the step count of the next run of launches to the batch's step slot
@@ -1599,6 +1611,30 @@ lc_status lc_batch_set_tiles(lc_batch* b, int32_t v_lb, int32_t v_q) {
 }
 
 lc_status lc_batch_set_tile(lc_batch* b, int32_t variant) { return lc_batch_set_tiles(b, variant, variant); }
+
+lc_status lc_batch_set_collision(lc_batch* b, int32_t kind, const double* rates, int32_t nrates) {
+  clear_error();
+  if (!b) return fail(LC_EINVAL, "batch is NULL");
+  double r[5] = {0, 0, 0, 0, 0};
+  if (kind == LC_COLL_MRT) {
+    const int ng = Ghosts<0>::ngroups;
+    if (!rates) return fail(LC_EINVAL, "rates is NULL");
+    if (nrates != ng) return fail(LC_EINVAL, "D2Q9 takes %d MRT rates (got %d)", ng, nrates);
+    for (int g = 0; g < ng; g++) {
+      if (!(rates[g] > 0.0 && rates[g] < 2.0)) return fail(LC_EINVAL, "MRT rate %d = %g outside (0, 2)", g, rates[g]);
+      r[g] = rates[g];
+    }
+  } else if (kind != LC_COLL_BGK) {
+    return fail(LC_EINVAL, "unknown collision %d", kind);
+  }
+  b->coll = kind;
+  for (int g = 0; g < 5; g++) b->mrt[g] = r[g];
+  // the descriptors carry the rates, and captured graphs the kernels
+  batch_drop_graphs(b);
+  lc_status st = batch_upload(b);
+  if (st) return st;
+  return hip_check(hipStreamSynchronize(b->stream), "descriptor upload sync");
+}
 
 lc_status lc_batch_autotune(lc_batch* b, int32_t trial_steps, int32_t* chosen, double* ms_per_step) {
   clear_error();

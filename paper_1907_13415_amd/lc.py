@@ -103,6 +103,8 @@ def _load():
         "lc_batch_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
         "lc_batch_set_tile": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
         "lc_batch_set_tiles": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+        "lc_batch_set_collision": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32],
+                                   ctypes.c_int32),
         "lc_batch_autotune": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)],
                               ctypes.c_int32),
         "lc_batch_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
@@ -406,6 +408,12 @@ def lc_batch_set_tiles(b, v_lb, v_q):
     _check(_lib.lc_batch_set_tiles(b, int(v_lb), int(v_q)))
 
 
+def lc_batch_set_collision(b, kind, rates=()):
+    n = len(rates)
+    arr = (ctypes.c_double * max(n, 1))(*[float(r) for r in rates])
+    _check(_lib.lc_batch_set_collision(b, int(kind), arr if n else None, n))
+
+
 def lc_batch_autotune(b, trial_steps):
     ch = ctypes.c_int32()
     ms = ctypes.c_double()
@@ -480,6 +488,9 @@ class BatchSolver:
 
     def set_tiles(self, v_lb, v_q):
         lc_batch_set_tiles(self.b, v_lb, v_q)
+
+    def set_collision(self, kind, rates=()):
+        lc_batch_set_collision(self.b, kind, rates)
 
     def autotune(self, trial_steps=20):
         return lc_batch_autotune(self.b, trial_steps)

@@ -131,6 +131,13 @@ def test_mixed_precision_sizes_and_unsupported_paths():
     assert e.value.code == lc.LC_EUNSUPPORTED
 
 
+def test_batch_collision_needs_a_batch():
+    from paper_1907_13415_amd import lc
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_batch_set_collision(None, lc.LC_COLL_MRT, (1.64, 1.54, 1.9))
+    assert e.value.code == lc.LC_EINVAL
+
+
 def test_batch_layout_of_the_stochastic_rounding_form():
     """The batched form takes LC_FP32_SR with the float form's arenas; all
     grids of a batch share one precision."""

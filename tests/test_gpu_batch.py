@@ -206,3 +206,49 @@ def test_batch_tile_shapes_agree_bitwise(prec):
         for k in range(len(SHAPES)):
             assert np.array_equal(res[0][k][0], res[v][k][0]), (v, k)
             assert np.array_equal(res[0][k][1], res[v][k][1]), (v, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32dev"])
+def test_batch_mrt_equals_single_grid(prec):
+    """The multiple-relaxation-time collision in the batched form: every
+    grid, with its own tau among the group rates, equals the same grid
+    stepped alone with that collision, across graph replays and an eager
+    tail; bad rates are refused and BGK restores the default operator."""
+    lc = _lc()
+    _say("batch MRT vs single %s" % prec)
+    q5s, params = _batch_inputs(7)
+    params = [p[:5] + (1.0 + 0.1 * k,) for k, p in enumerate(params)]  # a tau per grid
+    rates = (1.64, 1.54, 1.9)
+    b = lc.BatchSolver(prec, SHAPES, params)
+    b.set_collision(lc.LC_COLL_MRT, rates)
+    for bad in ((1.64, 1.54), (1.64, 2.0, 1.9), (0.0, 1.54, 1.9)):
+        with pytest.raises(lc.LCError) as e:
+            b.set_collision(lc.LC_COLL_MRT, bad)
+        assert e.value.code == lc.LC_EINVAL
+    with pytest.raises(lc.LCError):
+        b.set_collision(7)
+    b.set_collision(lc.LC_COLL_MRT, rates)  # the refused calls left nothing half set
+    singles = []
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+        s = lc.Solver("D2Q9", prec, (1,) + SHAPES[k], params[k])
+        s.set_collision(lc.LC_COLL_MRT, rates)
+        s.load(q5)
+        singles.append(s)
+    for chunk in (64, 11, 64):
+        b.step(chunk)
+        for s in singles:
+            s.step(chunk)
+        for k, s in enumerate(singles):
+            assert np.array_equal(b.export(k, lc.LC_FIELD_F), s.export(lc.LC_FIELD_F)), (k, chunk)
+            assert np.array_equal(b.export(k, lc.LC_FIELD_Q), s.export(lc.LC_FIELD_Q)), (k, chunk)
+    # back to BGK: equals a batch that never left it
+    b.set_collision(lc.LC_COLL_BGK)
+    ref = lc.BatchSolver(prec, SHAPES, params)
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+        ref.load(k, q5)
+    b.step(70)
+    ref.step(70)
+    for k in range(len(SHAPES)):
+        assert np.array_equal(b.export(k, lc.LC_FIELD_Q), ref.export(k, lc.LC_FIELD_Q)), k
