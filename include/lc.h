@@ -242,8 +242,8 @@ lc_status lc_set_collision(lc_ctx *ctx, int32_t kind, const double *rates, int32
  * isotropic stencils run in the two-sweep and staged variants, and in the
  * single pass on D2Q9 grids (lc_step returns LC_EUNSUPPORTED for
  * LC_VARIANT_FUSED on D3Q19), in LC_FP64 and LC_FP32_DEV (LC_EUNSUPPORTED
- * otherwise), with either collision; the reverse step and the batched form
- * use the compact stencils only.
+ * otherwise), with either collision; the batched form takes them through
+ * lc_batch_set_stencil, and the reverse step uses the compact stencils only.
  * LC_EINVAL for an unknown stencil. */
 lc_status lc_set_stencil(lc_ctx *ctx, int32_t stencil);
 
@@ -442,6 +442,13 @@ lc_status lc_batch_set_tiles(lc_batch *b, int32_t v_lb, int32_t v_q);
 /* lc_batch_set_tiles(b, variant, variant).  A launch shape: implements no
  * passage of the paper and does not change results. */
 lc_status lc_batch_set_tile(lc_batch *b, int32_t variant);
+
+/* Difference stencils of every grid of the batch, as lc_set_stencil (the
+ * compact ones of Sec. 1.2.2, or the isotropic ones of the closing remarks
+ * of Sec. 2.2 in LC_FP64 and LC_FP32_DEV, LC_EUNSUPPORTED otherwise); for
+ * the steps, exports and observables after the call.  LC_EINVAL for an
+ * unknown stencil. */
+lc_status lc_batch_set_stencil(lc_batch *b, int32_t stencil);
 
 /* Collision operator of every grid of the batch, as lc_set_collision
  * (Sec. 1.2.1; BGK by default, or MRT with the D2Q9 group rates

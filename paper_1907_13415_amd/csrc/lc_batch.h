@@ -33,8 +33,9 @@ struct BatchDesc {
 };
 
 // MRT: the multiple-relaxation-time collision (rates in the descriptors'
-// constants).
-template <int LAT, typename S, bool DEV, int TX, int TY, typename QT = S, bool MRT = false>
+// constants); ST: the difference stencils (STENCIL_*).
+template <int LAT, typename S, bool DEV, int TX, int TY, typename QT = S, bool MRT = false,
+          int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(TX* TY)
     batch_lb(const BatchDesc<S, QT>* __restrict__ desc, const int* __restrict__ tile_grid,
              const QT* __restrict__ Qa, const S* __restrict__ fa, S* __restrict__ fb, QT* __restrict__ ua) {
@@ -45,7 +46,7 @@ __global__ void __launch_bounds__(TX* TY)
   const GridDims g{d.nx, d.ny, 1, d.N};
   // many grids stream through the caches together: populations read with
   // nontemporal loads
-  split_lb_body<LAT, S, DEV, TX, TY, MRT, true, QT>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g,
+  split_lb_body<LAT, S, DEV, TX, TY, MRT, true, QT, ST>(Qa + d.q_off, fa + d.f_off, fb + d.f_off, ua + d.u_off, g,
                                                       d.c, d.cq, 1, t % d.tiles_x[0], t / d.tiles_x[0], 0);
 }
 
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(TX* TY)
 // of the steps they advance.
 // The Q sweep runs in the order-tensor type QT; S is the population type
 // of the descriptors.
-template <int LAT, typename S, typename QT, int TX, int TY, bool SR = false>
+template <int LAT, typename S, typename QT, int TX, int TY, bool SR = false, int ST = STENCIL_COMPACT>
 __global__ void __launch_bounds__(TX* TY)
     batch_q(const BatchDesc<S, QT>* __restrict__ desc, const int* __restrict__ tile_grid,
             const QT* __restrict__ Qa, const QT* __restrict__ ua, QT* __restrict__ Qb,
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(TX* TY)
   const int t = b - d.tile0[1];
   const GridDims g{d.nx, d.ny, 1, d.N};
   const uint32_t key = SR ? step_key(int64_t(*step_base) + step_off) : 0u;
-  split_q_body<LAT, QT, TX, TY, SR>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.cq, 1, t % d.tiles_x[1],
+  split_q_body<LAT, QT, TX, TY, SR, ST>(Qa + d.q_off, ua + d.u_off, Qb + d.q_off, g, d.cq, 1, t % d.tiles_x[1],
                                     t / d.tiles_x[1], 0, nullptr, key);
 }
 

@@ -1262,6 +1262,7 @@ struct lc_batch {
   int vt[2];  // tile shape of each sweep (0: LB, 1: Q)
   int coll = LC_COLL_BGK;  // LC_COLL_*, for every grid
   double mrt[5] = {};      // MRT rates of the ghost groups
+  int stencil = LC_STENCIL_COMPACT;  // LC_STENCIL_*, for every grid
   int parity;
   int64_t step;
   bool loaded;
@@ -1310,7 +1311,7 @@ static lc_status batch_upload(lc_batch* b) {
                    "batch descriptor upload");
 }
 
-template <typename S, bool DEV, typename QT, bool MRT, int V>
+template <typename S, bool DEV, typename QT, bool MRT, int ST, int V>
 static void batch_launch_lb(lc_batch* b, hipStream_t st, int parity) {
   constexpr int TX = batch_tx(V), TY = batch_ty(V);
   char* scr = static_cast<char*>(b->arena.scratch);
@@ -1320,11 +1321,11 @@ static void batch_launch_lb(lc_batch* b, hipStream_t st, int parity) {
   const S* f0 = static_cast<const S*>(b->arena.f[parity]);
   S* f1 = static_cast<S*>(b->arena.f[parity ^ 1]);
   const QT* q0 = static_cast<const QT*>(b->arena.Q[parity]);
-  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY, QT, MRT>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st,
-                     desc, map, q0, f0, f1, u);
+  hipLaunchKernelGGL((batch_lb<0, S, DEV, TX, TY, QT, MRT, ST>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0,
+                     st, desc, map, q0, f0, f1, u);
 }
 
-template <typename S, typename QT, bool SR, int V>
+template <typename S, typename QT, bool SR, int ST, int V>
 static void batch_launch_q(lc_batch* b, hipStream_t st, int parity, int step_off) {
   constexpr int TX = batch_tx(V), TY = batch_ty(V);
   char* scr = static_cast<char*>(b->arena.scratch);
@@ -1334,30 +1335,30 @@ static void batch_launch_q(lc_batch* b, hipStream_t st, int parity, int step_off
   const uint32_t* step_base = reinterpret_cast<const uint32_t*>(scr + b->B.off_step);
   const QT* q0 = static_cast<const QT*>(b->arena.Q[parity]);
   QT* q1 = static_cast<QT*>(b->arena.Q[parity ^ 1]);
-  hipLaunchKernelGGL((batch_q<0, S, QT, TX, TY, SR>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc, map,
-                     q0, u, q1, step_base, step_off);
+  hipLaunchKernelGGL((batch_q<0, S, QT, TX, TY, SR, ST>), dim3(unsigned(b->B.tiles[V])), dim3(TX, TY), 0, st, desc,
+                     map, q0, u, q1, step_base, step_off);
 }
 
-template <typename S, bool DEV, typename QT, bool SR, bool MRT>
+template <typename S, bool DEV, typename QT, bool SR, bool MRT, int ST>
 static void batch_launch(lc_batch* b, hipStream_t st, int parity, int step_off) {
   static_assert(BATCH_NV == 7, "one launch branch per tile shape");
   switch (b->vt[0]) {
-    case 0: batch_launch_lb<S, DEV, QT, MRT, 0>(b, st, parity); break;
-    case 1: batch_launch_lb<S, DEV, QT, MRT, 1>(b, st, parity); break;
-    case 2: batch_launch_lb<S, DEV, QT, MRT, 2>(b, st, parity); break;
-    case 3: batch_launch_lb<S, DEV, QT, MRT, 3>(b, st, parity); break;
-    case 4: batch_launch_lb<S, DEV, QT, MRT, 4>(b, st, parity); break;
-    case 5: batch_launch_lb<S, DEV, QT, MRT, 5>(b, st, parity); break;
-    default: batch_launch_lb<S, DEV, QT, MRT, 6>(b, st, parity); break;
+    case 0: batch_launch_lb<S, DEV, QT, MRT, ST, 0>(b, st, parity); break;
+    case 1: batch_launch_lb<S, DEV, QT, MRT, ST, 1>(b, st, parity); break;
+    case 2: batch_launch_lb<S, DEV, QT, MRT, ST, 2>(b, st, parity); break;
+    case 3: batch_launch_lb<S, DEV, QT, MRT, ST, 3>(b, st, parity); break;
+    case 4: batch_launch_lb<S, DEV, QT, MRT, ST, 4>(b, st, parity); break;
+    case 5: batch_launch_lb<S, DEV, QT, MRT, ST, 5>(b, st, parity); break;
+    default: batch_launch_lb<S, DEV, QT, MRT, ST, 6>(b, st, parity); break;
   }
   switch (b->vt[1]) {
-    case 0: batch_launch_q<S, QT, SR, 0>(b, st, parity, step_off); break;
-    case 1: batch_launch_q<S, QT, SR, 1>(b, st, parity, step_off); break;
-    case 2: batch_launch_q<S, QT, SR, 2>(b, st, parity, step_off); break;
-    case 3: batch_launch_q<S, QT, SR, 3>(b, st, parity, step_off); break;
-    case 4: batch_launch_q<S, QT, SR, 4>(b, st, parity, step_off); break;
-    case 5: batch_launch_q<S, QT, SR, 5>(b, st, parity, step_off); break;
-    default: batch_launch_q<S, QT, SR, 6>(b, st, parity, step_off); break;
+    case 0: batch_launch_q<S, QT, SR, ST, 0>(b, st, parity, step_off); break;
+    case 1: batch_launch_q<S, QT, SR, ST, 1>(b, st, parity, step_off); break;
+    case 2: batch_launch_q<S, QT, SR, ST, 2>(b, st, parity, step_off); break;
+    case 3: batch_launch_q<S, QT, SR, ST, 3>(b, st, parity, step_off); break;
+    case 4: batch_launch_q<S, QT, SR, ST, 4>(b, st, parity, step_off); break;
+    case 5: batch_launch_q<S, QT, SR, ST, 5>(b, st, parity, step_off); break;
+    default: batch_launch_q<S, QT, SR, ST, 6>(b, st, parity, step_off); break;
   }
 }
 
@@ -1365,14 +1366,23 @@ static void batch_launch(lc_batch* b, hipStream_t st, int parity, int step_off) 
 // last written to the batch's step slot (stochastic rounding only).
 template <bool MRT>
 static void batch_launch_step_coll(lc_batch* b, hipStream_t st, int parity, int step_off) {
-  if (b->grids[0].precision == LC_FP64)
-    batch_launch<double, false, double, false, MRT>(b, st, parity, step_off);
-  else if (b->grids[0].precision == LC_MIXED)
-    batch_launch<float, true, double, false, MRT>(b, st, parity, step_off);
-  else if (b->grids[0].precision == LC_FP32_SR)
-    batch_launch<float, true, float, true, MRT>(b, st, parity, step_off);
-  else
-    batch_launch<float, true, float, false, MRT>(b, st, parity, step_off);
+  // the isotropic stencils: LC_FP64 and LC_FP32_DEV (lc_batch_set_stencil)
+  const bool iso = b->stencil == LC_STENCIL_ISOTROPIC;
+  if (b->grids[0].precision == LC_FP64) {
+    if (iso)
+      batch_launch<double, false, double, false, MRT, STENCIL_ISO>(b, st, parity, step_off);
+    else
+      batch_launch<double, false, double, false, MRT, STENCIL_COMPACT>(b, st, parity, step_off);
+  } else if (b->grids[0].precision == LC_MIXED) {
+    batch_launch<float, true, double, false, MRT, STENCIL_COMPACT>(b, st, parity, step_off);
+  } else if (b->grids[0].precision == LC_FP32_SR) {
+    batch_launch<float, true, float, true, MRT, STENCIL_COMPACT>(b, st, parity, step_off);
+  } else {
+    if (iso)
+      batch_launch<float, true, float, false, MRT, STENCIL_ISO>(b, st, parity, step_off);
+    else
+      batch_launch<float, true, float, false, MRT, STENCIL_COMPACT>(b, st, parity, step_off);
+  }
 }
 
 static void batch_launch_step(lc_batch* b, hipStream_t st, int parity, int step_off) {
@@ -1611,6 +1621,20 @@ lc_status lc_batch_set_tiles(lc_batch* b, int32_t v_lb, int32_t v_q) {
 }
 
 lc_status lc_batch_set_tile(lc_batch* b, int32_t variant) { return lc_batch_set_tiles(b, variant, variant); }
+
+lc_status lc_batch_set_stencil(lc_batch* b, int32_t stencil) {
+  clear_error();
+  if (!b) return fail(LC_EINVAL, "batch is NULL");
+  if (stencil != LC_STENCIL_COMPACT && stencil != LC_STENCIL_ISOTROPIC)
+    return fail(LC_EINVAL, "unknown stencil %d", stencil);
+  if (stencil == LC_STENCIL_ISOTROPIC && b->grids[0].precision != LC_FP64 && b->grids[0].precision != LC_FP32_DEV)
+    return fail(LC_EUNSUPPORTED, "the isotropic stencils are provided in LC_FP64 and LC_FP32_DEV");
+  b->stencil = stencil;
+  // exports and observables of the grids differentiate with the same stencils
+  for (auto& v : b->views) v.stencil = stencil;
+  batch_drop_graphs(b);
+  return LC_OK;
+}
 
 lc_status lc_batch_set_collision(lc_batch* b, int32_t kind, const double* rates, int32_t nrates) {
   clear_error();

@@ -105,6 +105,7 @@ def _load():
         "lc_batch_set_tiles": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
         "lc_batch_set_collision": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double), ctypes.c_int32],
                                    ctypes.c_int32),
+        "lc_batch_set_stencil": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
         "lc_batch_autotune": ([ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)],
                               ctypes.c_int32),
         "lc_batch_observe": ([ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, P(lc_observables)], ctypes.c_int32),
@@ -408,6 +409,10 @@ def lc_batch_set_tiles(b, v_lb, v_q):
     _check(_lib.lc_batch_set_tiles(b, int(v_lb), int(v_q)))
 
 
+def lc_batch_set_stencil(b, stencil):
+    _check(_lib.lc_batch_set_stencil(b, int(stencil)))
+
+
 def lc_batch_set_collision(b, kind, rates=()):
     n = len(rates)
     arr = (ctypes.c_double * max(n, 1))(*[float(r) for r in rates])
@@ -491,6 +496,9 @@ class BatchSolver:
 
     def set_collision(self, kind, rates=()):
         lc_batch_set_collision(self.b, kind, rates)
+
+    def set_stencil(self, stencil):
+        lc_batch_set_stencil(self.b, stencil)
 
     def autotune(self, trial_steps=20):
         return lc_batch_autotune(self.b, trial_steps)

@@ -131,10 +131,13 @@ def test_mixed_precision_sizes_and_unsupported_paths():
     assert e.value.code == lc.LC_EUNSUPPORTED
 
 
-def test_batch_collision_needs_a_batch():
+def test_batch_collision_and_stencil_need_a_batch():
     from paper_1907_13415_amd import lc
     with pytest.raises(lc.LCError) as e:
         lc.lc_batch_set_collision(None, lc.LC_COLL_MRT, (1.64, 1.54, 1.9))
+    assert e.value.code == lc.LC_EINVAL
+    with pytest.raises(lc.LCError) as e:
+        lc.lc_batch_set_stencil(None, lc.LC_STENCIL_ISOTROPIC)
     assert e.value.code == lc.LC_EINVAL
 
 

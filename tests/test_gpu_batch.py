@@ -187,17 +187,20 @@ def test_sweep_front_speeds_fp32_against_fp64():
         assert n >= 10 and worst < 1e-3  # measured 1.3e-5 (FP32 deviation), 4.3e-6 (stochastic rounding) over 24 moving grids
 
 
-@pytest.mark.parametrize("prec", ["fp32dev", "fp32sr", "mixed"])
-def test_batch_tile_shapes_agree_bitwise(prec):
+@pytest.mark.parametrize("prec,iso", [("fp32dev", False), ("fp32sr", False), ("mixed", False), ("fp32dev", True),
+                                      ("fp64", True)])
+def test_batch_tile_shapes_agree_bitwise(prec, iso):
     """Every site runs the same code wherever it falls in a tile, so every
     tile shape of either sweep gives identical results (seven pairings that
-    use each shape once in each sweep)."""
+    use each shape once in each sweep), with the isotropic stencils too."""
     lc = _lc()
     q5s, params = _batch_inputs(4)
     res = []
     for v in range(7):
         b = lc.BatchSolver(prec, SHAPES, params)
         b.set_tiles(v, (3 * v + 1) % 7)
+        if iso:
+            b.set_stencil(lc.LC_STENCIL_ISOTROPIC)
         for k, q5 in enumerate(q5s):
             b.load(k, q5)
         b.step(70)
@@ -252,3 +255,40 @@ def test_batch_mrt_equals_single_grid(prec):
     ref.step(70)
     for k in range(len(SHAPES)):
         assert np.array_equal(b.export(k, lc.LC_FIELD_Q), ref.export(k, lc.LC_FIELD_Q)), k
+
+
+@pytest.mark.parametrize("prec,coll", [("fp64", "bgk"), ("fp32dev", "bgk"), ("fp64", "mrt")])
+def test_batch_isotropic_stencils_equal_single_grid(prec, coll):
+    """The isotropic stencils in the batched form: every grid equals the same
+    grid stepped alone with them (states and the force export, which
+    differentiates the stress with the same stencils), across graph replays
+    and an eager tail; the float forms without them are refused."""
+    lc = _lc()
+    _say("batch isotropic vs single %s %s" % (prec, coll))
+    q5s, params = _batch_inputs(8)
+    rates = (1.64, 1.54, 1.9)
+    b = lc.BatchSolver(prec, SHAPES, params)
+    b.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+    if coll == "mrt":
+        b.set_collision(lc.LC_COLL_MRT, rates)
+    singles = []
+    for k, q5 in enumerate(q5s):
+        b.load(k, q5)
+        s = lc.Solver("D2Q9", prec, (1,) + SHAPES[k], params[k])
+        s.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+        if coll == "mrt":
+            s.set_collision(lc.LC_COLL_MRT, rates)
+        s.load(q5)
+        singles.append(s)
+    for chunk in (64, 11):
+        b.step(chunk)
+        for s in singles:
+            s.step(chunk)
+        for k, s in enumerate(singles):
+            for field in (lc.LC_FIELD_F, lc.LC_FIELD_Q, lc.LC_FIELD_FORCE):
+                assert np.array_equal(b.export(k, field), s.export(field)), (k, chunk, field)
+    for other in ("fp32sr", "mixed"):
+        ob = lc.BatchSolver(other, SHAPES[:1], params[:1])
+        with pytest.raises(lc.LCError) as e:
+            ob.set_stencil(lc.LC_STENCIL_ISOTROPIC)
+        assert e.value.code == lc.LC_EUNSUPPORTED
