@@ -30,8 +30,8 @@
  *    force and Q update in double: the float rounding
  *    of the Q right-hand side, which moves slow interfaces in LC_FP32_DEV,
  *    is gone, at 2(q*4 + 5*8) bytes per site update.  LC_MIXED runs the
- *    split variant only (LC_VARIANT_STAGED: LC_EUNSUPPORTED) and single
- *    grids only (the batched form rejects it).
+ *    split and fused variants and the batched form (LC_VARIANT_STAGED:
+ *    LC_EUNSUPPORTED).
  *    LC_FP32_SR stores f and Q as LC_FP32_DEV does and computes as it does,
  *    except in the Q update: the molecular field of Eq. (4) is summed in
  *    double from the float Q and Laplacian (its bulk terms nearly cancel),
@@ -40,7 +40,7 @@
  *    counter-based hash of the site index and the step count), so that
  *    increments below half a unit in the last place are not lost at every
  *    step; results depend on the step count since the last load, and are
- *    reproducible.  Split and fused variants only; single grids only; no
+ *    reproducible.  Split and fused variants and the batched form; no
  *    lc_step_static.
  *    Every load/export entry point speaks double "logical" values (full f)
  *    whatever the storage precision.
